@@ -1,0 +1,844 @@
+/*
+ * orc.c -- plain, slow, FP64 CPU oracle for one explicit TVD-MUSCL ideal-MHD
+ * step with constrained transport.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the product path.  It shares no
+ * source with the GPU library.  Every loop is a plain scalar triple loop over
+ * a padded grid; the only parallelism is an OpenMP split over z-planes.
+ *
+ * Paper: Khoperskov, Vasiliev, Khoperskov, Lubimov, "Numerical code for
+ * multi-component galaxies: from N-body to chemistry and magnetic fields",
+ * section 2.1 (gas dynamics).  Readings used where the paper is silent or
+ * misprinted (each restated where it is implemented):
+ *   R1  time integrator: predictor-corrector reaching t^{n+1/2}: first-order
+ *       half step, then a MUSCL full step from U^n (the paper only names
+ *       fluxes at n+1/2 in Eq. 7).
+ *   R2  Eq. 13-14 are used as printed (K2 on minmod(dw_{i-1},dw_i), K1 on
+ *       minmod(dw_i, b dw_{i-1})); the textbook kappa-scheme is a flag.
+ *   R3  Eq. 10: the derivative correction is (3/4-point) minus (1/4-point);
+ *       the printed order fails the one-dimensional reduction.
+ *   R4  Eq. 10 uses the four faces that touch the edge.
+ *   R5  Eq. 8: the second bracket is E_y (the curl), not E_z.
+ *   R6  Eq. 11 upwinds by the sign of the Riemann mass flux at the face.
+ *   R7  only the two transverse B components are reconstructed; the normal
+ *       one is the face value.
+ *   R8  HLLD: Miyoshi & Kusano wave-speed estimate; star states with a
+ *       vanishing denominator (|den| <= 1e-8 p_T*) keep their transverse
+ *       v and B; HLL flux if S_M is not strictly inside (S_L, S_R).
+ *   R9  CFL: dt = C min_cells min_d dx_d / (|v_d| + c_f,d) at step start.
+ *   R10 source S = (0, -rho grad Phi, -rho v.grad Phi, 0) at cell centres,
+ *       dt/2 S(W^n) in the predictor, dt S(W*) in the corrector.
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NG 2
+#define DEG_EPS 1.0e-8
+
+struct orc_grid {
+  orc_config c;
+  int n[3];
+  int ext[3];
+  long st[3];     /* strides of the padded layout */
+  long np;        /* points per padded array */
+  double d[3];
+  int per[3];
+  double *u[5], *b[3];    /* state at t^n */
+  double *us[5], *bs[3];  /* predictor state at t^{n+1/2} */
+  double *w[8];           /* primitives rho, vx, vy, vz, P, Bcx, Bcy, Bcz */
+  double *ec[3];          /* cell-centred EMF */
+  double *fl[3][8];       /* face fluxes per axis, global components */
+  signed char *sg[3];     /* sign of the mass flux per face */
+  double *e[3];           /* edge EMFs */
+  double t;
+  int64_t step;
+  int64_t n_floor, n_hll, n_deg;
+};
+
+static long at(const orc_grid *g, int i, int j, int k) {
+  return (long)(i + NG) + g->st[1] * (long)(j + NG) + g->st[2] * (long)(k + NG);
+}
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-face physics in the face-normal frame (n, t1, t2).               */
+/* A frame state is w = rho, vn, vt1, vt2, P, Bt1, Bt2 plus the normal Bn. */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. 3 conserved vector: E = P/(gamma-1) + rho v^2/2 + B^2/2. */
+void orc_prim_to_cons(const double w[7], double bn, double gam, double u[7]) {
+  double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+  double b2 = bn * bn + w[5] * w[5] + w[6] * w[6];
+  u[0] = w[0];
+  u[1] = w[0] * w[1];
+  u[2] = w[0] * w[2];
+  u[3] = w[0] * w[3];
+  u[4] = w[4] / (gam - 1.0) + 0.5 * w[0] * v2 + 0.5 * b2;
+  u[5] = w[5];
+  u[6] = w[6];
+}
+
+/* Eq. 3 physical flux F along the normal, P* = P + B^2/2. */
+void orc_phys_flux(const double w[7], double bn, double gam, double f[7]) {
+  double u[7];
+  orc_prim_to_cons(w, bn, gam, u);
+  double b2 = bn * bn + w[5] * w[5] + w[6] * w[6];
+  double pt = w[4] + 0.5 * b2;
+  double vb = w[1] * bn + w[2] * w[5] + w[3] * w[6];
+  f[0] = w[0] * w[1];
+  f[1] = w[0] * w[1] * w[1] + pt - bn * bn;
+  f[2] = w[0] * w[1] * w[2] - bn * w[5];
+  f[3] = w[0] * w[1] * w[3] - bn * w[6];
+  f[4] = (u[4] + pt) * w[1] - vb * bn;
+  f[5] = w[5] * w[1] - bn * w[2];
+  f[6] = w[6] * w[1] - bn * w[3];
+}
+
+/* Fast magnetosonic speed along the normal.  The textbook discriminant
+   (a^2+b^2)^2 - 4 a^2 bn^2 is rewritten as (a^2-b^2)^2 + 4 a^2 bt^2, a sum of
+   non-negative terms. */
+double orc_fast_speed(const double w[7], double bn, double gam) {
+  double a2 = gam * w[4] / w[0];
+  double bt2 = (w[5] * w[5] + w[6] * w[6]) / w[0];
+  double b2 = (bn * bn + w[5] * w[5] + w[6] * w[6]) / w[0];
+  double dd = a2 - b2;
+  double cf2 = 0.5 * ((a2 + b2) + sqrt(dd * dd + 4.0 * a2 * bt2));
+  return sqrt(cf2);
+}
+
+/* One side of the HLLD star region (Miyoshi & Kusano 2005, section 3).
+   S is the outer wave speed of this side, SM the contact speed, pts the star
+   total pressure.  Outputs the star conserved vector and v*.B*. */
+static int hlld_star(const double w[7], const double u[7], double bn,
+                     double S, double SM, double pts, double us[7],
+                     double *vbs, double *dens) {
+  double rho = w[0], vn = w[1], vt1 = w[2], vt2 = w[3];
+  double bt1 = w[5], bt2 = w[6];
+  double pt = w[4] + 0.5 * (bn * bn + bt1 * bt1 + bt2 * bt2);
+  double ds = rho * (S - vn) / (S - SM);
+  double den = rho * (S - vn) * (S - SM) - bn * bn;
+  double vs1, vs2, bs1, bs2;
+  int degenerate = 0;
+  if (fabs(den) > DEG_EPS * pts) {
+    vs1 = vt1 - bn * bt1 * (SM - vn) / den;
+    vs2 = vt2 - bn * bt2 * (SM - vn) / den;
+    bs1 = bt1 * (rho * (S - vn) * (S - vn) - bn * bn) / den;
+    bs2 = bt2 * (rho * (S - vn) * (S - vn) - bn * bn) / den;
+  } else {
+    /* S*_alpha -> S_alpha: the transverse field and velocity do not jump. */
+    vs1 = vt1;
+    vs2 = vt2;
+    bs1 = bt1;
+    bs2 = bt2;
+    degenerate = 1;
+  }
+  double vb = vn * bn + vt1 * bt1 + vt2 * bt2;
+  double vbstar = SM * bn + vs1 * bs1 + vs2 * bs2;
+  double es = ((S - vn) * u[4] - pt * vn + pts * SM + bn * (vb - vbstar)) / (S - SM);
+  us[0] = ds;
+  us[1] = ds * SM;
+  us[2] = ds * vs1;
+  us[3] = ds * vs2;
+  us[4] = es;
+  us[5] = bs1;
+  us[6] = bs2;
+  *vbs = vbstar;
+  *dens = ds;
+  return degenerate;
+}
+
+int orc_hlld(const double wl[7], const double wr[7], double bn, double gam,
+             double flux[7]) {
+  double ul[7], ur[7], fl[7], fr[7];
+  orc_prim_to_cons(wl, bn, gam, ul);
+  orc_prim_to_cons(wr, bn, gam, ur);
+  orc_phys_flux(wl, bn, gam, fl);
+  orc_phys_flux(wr, bn, gam, fr);
+
+  /* Outer wave speeds: min/max of the normal velocities -/+ the larger fast
+     speed. */
+  double cfl = orc_fast_speed(wl, bn, gam);
+  double cfr = orc_fast_speed(wr, bn, gam);
+  double cmax = cfl > cfr ? cfl : cfr;
+  double SL = (wl[1] < wr[1] ? wl[1] : wr[1]) - cmax;
+  double SR = (wl[1] > wr[1] ? wl[1] : wr[1]) + cmax;
+  int m;
+  if (SL > 0.0) {
+    for (m = 0; m < 7; ++m) flux[m] = fl[m];
+    return 0;
+  }
+  if (SR < 0.0) {
+    for (m = 0; m < 7; ++m) flux[m] = fr[m];
+    return 0;
+  }
+
+  /* Contact speed and star total pressure. */
+  double ptl = wl[4] + 0.5 * (bn * bn + wl[5] * wl[5] + wl[6] * wl[6]);
+  double ptr = wr[4] + 0.5 * (bn * bn + wr[5] * wr[5] + wr[6] * wr[6]);
+  double al = wl[0] * (SL - wl[1]);
+  double ar = wr[0] * (SR - wr[1]);
+  double SM = (ar * wr[1] - al * wl[1] - ptr + ptl) / (ar - al);
+  double pts = (ar * ptl - al * ptr + al * ar * (wr[1] - wl[1])) / (ar - al);
+
+  if (!(SL < SM && SM < SR)) {
+    /* HLL flux: two-wave average between SL and SR. */
+    for (m = 0; m < 7; ++m)
+      flux[m] = (SR * fl[m] - SL * fr[m] + SL * SR * (ur[m] - ul[m])) / (SR - SL);
+    return 1;
+  }
+
+  double usl[7], usr[7], vbsl, vbsr, dsl, dsr;
+  int deg = hlld_star(wl, ul, bn, SL, SM, pts, usl, &vbsl, &dsl);
+  deg |= hlld_star(wr, ur, bn, SR, SM, pts, usr, &vbsr, &dsr);
+
+  /* Double-star states across the rotational discontinuities. */
+  double sl = sqrt(dsl), sr = sqrt(dsr);
+  double SsL = SM - fabs(bn) / sl;
+  double SsR = SM + fabs(bn) / sr;
+  double sgn = bn > 0.0 ? 1.0 : (bn < 0.0 ? -1.0 : 0.0);
+  double vl1 = usl[2] / dsl, vl2 = usl[3] / dsl;
+  double vr1 = usr[2] / dsr, vr2 = usr[3] / dsr;
+  double vss1 = (sl * vl1 + sr * vr1 + sgn * (usr[5] - usl[5])) / (sl + sr);
+  double vss2 = (sl * vl2 + sr * vr2 + sgn * (usr[6] - usl[6])) / (sl + sr);
+  double bss1 = (sr * usl[5] + sl * usr[5] + sgn * sl * sr * (vr1 - vl1)) / (sl + sr);
+  double bss2 = (sr * usl[6] + sl * usr[6] + sgn * sl * sr * (vr2 - vl2)) / (sl + sr);
+  double vbss = SM * bn + vss1 * bss1 + vss2 * bss2;
+
+  double fs[7];
+  if (SsL >= 0.0) {
+    /* F*_L = F_L + S_L (U*_L - U_L) */
+    for (m = 0; m < 7; ++m) flux[m] = fl[m] + SL * (usl[m] - ul[m]);
+  } else if (SM >= 0.0) {
+    /* F**_L = F*_L + S*_L (U**_L - U*_L) */
+    double uss[7] = {dsl, dsl * SM, dsl * vss1, dsl * vss2,
+                     usl[4] - sl * sgn * (vbsl - vbss), bss1, bss2};
+    for (m = 0; m < 7; ++m) fs[m] = fl[m] + SL * (usl[m] - ul[m]);
+    for (m = 0; m < 7; ++m) flux[m] = fs[m] + SsL * (uss[m] - usl[m]);
+  } else if (SsR >= 0.0) {
+    double uss[7] = {dsr, dsr * SM, dsr * vss1, dsr * vss2,
+                     usr[4] + sr * sgn * (vbsr - vbss), bss1, bss2};
+    for (m = 0; m < 7; ++m) fs[m] = fr[m] + SR * (usr[m] - ur[m]);
+    for (m = 0; m < 7; ++m) flux[m] = fs[m] + SsR * (uss[m] - usr[m]);
+  } else {
+    for (m = 0; m < 7; ++m) flux[m] = fr[m] + SR * (usr[m] - ur[m]);
+  }
+  return deg ? 2 : 0;
+}
+
+/* minmod limiter: the argument of smaller magnitude when both have the same
+   strict sign, else 0.  The sign test is by comparison, never by a*b. */
+double orc_minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return a <= b ? a : b;
+  if (a < 0.0 && b < 0.0) return a >= b ? a : b;
+  return 0.0;
+}
+
+/* Eq. 12-14.  The paper's form is dW_i = K2 mm(dw_{i-1}, dw_i)
+   + K1 mm(dw_i, b dw_{i-1}); the textbook kappa-scheme is
+   dW_i = K1 mm(dw_{i-1}, b dw_i) + K2 mm(dw_i, b dw_{i-1}).  Both are
+   cA mm(dw_{i-1}, bA dw_i) + cB mm(dw_i, bB dw_{i-1}). */
+static void recon_coef(int recon, double kappa, double *cA, double *bA,
+                       double *cB, double *bB) {
+  double K1 = (1.0 - kappa) / 4.0;
+  double K2 = (1.0 + kappa) / 4.0;
+  double b = (3.0 - kappa) / (1.0 - kappa);
+  if (recon == ORC_RECON_KAPPA) {
+    *cA = K1; *bA = b; *cB = K2; *bB = b;
+  } else {
+    *cA = K2; *bA = 1.0; *cB = K1; *bB = b;
+  }
+}
+
+void orc_recon(const double w[4], int recon, double kappa, double *wl,
+               double *wr) {
+  if (recon == ORC_RECON_FIRST) {
+    *wl = w[1];
+    *wr = w[2];
+    return;
+  }
+  double cA, bA, cB, bB;
+  recon_coef(recon, kappa, &cA, &bA, &cB, &bB);
+  double dm = w[1] - w[0]; /* dw_{i-1} */
+  double d0 = w[2] - w[1]; /* dw_i     */
+  double dp = w[3] - w[2]; /* dw_{i+1} */
+  double dWi = cA * orc_minmod(dm, bA * d0) + cB * orc_minmod(d0, bB * dm);
+  double dWi1 = cA * orc_minmod(dp, bA * d0) + cB * orc_minmod(d0, bB * dp);
+  *wl = w[1] + dWi;
+  *wr = w[2] - dWi1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid set-up                                                              */
+/* ------------------------------------------------------------------------ */
+
+static double *alloc_arr(long n) { return (double *)calloc((size_t)n, sizeof(double)); }
+
+orc_grid *orc_create(const orc_config *cfg) {
+  orc_grid *g = (orc_grid *)calloc(1, sizeof(orc_grid));
+  int a, m;
+  if (!g) return NULL;
+  g->c = *cfg;
+  g->n[0] = cfg->nx; g->n[1] = cfg->ny; g->n[2] = cfg->nz;
+  g->d[0] = cfg->dx; g->d[1] = cfg->dy; g->d[2] = cfg->dz;
+  for (a = 0; a < 3; ++a) {
+    if (g->n[a] < 1) { free(g); return NULL; }
+    g->ext[a] = g->n[a] + 2 * NG + 1;
+    g->per[a] = cfg->bc[2 * a] == ORC_BC_PERIODIC;
+    if ((cfg->bc[2 * a] == ORC_BC_PERIODIC) != (cfg->bc[2 * a + 1] == ORC_BC_PERIODIC)) {
+      free(g);
+      return NULL;
+    }
+  }
+  g->st[0] = 1;
+  g->st[1] = g->ext[0];
+  g->st[2] = (long)g->ext[0] * g->ext[1];
+  g->np = g->st[2] * g->ext[2];
+  for (m = 0; m < 5; ++m) { g->u[m] = alloc_arr(g->np); g->us[m] = alloc_arr(g->np); }
+  for (a = 0; a < 3; ++a) {
+    g->b[a] = alloc_arr(g->np); g->bs[a] = alloc_arr(g->np);
+    g->ec[a] = alloc_arr(g->np); g->e[a] = alloc_arr(g->np);
+    g->sg[a] = (signed char *)calloc((size_t)g->np, 1);
+    for (m = 0; m < 8; ++m) g->fl[a][m] = alloc_arr(g->np);
+  }
+  for (m = 0; m < 8; ++m) g->w[m] = alloc_arr(g->np);
+  return g;
+}
+
+void orc_destroy(orc_grid *g) {
+  int a, m;
+  if (!g) return;
+  for (m = 0; m < 5; ++m) { free(g->u[m]); free(g->us[m]); }
+  for (a = 0; a < 3; ++a) {
+    free(g->b[a]); free(g->bs[a]); free(g->ec[a]); free(g->e[a]); free(g->sg[a]);
+    for (m = 0; m < 8; ++m) free(g->fl[a][m]);
+  }
+  for (m = 0; m < 8; ++m) free(g->w[m]);
+  free(g);
+}
+
+long orc_padded_size(const orc_grid *g) { return g->np; }
+
+void orc_set_time(orc_grid *g, double t, int64_t step) { g->t = t; g->step = step; }
+
+/* Number of faces along axis a of the face array normal to a. */
+static int nface(const orc_grid *g, int a) { return g->n[a] + (g->per[a] ? 0 : 1); }
+
+/* ------------------------------------------------------------------------ */
+/* O1: ghost fill, ng = 2, x then y then z over the full padded ranges.     */
+/* ------------------------------------------------------------------------ */
+
+/* Source coordinate of a ghost coordinate c along axis a, or -1000 for an
+   inflow ghost.  interior = number of interior entries along a. */
+static int ghost_src(const orc_grid *g, int a, int c, int interior) {
+  int side = c < 0 ? 0 : 1;
+  int bc = g->c.bc[2 * a + side];
+  if (bc == ORC_BC_PERIODIC) {
+    int n = g->n[a];
+    return ((c % n) + n) % n;
+  }
+  if (bc == ORC_BC_OUTFLOW) return c < 0 ? 0 : interior - 1;
+  return -1000;
+}
+
+/* Inflow value of field m (0..4 cell conserved, 5..7 face B). */
+static double inflow_value(const orc_grid *g, int m) {
+  const double *q = g->c.inflow;
+  double gam = g->c.gamma;
+  switch (m) {
+    case 0: return q[0];
+    case 1: return q[0] * q[1];
+    case 2: return q[0] * q[2];
+    case 3: return q[0] * q[3];
+    case 4:
+      return q[4] / (gam - 1.0) + 0.5 * q[0] * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) +
+             0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
+    default: return q[m];
+  }
+}
+
+/* normal = axis along which this array is face-centred, or -1 for cells. */
+static void fill_ghosts_one(orc_grid *g, double *arr, int normal, int m) {
+  int a;
+  double vin = inflow_value(g, m);
+  for (a = 0; a < 3; ++a) {
+    int interior = (a == normal) ? nface(g, a) : g->n[a];
+    int ax1 = (a + 1) % 3, ax2 = (a + 2) % 3;
+    int c1, c2, c;
+    for (c2 = -NG; c2 <= g->n[ax2] + NG; ++c2)
+      for (c1 = -NG; c1 <= g->n[ax1] + NG; ++c1)
+        for (c = -NG; c <= g->n[a] + NG; ++c) {
+          if (c >= 0 && c < interior) continue;
+          int src = ghost_src(g, a, c, interior);
+          int dst[3], s[3];
+          dst[a] = c; dst[ax1] = c1; dst[ax2] = c2;
+          long pd = at(g, dst[0], dst[1], dst[2]);
+          if (src == -1000) {
+            arr[pd] = vin;
+          } else {
+            s[a] = src; s[ax1] = c1; s[ax2] = c2;
+            arr[pd] = arr[at(g, s[0], s[1], s[2])];
+          }
+        }
+  }
+}
+
+static void fill_ghosts(orc_grid *g, double *const u[5], double *const b[3]) {
+  int m;
+  for (m = 0; m < 5; ++m) fill_ghosts_one(g, u[m], -1, m);
+  for (m = 0; m < 3; ++m) fill_ghosts_one(g, b[m], m, 5 + m);
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2: primitives and cell EMF (Eq. 6, Eq. 9).                              */
+/* ------------------------------------------------------------------------ */
+
+/* Primitives of one cell: rho, vx, vy, vz, P, Bcx, Bcy, Bcz. */
+static void cell_prim(const orc_grid *g, double *const u[5], double *const b[3],
+                      long p, double w[8]) {
+  double gam = g->c.gamma;
+  double rho = u[0][p];
+  double bcx = 0.5 * (b[0][p] + b[0][p + g->st[0]]);
+  double bcy = 0.5 * (b[1][p] + b[1][p + g->st[1]]);
+  double bcz = 0.5 * (b[2][p] + b[2][p + g->st[2]]);
+  double ke = 0.5 * (u[1][p] * u[1][p] + u[2][p] * u[2][p] + u[3][p] * u[3][p]) / rho;
+  double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
+  w[0] = rho;
+  w[1] = u[1][p] / rho;
+  w[2] = u[2][p] / rho;
+  w[3] = u[3][p] / rho;
+  w[4] = (gam - 1.0) * (u[4][p] - ke - me);
+  w[5] = bcx;
+  w[6] = bcy;
+  w[7] = bcz;
+}
+
+static void primitives(orc_grid *g, double *const u[5], double *const b[3]) {
+  int k;
+#pragma omp parallel for schedule(static)
+  for (k = -NG; k <= g->n[2] + NG - 1; ++k) {
+    int i, j, m;
+    for (j = -NG; j <= g->n[1] + NG - 1; ++j)
+      for (i = -NG; i <= g->n[0] + NG - 1; ++i) {
+        long p = at(g, i, j, k);
+        double w[8];
+        cell_prim(g, u, b, p, w);
+        for (m = 0; m < 8; ++m) g->w[m][p] = w[m];
+        /* E = -v x B */
+        g->ec[0][p] = w[3] * w[6] - w[2] * w[7];
+        g->ec[1][p] = w[1] * w[7] - w[3] * w[5];
+        g->ec[2][p] = w[2] * w[5] - w[1] * w[6];
+      }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O4 / O9: flux sweep along axis a.                                        */
+/* ------------------------------------------------------------------------ */
+
+static void sweep(orc_grid *g, int a, double *const bf[3], int recon) {
+  int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+  long s = g->st[a];
+  /* frame variable -> primitive array: rho, vn, vt1, vt2, P, Bt1, Bt2 */
+  double *src[7] = {g->w[0], g->w[1 + a], g->w[1 + t1], g->w[1 + t2], g->w[4],
+                    g->w[5 + t1], g->w[5 + t2]};
+  int lo[3], hi[3], k;
+  int64_t nhll = 0, ndeg = 0;
+  /* normal: faces 0..n; transverse: rows -1..n, which the corner EMFs of
+     the boundary edges need */
+  for (k = 0; k < 3; ++k) { lo[k] = -1; hi[k] = g->n[k]; }
+  lo[a] = 0; hi[a] = g->n[a];
+#pragma omp parallel for schedule(static) reduction(+ : nhll, ndeg)
+  for (k = lo[2]; k <= hi[2]; ++k) {
+    int i, j, v;
+    for (j = lo[1]; j <= hi[1]; ++j)
+      for (i = lo[0]; i <= hi[0]; ++i) {
+        long p = at(g, i, j, k); /* face between cells p - s and p */
+        double wl[7], wr[7], f[7];
+        for (v = 0; v < 7; ++v) {
+          double st4[4] = {src[v][p - 2 * s], src[v][p - s], src[v][p], src[v][p + s]};
+          orc_recon(st4, recon, g->c.kappa, &wl[v], &wr[v]);
+        }
+        int code = orc_hlld(wl, wr, bf[a][p], g->c.gamma, f);
+        if (code & 1) nhll++;
+        if (code & 2) ndeg++;
+        g->fl[a][0][p] = f[0];
+        g->fl[a][1 + a][p] = f[1];
+        g->fl[a][1 + t1][p] = f[2];
+        g->fl[a][1 + t2][p] = f[3];
+        g->fl[a][4][p] = f[4];
+        g->fl[a][5 + a][p] = 0.0;
+        g->fl[a][5 + t1][p] = f[5];
+        g->fl[a][5 + t2][p] = f[6];
+        g->sg[a][p] = f[0] > 0.0 ? 1 : (f[0] < 0.0 ? -1 : 0);
+      }
+  }
+  g->n_hll += nhll;
+  g->n_deg += ndeg;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O5 / O6: corner EMF, Eq. 10 with R3/R4, Eq. 11 with R6.                  */
+/* ------------------------------------------------------------------------ */
+
+/* Upwind choice of Eq. 11: the value on the side the mass flux comes from. */
+static double upwind(int sign, double from_low, double from_high) {
+  if (sign > 0) return from_low;
+  if (sign < 0) return from_high;
+  return 0.5 * (from_low + from_high);
+}
+
+/* Edge EMF component c, staggered along a = c+1 and b = c+2 (cyclic).
+   Edge index p sits at p - ea/2 - eb/2. */
+static void corner_emf(orc_grid *g, int c) {
+  int a = (c + 1) % 3, b = (c + 2) % 3;
+  long sa = g->st[a], sb = g->st[b];
+  const double *fa = g->fl[a][5 + b]; /* a-face flux of B_b */
+  const double *fb = g->fl[b][5 + a]; /* b-face flux of B_a */
+  const signed char *ga = g->sg[a], *gb = g->sg[b];
+  const double *cc = g->ec[c];
+  double *out = g->e[c];
+  int lo[3] = {0, 0, 0}, hi[3], k;
+  hi[a] = g->n[a];
+  hi[b] = g->n[b];
+  hi[c] = g->n[c] - 1;
+#pragma omp parallel for schedule(static)
+  for (k = lo[2]; k <= hi[2]; ++k) {
+    int i, j;
+    for (j = lo[1]; j <= hi[1]; ++j)
+      for (i = lo[0]; i <= hi[0]; ++i) {
+        long p = at(g, i, j, k);
+        /* face EMFs: at an a-face E_c = -Fa[B_b]; at a b-face E_c = +Fb[B_a] */
+        double X0 = -fa[p], X1 = -fa[p - sb];      /* (a-1/2, b), (a-1/2, b-1) */
+        double Y0 = fb[p], Y1 = fb[p - sa];        /* (a, b-1/2), (a-1, b-1/2) */
+        double c00 = cc[p - sa - sb], c10 = cc[p - sb]; /* (a-1,b-1), (a,b-1) */
+        double c01 = cc[p - sa], c11 = cc[p];           /* (a-1,b),   (a,b)   */
+        /* derivatives along b, upwinded by the a-face mass flux */
+        double db_q1 = upwind(ga[p], c01 - Y1, c11 - Y0);          /* b - 1/4 */
+        double db_q3 = upwind(ga[p - sb], Y1 - c00, Y0 - c10);     /* b - 3/4 */
+        /* derivatives along a, upwinded by the b-face mass flux */
+        double da_q1 = upwind(gb[p], c10 - X1, c11 - X0);          /* a - 1/4 */
+        double da_q3 = upwind(gb[p - sa], X1 - c00, X0 - c01);     /* a - 3/4 */
+        out[p] = 0.25 * (X0 + X1 + Y0 + Y1) + 0.25 * (db_q3 - db_q1) +
+                 0.25 * (da_q3 - da_q1);
+      }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O12: source vector S = (0, -rho grad Phi, -rho v.grad Phi, 0).          */
+/* ------------------------------------------------------------------------ */
+
+static void grad_phi(const orc_grid *g, double x, double y, double z, double gp[3]) {
+  const double *s = g->c.src;
+  gp[0] = gp[1] = gp[2] = 0.0;
+  switch (g->c.source) {
+    case ORC_SRC_LOGPOT: {
+      double v0 = s[0], rc = s[1], q = s[2];
+      double den = rc * rc + x * x + y * y + z * z / (q * q);
+      gp[0] = v0 * v0 * x / den;
+      gp[1] = v0 * v0 * y / den;
+      gp[2] = v0 * v0 * (z / (q * q)) / den;
+      break;
+    }
+    case ORC_SRC_UNIFORM:
+      gp[0] = s[0]; gp[1] = s[1]; gp[2] = s[2];
+      break;
+    case ORC_SRC_GAUSS_X: {
+      double A = s[0], wd = s[1];
+      /* Phi = -A exp(-(x/w)^2) -> dPhi/dx = 2 A x / w^2 exp(-(x/w)^2) */
+      gp[0] = 2.0 * A * x / (wd * wd) * exp(-(x / wd) * (x / wd));
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O7 / O11: conservative update (Eq. 7) and CT induction update (Eq. 8).  */
+/* ------------------------------------------------------------------------ */
+
+static void update(orc_grid *g, double dt, double *const u0[5], double *const b0[3],
+                   double *const u1[5], double *const b1[3]) {
+  int a, k;
+  /* faces first (the floors below need the new cell-centred B) */
+  for (a = 0; a < 3; ++a) {
+    int b = (a + 1) % 3, c = (a + 2) % 3;
+    long sb = g->st[b], sc = g->st[c];
+    const double *Ec = g->e[c], *Eb = g->e[b];
+    double rb = dt / g->d[b], rc = dt / g->d[c];
+    int hi[3];
+    hi[0] = g->n[0] - 1; hi[1] = g->n[1] - 1; hi[2] = g->n[2] - 1;
+    hi[a] = nface(g, a) - 1;
+#pragma omp parallel for schedule(static)
+    for (k = 0; k <= hi[2]; ++k) {
+      int i, j;
+      for (j = 0; j <= hi[1]; ++j)
+        for (i = 0; i <= hi[0]; ++i) {
+          long p = at(g, i, j, k);
+          /* dB_a/dt = -(curl E)_a = -(dE_c/db - dE_b/dc) */
+          b1[a][p] = b0[a][p] - rb * (Ec[p + sb] - Ec[p]) + rc * (Eb[p + sc] - Eb[p]);
+        }
+    }
+  }
+  double rx = dt / g->d[0], ry = dt / g->d[1], rz = dt / g->d[2];
+  double gam = g->c.gamma;
+  int64_t nfl = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nfl)
+  for (k = 0; k < g->n[2]; ++k) {
+    int i, j, m;
+    for (j = 0; j < g->n[1]; ++j)
+      for (i = 0; i < g->n[0]; ++i) {
+        long p = at(g, i, j, k);
+        double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (g->c.source != ORC_SRC_NONE) {
+          double gp[3];
+          double x = g->c.x0 + (i + 0.5) * g->d[0];
+          double y = g->c.y0 + (j + 0.5) * g->d[1];
+          double z = g->c.z0 + (k + 0.5) * g->d[2];
+          grad_phi(g, x, y, z, gp);
+          double rho = g->w[0][p];
+          s[1] = -rho * gp[0];
+          s[2] = -rho * gp[1];
+          s[3] = -rho * gp[2];
+          s[4] = -rho * (g->w[1][p] * gp[0] + g->w[2][p] * gp[1] + g->w[3][p] * gp[2]);
+        }
+        for (m = 0; m < 5; ++m) {
+          double v = u0[m][p];
+          v -= rx * (g->fl[0][m][p + g->st[0]] - g->fl[0][m][p]);
+          v -= ry * (g->fl[1][m][p + g->st[1]] - g->fl[1][m][p]);
+          v -= rz * (g->fl[2][m][p + g->st[2]] - g->fl[2][m][p]);
+          v += dt * s[m];
+          u1[m][p] = v;
+        }
+        if (g->c.rho_floor > 0.0 || g->c.p_floor > 0.0) {
+          int hit = 0;
+          if (u1[0][p] < g->c.rho_floor) { u1[0][p] = g->c.rho_floor; hit = 1; }
+          double bcx = 0.5 * (b1[0][p] + b1[0][p + g->st[0]]);
+          double bcy = 0.5 * (b1[1][p] + b1[1][p + g->st[1]]);
+          double bcz = 0.5 * (b1[2][p] + b1[2][p + g->st[2]]);
+          double rho = u1[0][p];
+          double ke = 0.5 * (u1[1][p] * u1[1][p] + u1[2][p] * u1[2][p] + u1[3][p] * u1[3][p]) / rho;
+          double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
+          double P = (gam - 1.0) * (u1[4][p] - ke - me);
+          if (P < g->c.p_floor) { u1[4][p] += (g->c.p_floor - P) / (gam - 1.0); hit = 1; }
+          nfl += hit;
+        }
+      }
+  }
+  g->n_floor += nfl;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O3: CFL time step (R9).                                                  */
+/* ------------------------------------------------------------------------ */
+
+double orc_dt(orc_grid *g) {
+  double gam = g->c.gamma;
+  double best = INFINITY;
+  int k;
+#pragma omp parallel for schedule(static) reduction(min : best)
+  for (k = 0; k < g->n[2]; ++k) {
+    int i, j, a;
+    for (j = 0; j < g->n[1]; ++j)
+      for (i = 0; i < g->n[0]; ++i) {
+        double w[8];
+        cell_prim(g, g->u, g->b, at(g, i, j, k), w);
+        for (a = 0; a < 3; ++a) {
+          int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+          double w7[7] = {w[0], w[1 + a], w[1 + t1], w[1 + t2], w[4], w[5 + t1], w[5 + t2]};
+          double cf = orc_fast_speed(w7, w[5 + a], gam);
+          double v = fabs(w[1 + a]);
+          double r = g->d[a] / (v + cf);
+          if (r < best) best = r;
+        }
+      }
+  }
+  return g->c.cfl * best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One step (R1): predictor to t^{n+1/2}, corrector to t^{n+1}.            */
+/* ------------------------------------------------------------------------ */
+
+double orc_step(orc_grid *g, double dt) {
+  int a;
+  if (!(dt > 0.0)) dt = orc_dt(g);
+  /* predictor: first-order fluxes of U^n, half step */
+  primitives(g, g->u, g->b);
+  for (a = 0; a < 3; ++a) sweep(g, a, g->b, ORC_RECON_FIRST);
+  for (a = 0; a < 3; ++a) corner_emf(g, a);
+  update(g, 0.5 * dt, g->u, g->b, g->us, g->bs);
+  fill_ghosts(g, g->us, g->bs);
+  /* corrector: MUSCL fluxes of U*, full step from U^n */
+  primitives(g, g->us, g->bs);
+  for (a = 0; a < 3; ++a) sweep(g, a, g->bs, g->c.recon);
+  for (a = 0; a < 3; ++a) corner_emf(g, a);
+  update(g, dt, g->u, g->b, g->u, g->b);
+  fill_ghosts(g, g->u, g->b);
+  g->t += dt;
+  g->step += 1;
+  return dt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* State in / out                                                           */
+/* ------------------------------------------------------------------------ */
+
+int orc_set_state(orc_grid *g, const double *cell5, const double *bx,
+                  const double *by, const double *bz) {
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+  int fx = nface(g, 0), fy = nface(g, 1), fz = nface(g, 2);
+  int i, j, k, m;
+  long ncell = (long)nx * ny * nz;
+  for (m = 0; m < 5; ++m)
+    for (k = 0; k < nz; ++k)
+      for (j = 0; j < ny; ++j)
+        for (i = 0; i < nx; ++i)
+          g->u[m][at(g, i, j, k)] = cell5[m * ncell + ((long)k * ny + j) * nx + i];
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < fx; ++i) g->b[0][at(g, i, j, k)] = bx[((long)k * ny + j) * fx + i];
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < fy; ++j)
+      for (i = 0; i < nx; ++i) g->b[1][at(g, i, j, k)] = by[((long)k * fy + j) * nx + i];
+  for (k = 0; k < fz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < nx; ++i) g->b[2][at(g, i, j, k)] = bz[((long)k * ny + j) * nx + i];
+  fill_ghosts(g, g->u, g->b);
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < nx; ++i) {
+        double w[8];
+        cell_prim(g, g->u, g->b, at(g, i, j, k), w);
+        for (m = 0; m < 8; ++m)
+          if (!isfinite(w[m])) return -3;
+        if (!(w[0] > 0.0) || !(w[4] > 0.0)) return -3;
+      }
+  return 0;
+}
+
+void orc_get_state(const orc_grid *g, double *cell5, double *bx, double *by,
+                   double *bz) {
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+  int fx = nface(g, 0), fy = nface(g, 1), fz = nface(g, 2);
+  int i, j, k, m;
+  long ncell = (long)nx * ny * nz;
+  if (cell5)
+    for (m = 0; m < 5; ++m)
+      for (k = 0; k < nz; ++k)
+        for (j = 0; j < ny; ++j)
+          for (i = 0; i < nx; ++i)
+            cell5[m * ncell + ((long)k * ny + j) * nx + i] = g->u[m][at(g, i, j, k)];
+  if (bx)
+    for (k = 0; k < nz; ++k)
+      for (j = 0; j < ny; ++j)
+        for (i = 0; i < fx; ++i) bx[((long)k * ny + j) * fx + i] = g->b[0][at(g, i, j, k)];
+  if (by)
+    for (k = 0; k < nz; ++k)
+      for (j = 0; j < fy; ++j)
+        for (i = 0; i < nx; ++i) by[((long)k * fy + j) * nx + i] = g->b[1][at(g, i, j, k)];
+  if (bz)
+    for (k = 0; k < fz; ++k)
+      for (j = 0; j < ny; ++j)
+        for (i = 0; i < nx; ++i) bz[((long)k * ny + j) * nx + i] = g->b[2][at(g, i, j, k)];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics: Neumaier-compensated FP64 sums.                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double s, c; } ksum;
+static void kadd(ksum *k, double x) {
+  double t = k->s + x;
+  if (fabs(k->s) >= fabs(x)) k->c += (k->s - t) + x;
+  else k->c += (x - t) + k->s;
+  k->s = t;
+}
+static double kval(const ksum *k) { return k->s + k->c; }
+
+void orc_diag_get(orc_grid *g, orc_diag *out) {
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+  double dv = g->d[0] * g->d[1] * g->d[2];
+  ksum s[5], bs[3];
+  int i, j, k, m, a;
+  memset(s, 0, sizeof s);
+  memset(bs, 0, sizeof bs);
+  double rmin = INFINITY, pmin = INFINITY, bmax = 0.0, dmax = 0.0;
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < nx; ++i) {
+        long p = at(g, i, j, k);
+        double w[8];
+        cell_prim(g, g->u, g->b, p, w);
+        for (m = 0; m < 5; ++m) kadd(&s[m], g->u[m][p]);
+        if (w[0] < rmin) rmin = w[0];
+        if (w[4] < pmin) pmin = w[4];
+        double dvb = (g->b[0][p + g->st[0]] - g->b[0][p]) / g->d[0] +
+                     (g->b[1][p + g->st[1]] - g->b[1][p]) / g->d[1] +
+                     (g->b[2][p + g->st[2]] - g->b[2][p]) / g->d[2];
+        if (fabs(dvb) > dmax) dmax = fabs(dvb);
+      }
+  for (a = 0; a < 3; ++a) {
+    int hi[3] = {nx, ny, nz};
+    hi[a] = nface(g, a);
+    for (k = 0; k < hi[2]; ++k)
+      for (j = 0; j < hi[1]; ++j)
+        for (i = 0; i < hi[0]; ++i) {
+          double v = g->b[a][at(g, i, j, k)];
+          kadd(&bs[a], v);
+          if (fabs(v) > bmax) bmax = fabs(v);
+        }
+  }
+  double h = g->d[0];
+  if (g->d[1] < h) h = g->d[1];
+  if (g->d[2] < h) h = g->d[2];
+  out->t = g->t;
+  out->step = g->step;
+  out->mass = kval(&s[0]) * dv;
+  out->mom[0] = kval(&s[1]) * dv;
+  out->mom[1] = kval(&s[2]) * dv;
+  out->mom[2] = kval(&s[3]) * dv;
+  out->energy = kval(&s[4]) * dv;
+  for (a = 0; a < 3; ++a) out->bsum[a] = kval(&bs[a]) * dv;
+  out->divb_max = bmax > 0.0 ? dmax * h / bmax : dmax * h;
+  out->rho_min = rmin;
+  out->p_min = pmin;
+  out->n_floor = g->n_floor;
+  out->n_hll_fallback = g->n_hll;
+  out->n_degenerate = g->n_deg;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Debug access to the last corrector stage.                                */
+/* ------------------------------------------------------------------------ */
+
+long orc_debug_array(const orc_grid *g, int what, double *out) {
+  long p;
+  const double *src = NULL;
+  if (what >= 0 && what < 24) src = g->fl[what / 8][what % 8];
+  else if (what >= 24 && what < 27) src = g->e[what - 24];
+  else if (what >= 27 && what < 30) src = g->ec[what - 27];
+  else if (what >= 30 && what < 33) {
+    for (p = 0; p < g->np; ++p) out[p] = (double)g->sg[what - 30][p];
+    return g->np;
+  } else {
+    return -1;
+  }
+  memcpy(out, src, (size_t)g->np * sizeof(double));
+  return g->np;
+}

@@ -1,0 +1,128 @@
+/*
+ * orc.h -- plain FP64 CPU oracle for the explicit TVD-MUSCL ideal-MHD step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this library; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source with the GPU library.
+ *
+ * What it computes (Khoperskov et al., "Numerical code for multi-component
+ * galaxies", section 2.1):
+ *   - conserved state U = [rho, rho v, E, B]                      (Eq. 1)
+ *   - dU/dt + dF/dx + dG/dy + dH/dz = S                           (Eq. 2)
+ *   - physical fluxes, P* = P + B^2/2, E = P/(g-1)+rho v^2/2+B^2/2 (Eq. 3)
+ *   - cell-centred rho, M, E; face-centred B                      (Eq. 4-5)
+ *   - cell-centred B as the mean of the two faces                 (Eq. 6)
+ *   - finite-volume update with time-averaged fluxes              (Eq. 7)
+ *   - constrained-transport induction update                      (Eq. 8-9)
+ *   - contact-upwinded corner EMF                                 (Eq. 10-11)
+ *   - HLLD approximate Riemann solver (Miyoshi & Kusano 2005)     (sec. 2.1)
+ *   - kappa-MUSCL reconstruction with minmod                      (Eq. 12-14)
+ * Readings where the paper is silent or misprinted (time integrator, CFL,
+ * sign of the Eq. 10 correction, ...) are listed in the project design notes
+ * and restated next to the code that implements each one.
+ *
+ * All arrays handed across this interface are host memory, FP64, interior
+ * cells only, x fastest:
+ *   cell5 : [5][nz][ny][nx]      rho, Mx, My, Mz, E
+ *   bx    : [nz][ny][nx + ox]    ox = 0 if x is periodic, else 1
+ *   by    : [nz][ny + oy][nx]
+ *   bz    : [nz + oz][ny][nx]
+ * Face (i,j,k) of bx sits at x_{i-1/2}.
+ */
+#ifndef ORC_H
+#define ORC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_INFLOW = 2 };
+enum { ORC_RECON_PAPER = 0, ORC_RECON_KAPPA = 1, ORC_RECON_FIRST = 2 };
+enum {
+  ORC_SRC_NONE = 0,
+  ORC_SRC_LOGPOT = 1,  /* Phi = v0^2/2 ln(Rc^2 + x^2 + y^2 + z^2/q^2): par = v0, Rc, q */
+  ORC_SRC_UNIFORM = 2, /* grad Phi = (gx, gy, gz) constant:              par = gx, gy, gz */
+  ORC_SRC_GAUSS_X = 3  /* Phi = -A exp(-(x/w)^2):                         par = A, w     */
+};
+
+typedef struct orc_config {
+  int32_t nx, ny, nz;
+  int32_t bc[6];          /* -x, +x, -y, +y, -z, +z; periodic must be paired */
+  double x0, y0, z0;      /* lower domain corner */
+  double dx, dy, dz;
+  double gamma;
+  double cfl;
+  int32_t recon;          /* ORC_RECON_* used by the corrector stage */
+  double kappa;           /* kappa of Eq. 12-14; 1/3 in the paper */
+  int32_t source;         /* ORC_SRC_* */
+  double src[4];
+  double rho_floor, p_floor; /* 0 = off */
+  double inflow[8];       /* primitive ghost state for ORC_BC_INFLOW sides:
+                             rho, vx, vy, vz, P, Bx, By, Bz */
+} orc_config;
+
+typedef struct orc_diag {
+  double t;
+  int64_t step;
+  double mass, mom[3], energy;  /* sums over interior cells times dV */
+  double bsum[3];               /* sums over interior faces of each B component times dV */
+  double divb_max;              /* max over interior cells |div_h B| * min(dx) / max|B| */
+  double rho_min, p_min;
+  int64_t n_floor, n_hll_fallback, n_degenerate;
+} orc_diag;
+
+typedef struct orc_grid orc_grid;
+
+orc_grid *orc_create(const orc_config *cfg);
+void orc_destroy(orc_grid *g);
+/* Returns 0, or -3 if the state has a non-finite value, rho <= 0 or P <= 0. */
+int orc_set_state(orc_grid *g, const double *cell5, const double *bx,
+                  const double *by, const double *bz);
+void orc_get_state(const orc_grid *g, double *cell5, double *bx, double *by,
+                   double *bz);
+void orc_set_time(orc_grid *g, double t, int64_t step);
+/* CFL time step of the current state. */
+double orc_dt(orc_grid *g);
+/* One full step of size dt (dt <= 0: use orc_dt()).  Returns the dt used. */
+double orc_step(orc_grid *g, double dt);
+void orc_diag_get(orc_grid *g, orc_diag *out);
+/* Number of OpenMP threads the oracle loops use (1 if built without OpenMP). */
+int orc_threads(void);
+
+/* Internal arrays left by the last corrector stage, interior-extended ranges,
+   in the padded layout [nz+2g+1][ny+2g+1][nx+2g+1] with g = 2 (x fastest):
+   what = 0..7 : x-face flux component (rho, Mx, My, Mz, E, Bx, By, Bz)
+          8..15: y-face flux, 16..23: z-face flux
+          24..26: edge EMF Ex, Ey, Ez
+          27..29: cell EMF of the corrector state
+          30..32: mass-flux sign of x, y, z faces (as doubles)
+   Returns the number of doubles written (padded size), or -1. */
+long orc_debug_array(const orc_grid *g, int what, double *out);
+long orc_padded_size(const orc_grid *g);
+
+/* ---- unit entry points (single face / stencil) ---- */
+
+/* Fast magnetosonic speed along the normal; w = rho, vn, vt1, vt2, P, Bt1, Bt2. */
+double orc_fast_speed(const double w[7], double bn, double gamma);
+/* HLLD flux in the face-normal frame.  wl, wr = rho, vn, vt1, vt2, P, Bt1, Bt2;
+   flux = rho, Mn, Mt1, Mt2, E, Bt1, Bt2.  Returns a code:
+   bit0 = HLL fallback used, bit1 = a degenerate star state met. */
+int orc_hlld(const double wl[7], const double wr[7], double bn, double gamma,
+             double flux[7]);
+/* Physical flux of Eq. 3 in the face-normal frame. */
+void orc_phys_flux(const double w[7], double bn, double gamma, double flux[7]);
+/* Conserved vector in the face-normal frame: rho, Mn, Mt1, Mt2, E, Bt1, Bt2. */
+void orc_prim_to_cons(const double w[7], double bn, double gamma, double u[7]);
+double orc_minmod(double a, double b);
+/* Interface values at the face between cells 1 and 2 of the 4-cell stencil
+   w[0..3].  recon/kappa as in orc_config. */
+void orc_recon(const double w[4], int recon, double kappa, double *wl,
+               double *wr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

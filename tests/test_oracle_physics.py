@@ -1,0 +1,219 @@
+"""Grid-level pins of the FP64 oracle (no GPU): what the paper's
+conservation-law statement (Eq. 2, Eq. 7-8), the CT construction (Eq. 8-11)
+and closed-form solutions fix."""
+import math
+
+import numpy as np
+import pytest
+
+from mhd_inputs import problems as P
+from tests.exact_euler import cell_average
+from tests.helpers import oracle_of, prim_1d, run_to
+from oracle import pyorc as O
+
+
+# ------------------------------------------------------------ free stream --
+
+@pytest.mark.parametrize("bc", [(P.PERIODIC,) * 6, (P.OUTFLOW,) * 6,
+                                (P.PERIODIC, P.PERIODIC, P.OUTFLOW, P.OUTFLOW, P.PERIODIC,
+                                 P.PERIODIC)])
+def test_free_stream_bitwise(bc):
+    """A uniform state stays bitwise uniform: every face sees identical
+    inputs, so every flux difference and every EMF curl is exactly zero."""
+    pb = P.uniform((7, 5, 6), bc=bc)
+    o = oracle_of(pb)
+    for _ in range(3):
+        o.step()
+    c5, bx, by, bz = o.get_state()
+    np.testing.assert_array_equal(c5, pb.cell5)
+    np.testing.assert_array_equal(bx, pb.bx)
+    np.testing.assert_array_equal(by, pb.by)
+    np.testing.assert_array_equal(bz, pb.bz)
+    # uniform flow: every edge EMF equals the cell EMF -v x B
+    v = np.array([0.3, -0.2, 0.1]); b = np.array([0.5, -0.4, 0.3])
+    ec = -np.cross(v, b)
+    for c in range(3):
+        e = o.debug_array(24 + c)[2:-3, 2:-3, 2:-3]
+        np.testing.assert_allclose(e, ec[c], rtol=0, atol=1e-15)
+
+
+# ----------------------------------------------------------- conservation --
+
+def test_conservation_periodic():
+    """Periodic box, S = 0: total mass, momentum and energy, and the sum of
+    each face-B component over every plane normal to it, are constant
+    (flux differences and EMF differences telescope)."""
+    pb = P.random_smooth((12, 10, 8), seed=11)
+    o = oracle_of(pb)
+    d0 = o.diag()
+    c0, bx0, by0, bz0 = o.get_state()
+    for _ in range(10):
+        o.step()
+    d1 = o.diag()
+    c1, bx1, by1, bz1 = o.get_state()
+    for m in range(5):
+        scale = np.abs(c0[m]).sum()
+        assert abs(c1[m].sum() - c0[m].sum()) <= 1e-13 * scale, m
+    for b0, b1, ax in ((bx0, bx1, 2), (by0, by1, 1), (bz0, bz1, 0)):
+        axes = tuple(a for a in range(3) if a != ax)
+        s0, s1 = b0.sum(axis=axes), b1.sum(axis=axes)
+        assert np.abs(s1 - s0).max() <= 1e-13 * np.abs(b0).sum(axis=axes).max()
+    assert d1["n_hll_fallback"] == 0 and d1["n_floor"] == 0
+
+
+@pytest.mark.parametrize("bc", [(P.PERIODIC,) * 6, (P.OUTFLOW,) * 6])
+def test_divb_preserved(bc):
+    """CT keeps the discrete divergence of a divergence-free initial field at
+    rounding level in every interior cell, for any boundary condition."""
+    pb = P.random_smooth((10, 9, 8), seed=12, bc=bc)
+    o = oracle_of(pb)
+    assert o.diag()["divb_max"] < 1e-13
+    for _ in range(10):
+        o.step()
+    assert o.diag()["divb_max"] < 1e-12
+
+
+# -------------------------------------------------- CT 1-D reduction (Eq.10)
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_ct_contact_one_dimensional_reduction(axis):
+    """For a flow that varies only along one axis, the corner EMF of Eq. 10
+    (with the derivative terms as (3/4-point) - (1/4-point)) must reduce to
+    the Godunov face EMF of that axis; the two edge components staggered in
+    the uniform directions reduce to the cell EMF.  The printed order of the
+    correction would give the mean of the two cell EMFs instead."""
+    pb = P.brio_wu(24, axis=axis)
+    o = oracle_of(pb)
+    o.step()
+    o.step()
+    n = [pb.nx, pb.ny, pb.nz]
+    a, t1, t2 = axis, (axis + 1) % 3, (axis + 2) % 3
+
+    def interior(arr, hi_extra):
+        sl = []
+        for d in (2, 1, 0):
+            sl.append(slice(2, 2 + n[d] + hi_extra[d]))
+        return arr[tuple(sl)]
+
+    fl = lambda comp: o.debug_array(8 * a + comp)  # face flux along the axis
+    ex = [0, 0, 0]
+    ex[a] = 1
+    # E_{t2} edge, staggered along a and t1: equals the a-face EMF -F_a[B_t1]
+    e_t2 = interior(o.debug_array(24 + t2), ex)
+    f_bt1 = interior(fl(5 + t1), ex)
+    scale = np.abs(f_bt1).max()
+    np.testing.assert_allclose(e_t2, -f_bt1, rtol=0, atol=1e-14 * scale)
+    # E_{t1} edge, staggered along t2 and a: equals the a-face EMF +F_a[B_t2]
+    e_t1 = interior(o.debug_array(24 + t1), ex)
+    f_bt2 = interior(fl(5 + t2), ex)
+    np.testing.assert_allclose(e_t1, f_bt2, rtol=0, atol=1e-14 * max(scale, 1e-300) + 1e-300)
+    # E_a edge, staggered along the two uniform axes: equals the cell EMF
+    e_a = interior(o.debug_array(24 + a), [0, 0, 0])
+    ec_a = interior(o.debug_array(27 + a), [0, 0, 0])
+    np.testing.assert_allclose(e_a, ec_a, rtol=0, atol=1e-14 * (np.abs(ec_a).max() + 1e-30))
+
+
+# ------------------------------------------------------- axis permutation --
+
+def test_axis_permutation():
+    """A one-dimensional problem laid along x, y or z gives the same numbers
+    up to rounding (the sweeps use the cyclic frames (x,y,z), (y,z,x),
+    (z,x,y); only the order of the three terms in |v|^2 and |B|^2 differs).
+    An index or component mix-up would show as an O(1) difference."""
+    res = []
+    for axis in range(3):
+        o = oracle_of(P.ryu_jones(40, axis=axis))
+        for _ in range(8):
+            o.step()
+        q = prim_1d(o, axis)
+        c5, bx, by, bz = o.get_state()
+        res.append((q, c5[0].reshape(-1), c5[4].reshape(-1)))
+    for r in res[1:]:
+        for k in res[0][0]:
+            np.testing.assert_allclose(r[0][k], res[0][0][k], rtol=0,
+                                       atol=1e-13 * (np.abs(res[0][0][k]).max() + 1e-300),
+                                       err_msg=k)
+        np.testing.assert_allclose(r[1], res[0][1], rtol=1e-13)
+        np.testing.assert_allclose(r[2], res[0][2], rtol=1e-13)
+
+
+# ---------------------------------------------------------- source term ---
+
+def test_uniform_gravity_closed_form():
+    """Uniform gas in a constant field grad Phi = g: fluxes stay uniform, so
+    v(t) = -g t and E(t) = E0 + rho |g|^2 t^2 / 2 exactly; the
+    stage-consistent source (dt/2 S(W^n), then dt S(W*)) integrates the
+    linear-in-time velocity without error."""
+    pb = P.uniform((4, 4, 4), v=(0.0, 0.0, 0.0), rho=1.3, p=0.9, b=(0.2, 0.1, 0.3))
+    g = (0.7, -0.4, 0.25)
+    pb.source, pb.src = P.SRC_UNIFORM, (g[0], g[1], g[2], 0.0)
+    o = oracle_of(pb)
+    t = 0.0
+    for _ in range(7):
+        t += o.step(0.013)
+    c5, *_ = o.get_state()
+    rho = 1.3
+    for d in range(3):
+        np.testing.assert_allclose(c5[1 + d], -rho * g[d] * t, rtol=1e-13, atol=1e-15)
+    E0 = pb.cell5[4]
+    np.testing.assert_allclose(c5[4], E0 + 0.5 * rho * sum(x * x for x in g) * t * t,
+                               rtol=1e-13)
+
+
+# ---------------------------------------------------- Alfven convergence ---
+
+def _alfven_err(n, t_end, recon=O.RECON_PAPER):
+    pb = P.alfven(n)
+    o = oracle_of(pb, recon=recon)
+    run_to(o, t_end)
+    c5, *_ = o.get_state()
+    vx, vy, vz = P.alfven_exact(n, t_end)
+    err = np.mean(np.abs(c5[1] - vx) + np.abs(c5[2] - vy) + np.abs(c5[3] - vz))
+    return err, o.diag()
+
+
+def test_alfven_wave_convergence_paper_muscl():
+    """The circularly polarised Alfven wave is an exact nonlinear solution.
+    With Eq. 13-14 as printed the L1 momentum error at a fixed time falls at
+    about h^1.56 (its limiter switches branch where dw_{i-1} = dw_i); a
+    dropped term or a sign slip anywhere in the step gives order <= 1."""
+    t_end = 0.1
+    e16, _ = _alfven_err(16, t_end)
+    e32, d32 = _alfven_err(32, t_end)
+    order = math.log2(e16 / e32)
+    assert order >= 1.5, (e16, e32, order)
+    assert e32 < 3e-3
+    assert d32["n_hll_fallback"] == 0
+    assert abs(d32["mass"] - 1.0) < 1e-13
+
+
+def test_alfven_wave_convergence_kappa_scheme():
+    """The textbook kappa = 1/3 form reaches second order (32^3 -> 64^3)."""
+    t_end = 0.1
+    e32, _ = _alfven_err(32, t_end, O.RECON_KAPPA)
+    e64, _ = _alfven_err(64, t_end, O.RECON_KAPPA)
+    order = math.log2(e32 / e64)
+    assert order >= 1.85, (e32, e64, order)
+
+
+# ------------------------------------------------------ Sod shock tube -----
+
+def test_sod_converges_to_exact():
+    """Sod tube (section 3), B = 0: the L1 density error against the exact
+    Euler solution decreases with resolution (first order at the shock and
+    contact)."""
+    errs = []
+    for n in (100, 200, 400):
+        pb = P.sod(n)
+        o = oracle_of(pb)
+        run_to(o, pb.t_end)
+        c5, *_ = o.get_state()
+        rho = c5[0].reshape(-1)
+        h = pb.extra["h"]
+        x_lo = pb.extra["xlo"] + np.arange(n) * h
+        ex = cell_average(x_lo, h, pb.t_end, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1.4)
+        errs.append(np.mean(np.abs(rho - ex)) * 2.0)
+    assert errs[0] > errs[1] > errs[2], errs
+    order = math.log2(errs[0] / errs[2]) / 2.0
+    assert order >= 0.6, (errs, order)
+    assert errs[2] < 5e-3
