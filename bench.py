@@ -1,0 +1,226 @@
+"""Throughput benchmark of the ideal-MHD TVD-MUSCL step on one MI355X.
+
+Workload: periodic turbulent-ISM box (256^3 cells, ideal MHD gamma 5/3,
+lognormal density sigma_lnrho = 1, k^-4 Gaussian random velocity on
+1 <= |k| <= 16 at rms Mach 3, isothermal start P = 0.1 rho, uniform B_x at
+plasma beta 1, seed 1, CFL 0.4).  One step = one full predictor-corrector
+step of the whole box (every kernel of the path, device CFL dt).
+
+Prints one JSON line: FP32-bulk throughput (the headline value), the FP64
+throughput, the FP32-vs-FP64 L1/Linf error per field after 100 steps from the
+same FP32-rounded state with the same time steps, the roofline position of
+the dominant kernel (HIP events around each launch inside the timed region)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--err-steps", type=int, default=100)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_run(pb, precision, steps, warmup):
+    import torch
+    from paper_1502_02935_amd import Sim, config_from_problem
+    cfg = config_from_problem(pb, precision=precision)
+    sim = Sim(cfg, pb.cell5, pb.bx, pb.by, pb.bz)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile_get()
+    sim.profile(False)
+    d = sim.diag()
+    return (t1 - t0), prof, d, sim
+
+
+def error_run(pb, nsteps):
+    """FP64 run recording its CFL dts, then FP32 with the same dts, both from
+    the same FP32-rounded initial state; L1 and Linf per field."""
+    import numpy as np
+    import torch
+    from paper_1502_02935_amd import Sim, config_from_problem
+    s64 = Sim(config_from_problem(pb, precision=0), pb.cell5, pb.bx, pb.by, pb.bz)
+    dts = []
+    for _ in range(nsteps):
+        dts.append(s64.dt())
+        s64.step(1, dt=dts[-1])
+    s32 = Sim(config_from_problem(pb, precision=1), pb.cell5, pb.bx, pb.by, pb.bz)
+    s32.step(nsteps, dt=dts)
+    a = s64.get_state()
+    b = s32.get_state()
+    names = ("rho", "Mx", "My", "Mz", "E")
+    out = {}
+    for m in range(5):
+        r = a[0][m]
+        e = (b[0][m].double() - r)
+        out[names[m]] = {"L1_rel": float(e.abs().mean() / r.abs().mean()),
+                         "Linf_rel": float(e.abs().max() / r.abs().max())}
+    for q, nm in enumerate(("Bx", "By", "Bz")):
+        r = a[1 + q]
+        e = b[1 + q].double() - r
+        den_mean = float(r.abs().mean())
+        den_max = float(r.abs().max())
+        out[nm] = {"L1_rel": float(e.abs().mean()) / den_mean if den_mean > 0 else float(e.abs().mean()),
+                   "Linf_rel": float(e.abs().max()) / den_max if den_max > 0 else float(e.abs().max())}
+    d32 = s32.diag()
+    torch.cuda.synchronize()
+    return out, {"steps": nsteps, "t_end": float(np.sum(dts)),
+                 "fp64_recovery_cell_evals": d32["n_fp64_recovery"]}
+
+
+def flux_kernel_bytes(n, elem):
+    """Algorithmic HBM bytes of one flux-sweep launch: each face reads the 7
+    reconstructed primitive fields once (neighbour reuse is on chip) and its
+    normal B, and writes 7 flux components and a sign byte."""
+    faces = (n + 1) * (n + 2) * (n + 2)
+    return faces * (8 * elem + 7 * elem + 1)
+
+
+def cpu_baseline(pb, seconds):
+    """The FP64 oracle on the first steps of the same workload, on this host's
+    cores, stopping after about `seconds` of work."""
+    from oracle.pyorc import Oracle, OrcConfig, load_oracle
+    L = load_oracle()
+    o = Oracle(OrcConfig(nx=pb.nx, ny=pb.ny, nz=pb.nz, dx=pb.dx, dy=pb.dy, dz=pb.dz,
+                         gamma=pb.gamma, cfl=pb.cfl, bc=pb.bc))
+    assert o.set_state(pb.cell5, pb.bx, pb.by, pb.bz) == 0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step()
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": pb.ncell * steps / el, "unit": "cell-updates/s", "cores": L.orc_threads(),
+            "kind": "oracle",
+            "sample": "first %d FP64 steps of the same %dx%dx%d box (CPU: %s)" % (
+                steps, pb.nx, pb.ny, pb.nz, model),
+            "seconds": el}
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print("bench.py runs one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if "cpu_baseline_threads" not in os.environ:
+        try:
+            os.environ.setdefault("OMP_NUM_THREADS", str(len(os.sched_getaffinity(0))))
+        except AttributeError:
+            pass
+    import torch
+
+    from mhd_inputs import problems as P
+    n = args.n
+    log("generating turbulent ISM box %d^3 seed %d" % (n, args.seed))
+    pb = P.turbulent_ism(n, seed=args.seed).astype("float32")
+    cells = pb.ncell
+
+    log("FP32 timed run: %d warmup + %d steps" % (args.warmup, args.steps))
+    el32, prof32, d32, _ = timed_run(pb, 1, args.steps, args.warmup)
+    rate32 = cells * args.steps / el32
+    log("  %.3f ms/step, %.3e cell-updates/s" % (1e3 * el32 / args.steps, rate32))
+    result = {
+        "metric": "MHD cell-updates/s",
+        "value": rate32,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "turbulent-ISM periodic box %d^3, ideal MHD gamma 5/3, lognormal rho "
+                        "(sigma 1), k^-4 velocity rms Mach 3, beta 1, seed %d, CFL 0.4; "
+                        "FP32 bulk with FP64 pressure recovery, dt and sums" % (n, args.seed),
+            "cells": cells,
+            "kernels_per_step": {k: v[1] / args.steps for k, v in prof32.items() if v[1]},
+        },
+    }
+    kern = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1], "share": v[0] / sum(
+        x[0] for x in prof32.values())} for k, v in prof32.items() if v[1]}
+    result["kernel_profile_fp32"] = kern
+    # dominant kernel class
+    flux = {k: v for k, v in kern.items() if k.startswith("flux")}
+    fx = flux.get("flux_x")
+    if fx:
+        ms = sum(v["ms_per_launch"] * v["launches"] for v in flux.values()) / sum(
+            v["launches"] for v in flux.values())
+        byts = flux_kernel_bytes(n, 4)
+        ach = byts / (ms * 1e-3) / 1e9
+        result["roofline"] = {"kernel": "k_flux (MUSCL/first-order + HLLD sweep)", "bound": "hbm",
+                              "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                              "ms_per_launch": ms, "bytes_per_launch": byts}
+
+    if not args.no_fp64:
+        log("FP64 timed run")
+        el64, prof64, d64, _ = timed_run(pb, 0, args.steps, args.warmup)
+        result["fp64"] = {"value": cells * args.steps / el64, "ms_per_step": 1e3 * el64 / args.steps,
+                          "kernel_ms": {k: v[0] / v[1] for k, v in prof64.items() if v[1]}}
+        log("  %.3f ms/step" % (1e3 * el64 / args.steps))
+    if not args.no_error:
+        log("FP32 vs FP64 error run, %d steps" % args.err_steps)
+        err, info = error_run(pb, args.err_steps)
+        result["error_fp32_vs_fp64"] = err
+        result["error_run"] = info
+    torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * mhd.h -- C ABI of the MI355X (gfx950) ideal-MHD TVD-MUSCL step library
+ * (libmhd.so).
+ *
+ * The library advances the conservation law of ideal magneto-gas dynamics
+ * (Khoperskov et al., "Numerical code for multi-component galaxies",
+ * section 2.1):
+ *     dU/dt + dF/dx + dG/dy + dH/dz = S,    U = [rho, rho v, E, B]   (Eq. 1-2)
+ * with the fluxes of Eq. 3 (P* = P + B^2/2, E = P/(gamma-1) + rho v^2/2 + B^2/2,
+ * rationalised units), cell-centred rho, rho v, E and face-centred B
+ * (Eq. 4-5), the finite-volume update of Eq. 7 and the constrained-transport
+ * induction update of Eq. 8-11, HLLD fluxes and the kappa-MUSCL/minmod
+ * reconstruction of Eq. 12-14.  One step is a predictor-corrector pair that
+ * yields the time-centred fluxes F^{n+1/2} of Eq. 7: first-order fluxes of U^n
+ * advance U and B by dt/2, then MUSCL fluxes of that half-step state advance
+ * U^n and B^n by dt.
+ *
+ * Memory layout of every state array handed across this ABI (device memory,
+ * x fastest, interior cells only, element type double for MHD_FP64 and float
+ * for MHD_FP32):
+ *     cell5 : [5][nz][ny][nx]     rho, Mx, My, Mz, E
+ *     bx    : [nz][ny][nx + ox]   face (i,j,k) at x0 + i dx
+ *     by    : [nz][ny + oy][nx]
+ *     bz    : [nz + oz][ny][nx]
+ * with o = 0 on a periodic axis and 1 otherwise (the last face is then a
+ * boundary face that the induction update also advances).
+ *
+ * Ownership: the caller owns every device buffer and the HIP stream; the
+ * library owns only the host-side context (freed by mhd_destroy).  The library
+ * never allocates device memory: all scratch lives in the caller's workspace
+ * (size from mhd_workspace_bytes).  Work is enqueued on the caller's stream;
+ * only mhd_init, mhd_dt, mhd_diag, mhd_get_state and mhd_debug_array wait for
+ * it.  A context is bound to one stream and is not thread-safe.
+ *
+ * Errors: every call returns MHD_OK (0) or a negative mhd_status.  No C++
+ * exception crosses the ABI.  MHD_E_STATE is sticky: once a kernel has seen a
+ * non-finite value, rho <= 0 or P <= 0 in an interior cell, mhd_step refuses
+ * to run and mhd_dt / mhd_diag report it.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHD_ABI_VERSION 1
+
+typedef enum mhd_status {
+  MHD_OK = 0,
+  MHD_E_ARG = -1,          /* bad argument or configuration */
+  MHD_E_HIP = -2,          /* a HIP runtime call failed */
+  MHD_E_STATE = -3,        /* non-finite, rho <= 0 or P <= 0 seen (sticky) */
+  MHD_E_UNSUPPORTED = -4,  /* valid but not implemented combination */
+  MHD_E_WS = -5            /* workspace too small or misaligned */
+} mhd_status;
+
+enum { MHD_FP64 = 0, MHD_FP32 = 1 };
+enum { MHD_BC_PERIODIC = 0, MHD_BC_OUTFLOW = 1, MHD_BC_INFLOW = 2 };
+enum { MHD_RECON_PAPER = 0, MHD_RECON_KAPPA = 1, MHD_RECON_FIRST = 2 };
+enum {
+  MHD_SRC_NONE = 0,
+  MHD_SRC_LOGPOT = 1,   /* Phi = v0^2/2 ln(Rc^2 + x^2 + y^2 + z^2/q^2); src = v0, Rc, q */
+  MHD_SRC_UNIFORM = 2,  /* grad Phi = (gx, gy, gz);                      src = gx, gy, gz */
+  MHD_SRC_GAUSS_X = 3   /* Phi = -A exp(-(x/w)^2);                        src = A, w */
+};
+
+/* Status bits (mhd_diag_t.status). */
+enum { MHD_ST_BAD_STATE = 1u };
+
+typedef struct mhd_config {
+  int32_t nx, ny, nz;     /* interior cells, each >= 1 */
+  int32_t precision;      /* MHD_FP64 or MHD_FP32 (FP32 bulk, FP64 where cancellation bites) */
+  int32_t bc[6];          /* -x, +x, -y, +y, -z, +z; periodic must be set on both sides */
+  double x0, y0, z0;      /* lower corner of the domain */
+  double dx, dy, dz;      /* cell sizes, > 0 */
+  double gamma;           /* ratio of specific heats, > 1 */
+  double cfl;             /* Courant number of the global time step, in (0, 1) */
+  int32_t recon;          /* MHD_RECON_*: reconstruction of the corrector stage */
+  int32_t source;         /* MHD_SRC_* */
+  double kappa;           /* kappa of Eq. 12-14, in [-1, 1); 1/3 in the paper */
+  double src[4];          /* parameters of the source model */
+  double rho_floor;       /* 0 = off; else rho is raised to it after each update */
+  double p_floor;         /* 0 = off; else E is raised so that P >= p_floor */
+  double inflow[8];       /* ghost primitive state of MHD_BC_INFLOW sides:
+                             rho, vx, vy, vz, P, Bx, By, Bz */
+  int32_t reserved[4];    /* must be 0 */
+} mhd_config;
+
+typedef struct mhd_diag_t {
+  double t;               /* simulated time */
+  int64_t step;           /* completed steps */
+  double dt;              /* CFL step of the current state */
+  double mass;            /* sum over interior cells of rho dV (FP64) */
+  double mom[3];          /* sum of rho v dV */
+  double energy;          /* sum of E dV */
+  double bsum[3];         /* sum over interior faces of B_d dV */
+  double divb_max;        /* max over interior cells |div_h B| min(dx,dy,dz) / max|B_face| */
+  double rho_min, p_min;  /* over interior cells */
+  int64_t n_floor;        /* floor activations */
+  int64_t n_hll_fallback; /* faces where HLLD fell back to HLL */
+  int64_t n_degenerate;   /* faces with a degenerate HLLD star state */
+  int64_t n_fp64_recovery;/* FP32 mode: cell evaluations whose pressure was redone in FP64 */
+  uint32_t status;        /* MHD_ST_* bits */
+  uint32_t pad;
+} mhd_diag_t;
+
+typedef struct mhd_ctx mhd_ctx;
+
+/* ABI version (MHD_ABI_VERSION). */
+int mhd_abi_version(void);
+
+/* Static description of an mhd_status code; never NULL. */
+const char *mhd_strerror(int code);
+
+/* Device workspace bytes needed for cfg (padded state, half-step state,
+   primitives, fluxes, edge EMFs, reduction scratch).  Returns MHD_E_ARG for
+   an invalid configuration. */
+int mhd_workspace_bytes(const mhd_config *cfg, size_t *out);
+
+/* Creates a context on the caller's stream (hip_stream: a hipStream_t, NULL =
+   the null stream).  d_ws: device workspace of ws_bytes >= the value from
+   mhd_workspace_bytes, 256-byte aligned; it must outlive the context.
+   d_cell5, d_bx, d_by, d_bz: the initial state U at t = 0 in the layout of
+   this header, copied into the workspace (the caller may free them after the
+   call).  Fills the ghost zones, checks the state (MHD_E_STATE if any
+   interior cell is non-finite or has rho <= 0 or P <= 0) and computes the
+   first CFL dt.  Synchronises the stream. */
+int mhd_init(const mhd_config *cfg, void *d_ws, size_t ws_bytes, const void *d_cell5,
+             const void *d_bx, const void *d_by, const void *d_bz, void *hip_stream,
+             mhd_ctx **out);
+
+/* Advances nsteps >= 0 steps (Eq. 7-8 via the predictor-corrector pair).
+   dt_host NULL: each step uses the CFL dt of its own initial state, computed
+   and kept on the device (no host synchronisation).  Otherwise dt_host[s]
+   (host memory, > 0) is the size of step s.  Asynchronous; returns
+   MHD_E_STATE without enqueuing anything once the sticky state error is set
+   (that is checked at the last synchronising call). */
+int mhd_step(mhd_ctx *ctx, const double *dt_host, int nsteps);
+
+/* CFL step dt = cfl min over interior cells and axes d of
+   dx_d / (|v_d| + c_f,d) of the current state, in FP64.  Synchronises. */
+int mhd_dt(mhd_ctx *ctx, double *out);
+
+/* FP64 diagnostics of the current state (see mhd_diag_t).  Synchronises.
+   Returns MHD_E_STATE (with *out filled) if the sticky status is set. */
+int mhd_diag(mhd_ctx *ctx, mhd_diag_t *out);
+
+/* Copies the interior state out, same layout and precision as mhd_init
+   (a checkpoint: mhd_init on it resumes bit-for-bit).  Synchronises. */
+int mhd_get_state(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_bz);
+
+/* Copies one internal padded array of the last corrector stage to d_out
+   (element type of the context precision, [nz+5][ny+5][nx+5], x fastest,
+   interior cell (i,j,k) at ((k+2)(ny+5) + j+2)(nx+5) + i+2):
+   what 0..6 x-face flux (rho, Mn, Mt1, Mt2, E, Bt1, Bt2 in the face frame
+   (x,y,z)), 7..13 y-face flux (frame (y,z,x)), 14..20 z-face flux (frame
+   (z,x,y)), 21..23 edge EMF Ex, Ey, Ez, 24..26 cell EMF, 27..34 primitives
+   rho, vx, vy, vz, P, Bcx, Bcy, Bcz.  *n_out gets the element count.
+   Synchronises. */
+int mhd_debug_array(mhd_ctx *ctx, int what, void *d_out, size_t *n_out);
+
+/* Kernel classes timed by the profiling hook. */
+enum {
+  MHD_K_GHOSTS = 0,
+  MHD_K_PRIM = 1,
+  MHD_K_FLUX_X = 2,
+  MHD_K_FLUX_Y = 3,
+  MHD_K_FLUX_Z = 4,
+  MHD_K_EMF = 5,
+  MHD_K_UPDATE = 6,
+  MHD_K_CFL = 7,
+  MHD_K_OTHER = 8,
+  MHD_K_COUNT = 9
+};
+
+typedef struct mhd_profile_t {
+  double ms[16];        /* summed device time per kernel class (MHD_K_*) */
+  int64_t launches[16]; /* launches per class */
+  int32_t n_kinds;      /* MHD_K_COUNT */
+  int32_t pad;
+} mhd_profile_t;
+
+/* enable != 0: from now on every kernel mhd_step enqueues is bracketed by HIP
+   events on the context's stream (host-side event objects only, no device
+   memory); enable == 0 stops.  Enabling clears earlier records. */
+int mhd_profile(mhd_ctx *ctx, int enable);
+
+/* Sums the recorded event intervals per kernel class.  Synchronises. */
+int mhd_profile_get(mhd_ctx *ctx, mhd_profile_t *out);
+
+/* Releases the host context (not the caller's device memory). */
+int mhd_destroy(mhd_ctx *ctx);
+
+/* ---- kernel-level entry points used by the parity tests ---------------- */
+
+/* HLLD flux (Miyoshi & Kusano 2005, the solver section 2.1 names) of n
+   faces in the face-normal frame on the device: d_wl, d_wr [n][7] =
+   rho, vn, vt1, vt2, P, Bt1, Bt2; d_bn [n]; d_flux [n][7] = rho, Mn, Mt1,
+   Mt2, E, Bt1, Bt2; d_code [n] (int8: bit0 HLL fallback, bit1 degenerate
+   star state; may be NULL).  precision selects double or float arrays.
+   Asynchronous on hip_stream. */
+int mhd_hlld_batch(int precision, int64_t n, const void *d_wl, const void *d_wr,
+                   const void *d_bn, double gamma, void *d_flux, int8_t *d_code,
+                   void *hip_stream);
+
+/* Eq. 12-14 interface values of n 4-cell stencils d_w4 [n][4] (face between
+   cells 1 and 2) into d_wl, d_wr [n].  Asynchronous on hip_stream. */
+int mhd_recon_batch(int precision, int64_t n, const void *d_w4, int recon, double kappa,
+                    void *d_wl, void *d_wr, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -281,6 +281,23 @@ void orc_recon(const double w[4], int recon, double kappa, double *wl,
   *wr = w[2] - dWi1;
 }
 
+void orc_hlld_batch(long n, const double *wl, const double *wr, const double *bn,
+                    double gamma, double *flux, int32_t *code) {
+  long t;
+#pragma omp parallel for schedule(static)
+  for (t = 0; t < n; ++t) {
+    int c = orc_hlld(wl + 7 * t, wr + 7 * t, bn[t], gamma, flux + 7 * t);
+    if (code) code[t] = c;
+  }
+}
+
+void orc_recon_batch(long n, const double *w4, int recon, double kappa, double *wl,
+                     double *wr) {
+  long t;
+#pragma omp parallel for schedule(static)
+  for (t = 0; t < n; ++t) orc_recon(w4 + 4 * t, recon, kappa, wl + t, wr + t);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid set-up                                                              */
 /* ------------------------------------------------------------------------ */

@@ -122,6 +122,13 @@ double orc_minmod(double a, double b);
 void orc_recon(const double w[4], int recon, double kappa, double *wl,
                double *wr);
 
+/* Loops over n faces / stencils of the two functions above (arrays [n][7],
+   [n][4], contiguous).  code may be NULL. */
+void orc_hlld_batch(long n, const double *wl, const double *wr, const double *bn,
+                    double gamma, double *flux, int32_t *code);
+void orc_recon_batch(long n, const double *w4, int recon, double kappa, double *wl,
+                     double *wr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -134,6 +134,8 @@ def load_oracle():
     L.orc_minmod.restype = C.c_double
     L.orc_minmod.argtypes = [C.c_double, C.c_double]
     L.orc_recon.argtypes = [dp, C.c_int, C.c_double, dp, dp]
+    L.orc_hlld_batch.argtypes = [C.c_long, dp, dp, dp, C.c_double, dp, C.POINTER(C.c_int32)]
+    L.orc_recon_batch.argtypes = [C.c_long, dp, C.c_int, C.c_double, dp, dp]
     _lib = L
     return L
 
@@ -259,3 +261,24 @@ def recon(w4, recon: int = RECON_PAPER, kappa: float = 1.0 / 3.0):
     wl, wr = C.c_double(), C.c_double()
     L.orc_recon(_ptr(w4), recon, kappa, C.byref(wl), C.byref(wr))
     return wl.value, wr.value
+
+
+def hlld_batch(wl, wr, bn, gamma: float):
+    """Oracle HLLD over n faces: returns flux [n][7] and codes [n]."""
+    L = load_oracle()
+    wl, wr, bn = _f64(wl), _f64(wr), _f64(bn)
+    n = bn.shape[0]
+    f = np.empty((n, 7))
+    code = np.empty(n, dtype=np.int32)
+    L.orc_hlld_batch(n, _ptr(wl), _ptr(wr), _ptr(bn), gamma, _ptr(f),
+                     code.ctypes.data_as(C.POINTER(C.c_int32)))
+    return f, code
+
+
+def recon_batch(w4, recon: int = RECON_PAPER, kappa: float = 1.0 / 3.0):
+    L = load_oracle()
+    w4 = _f64(w4)
+    n = w4.shape[0]
+    wl, wr = np.empty(n), np.empty(n)
+    L.orc_recon_batch(n, _ptr(w4), recon, kappa, _ptr(wl), _ptr(wr))
+    return wl, wr

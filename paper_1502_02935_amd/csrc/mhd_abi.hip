@@ -1,0 +1,554 @@
+// mhd_abi.hip -- C ABI of libmhd.so (declared in include/mhd.h): context,
+// workspace carving and the step sequence.  One step is the
+// predictor-corrector pair that gives the time-centred fluxes of Eq. 7:
+//   predictor: primitives of U^n, first-order HLLD fluxes, corner EMFs,
+//              U* = U^n - dt/2 div F + dt/2 S(W^n), B* = B^n - dt/2 curl E
+//   corrector: primitives of U*, MUSCL (Eq. 12-14) + HLLD fluxes, corner EMFs,
+//              U^{n+1} = U^n - dt div F + dt S(W*),  B^{n+1} = B^n - dt curl E
+// with the ghost zones refilled after each stage.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "mhd.h"
+#include "mhd_kernels.hpp"
+
+using namespace mhd;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kNumT = 51;  // T arrays: U 8, U* 8, W 8 + Ec 3, fluxes 21, edges 3
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t arr;       // bytes per padded T array
+  size_t arr8;      // bytes per padded int8 array
+  size_t off_t;     // T arrays
+  size_t off_sg;    // sign arrays
+  size_t off_misc;  // dt, t, step, counters, status, diag_out
+  size_t off_cfl;   // cfl partials
+  size_t off_diag;  // diag partials
+  size_t total;
+};
+
+bool geo_of(const mhd_config* c, Geo* g) {
+  const int n[3] = {c->nx, c->ny, c->nz};
+  long long np = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1 || n[a] > (1 << 20)) return false;
+    g->n[a] = n[a];
+    g->ext[a] = n[a] + 2 * NG + 1;
+    np *= g->ext[a];
+    const bool plo = c->bc[2 * a] == MHD_BC_PERIODIC, phi = c->bc[2 * a + 1] == MHD_BC_PERIODIC;
+    if (plo != phi) return false;
+    g->nf[a] = n[a] + (plo ? 0 : 1);
+    g->bc[2 * a] = c->bc[2 * a];
+    g->bc[2 * a + 1] = c->bc[2 * a + 1];
+  }
+  if (np >= (1ll << 31) - 16) return false;
+  g->sy = g->ext[0];
+  g->sz = g->ext[0] * g->ext[1];
+  g->np = (int)np;
+  g->d[0] = c->dx;
+  g->d[1] = c->dy;
+  g->d[2] = c->dz;
+  g->x0[0] = c->x0;
+  g->x0[1] = c->y0;
+  g->x0[2] = c->z0;
+  return true;
+}
+
+bool config_ok(const mhd_config* c) {
+  if (!c) return false;
+  if (c->precision != MHD_FP64 && c->precision != MHD_FP32) return false;
+  for (int q = 0; q < 6; ++q)
+    if (c->bc[q] < MHD_BC_PERIODIC || c->bc[q] > MHD_BC_INFLOW) return false;
+  if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0)) return false;
+  if (!isfinite(c->x0) || !isfinite(c->y0) || !isfinite(c->z0)) return false;
+  if (!(c->gamma > 1.0) || !isfinite(c->gamma)) return false;
+  if (!(c->cfl > 0.0) || !(c->cfl <= 1.0)) return false;
+  if (c->recon < MHD_RECON_PAPER || c->recon > MHD_RECON_FIRST) return false;
+  if (!(c->kappa >= -1.0) || !(c->kappa < 1.0)) return false;
+  if (c->source < MHD_SRC_NONE || c->source > MHD_SRC_GAUSS_X) return false;
+  if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0)) return false;
+  for (int q = 0; q < 4; ++q)
+    if (c->reserved[q] != 0) return false;
+  Geo g;
+  return geo_of(c, &g);
+}
+
+Layout layout_of(const mhd_config* c) {
+  Geo g;
+  geo_of(c, &g);
+  const size_t es = c->precision == MHD_FP64 ? sizeof(double) : sizeof(float);
+  Layout L;
+  L.arr = align_up((size_t)g.np * es);
+  L.arr8 = align_up((size_t)g.np);
+  L.off_t = 0;
+  L.off_sg = L.off_t + kNumT * L.arr;
+  L.off_misc = L.off_sg + 3 * L.arr8;
+  L.off_cfl = L.off_misc + align_up(64 * sizeof(double));
+  L.off_diag = L.off_cfl + align_up((size_t)cfl_blocks(g) * sizeof(double));
+  L.total = L.off_diag + align_up((size_t)diag_blocks(g) * 16 * sizeof(double));
+  return L;
+}
+
+// misc block (doubles): [0] dt, [1] t, [2] step (int64), [3..6] counters,
+// [7] status (uint32), [16..31] diag output
+enum { M_DT = 0, M_T = 1, M_STEP = 2, M_CNT = 3, M_STATUS = 7, M_DIAG = 16 };
+
+}  // namespace
+
+struct mhd_ctx {
+  mhd_config cfg;
+  Geo g;
+  Physics ph;
+  hipStream_t st;
+  char* ws;
+  Layout L;
+  bool sticky;
+  // profiling: event i opens the interval of a kernel of class kind[i]; the
+  // interval closes at event i + 1
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+  double prof_ms[16] = {0};
+  int64_t prof_n[16] = {0};
+  void mark(int kind) {
+    if (!prof_on) return;
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        prof_on = false;
+        return;
+      }
+      ev_pool.push_back(e);
+      ev_kind.push_back(0);
+    }
+    ev_kind[ev_used] = kind;
+    hipEventRecord(ev_pool[ev_used], st);
+    ++ev_used;
+  }
+  // fold the recorded intervals into the per-class sums (after a sync)
+  void fold() {
+    for (size_t i = 0; i + 1 < ev_used; ++i) {
+      if (ev_kind[i] < 0) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev_pool[i], ev_pool[i + 1]) == hipSuccess) {
+        prof_ms[ev_kind[i]] += ms;
+        prof_n[ev_kind[i]] += 1;
+      }
+    }
+    ev_used = 0;
+  }
+  ~mhd_ctx() {
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+  }
+  void* arr(int q) const { return ws + L.off_t + (size_t)q * L.arr; }
+  int8_t* sg(int a) const { return (int8_t*)(ws + L.off_sg + (size_t)a * L.arr8); }
+  double* misc() const { return (double*)(ws + L.off_misc); }
+  double* cfl_part() const { return (double*)(ws + L.off_cfl); }
+  double* diag_part() const { return (double*)(ws + L.off_diag); }
+  Counters counters() const {
+    Counters c;
+    unsigned long long* base = (unsigned long long*)(misc() + M_CNT);
+    c.hll = base;
+    c.deg = base + 1;
+    c.floor_hits = base + 2;
+    c.fp64_rec = base + 3;
+    c.status = (unsigned int*)(misc() + M_STATUS);
+    return c;
+  }
+  template <class T>
+  Cons<T> cons(int set) const {  // set 0: U (t^n), 1: U* (half step)
+    Cons<T> s;
+    for (int m = 0; m < 5; ++m) s.u[m] = (T*)arr(8 * set + m);
+    for (int a = 0; a < 3; ++a) s.b[a] = (T*)arr(8 * set + 5 + a);
+    return s;
+  }
+  template <class T>
+  Prim<T> prim() const {
+    Prim<T> w;
+    for (int m = 0; m < 8; ++m) w.w[m] = (T*)arr(16 + m);
+    for (int a = 0; a < 3; ++a) w.ec[a] = (T*)arr(24 + a);
+    return w;
+  }
+  template <class T>
+  Flux<T> flux() const {
+    Flux<T> f;
+    for (int a = 0; a < 3; ++a) {
+      for (int m = 0; m < 7; ++m) f.f[a][m] = (T*)arr(27 + 7 * a + m);
+      f.sg[a] = sg(a);
+    }
+    return f;
+  }
+  template <class T>
+  Edge<T> edge() const {
+    Edge<T> e;
+    for (int a = 0; a < 3; ++a) e.e[a] = (T*)arr(48 + a);
+    return e;
+  }
+};
+
+namespace {
+
+template <class T>
+Muscl<T> muscl_of(int recon, double kappa) {
+  Muscl<T> m;
+  const double K1 = (1.0 - kappa) / 4.0, K2 = (1.0 + kappa) / 4.0;
+  const double b = (3.0 - kappa) / (1.0 - kappa);
+  m.first_order = recon == MHD_RECON_FIRST;
+  if (recon == MHD_RECON_KAPPA) {
+    m.cA = (T)K1;
+    m.bA = (T)b;
+    m.cB = (T)K2;
+    m.bB = (T)b;
+  } else {  // the paper's Eq. 13-14 as printed
+    m.cA = (T)K2;
+    m.bA = (T)1.0;
+    m.cB = (T)K1;
+    m.bB = (T)b;
+  }
+  return m;
+}
+
+Physics physics_of(const mhd_config* c) {
+  Physics ph;
+  ph.gamma = c->gamma;
+  ph.cfl = c->cfl;
+  ph.source = c->source;
+  for (int q = 0; q < 4; ++q) ph.src[q] = c->src[q];
+  ph.rho_floor = c->rho_floor;
+  ph.p_floor = c->p_floor;
+  const double* q = c->inflow;
+  ph.inflow_u[0] = q[0];
+  ph.inflow_u[1] = q[0] * q[1];
+  ph.inflow_u[2] = q[0] * q[2];
+  ph.inflow_u[3] = q[0] * q[3];
+  ph.inflow_u[4] = q[4] / (c->gamma - 1.0) + 0.5 * q[0] * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) +
+                   0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
+  for (int a = 0; a < 3; ++a) ph.inflow_b[a] = q[5 + a];
+  return ph;
+}
+
+int hip_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MHD_OK : MHD_E_HIP;
+}
+
+template <class T>
+void enqueue_step(mhd_ctx* c, DtRef dt) {
+  const Geo& g = c->g;
+  const Counters cnt = c->counters();
+  const Cons<T> U = c->cons<T>(0), Us = c->cons<T>(1);
+  const Prim<T> W = c->prim<T>();
+  const Flux<T> F = c->flux<T>();
+  const Edge<T> E = c->edge<T>();
+  const Muscl<T> first = muscl_of<T>(MHD_RECON_FIRST, c->cfg.kappa);
+  const Muscl<T> second = muscl_of<T>(c->cfg.recon, c->cfg.kappa);
+  // predictor: first-order fluxes of U^n, half step into U*
+  c->mark(MHD_K_PRIM);
+  launch_prim<T>(g, c->ph, U, W, cnt, c->st);
+  for (int a = 0; a < 3; ++a) {
+    c->mark(MHD_K_FLUX_X + a);
+    launch_flux<T>(g, c->ph, a, W, U.b[a], F, first, cnt, c->st);
+  }
+  c->mark(MHD_K_EMF);
+  launch_emf<T>(g, W, F, E, c->st);
+  DtRef half = dt;
+  half.factor = 0.5;
+  c->mark(MHD_K_UPDATE);
+  launch_update<T>(g, c->ph, U, Us, W, F, E, half, cnt, c->st);
+  c->mark(MHD_K_GHOSTS);
+  launch_ghosts<T>(g, c->ph, Us, c->st);
+  // corrector: MUSCL fluxes of U*, full step from U^n
+  c->mark(MHD_K_PRIM);
+  launch_prim<T>(g, c->ph, Us, W, cnt, c->st);
+  for (int a = 0; a < 3; ++a) {
+    c->mark(MHD_K_FLUX_X + a);
+    launch_flux<T>(g, c->ph, a, W, Us.b[a], F, second, cnt, c->st);
+  }
+  c->mark(MHD_K_EMF);
+  launch_emf<T>(g, W, F, E, c->st);
+  c->mark(MHD_K_UPDATE);
+  launch_update<T>(g, c->ph, U, U, W, F, E, dt, cnt, c->st);
+  c->mark(MHD_K_GHOSTS);
+  launch_ghosts<T>(g, c->ph, U, c->st);
+  c->mark(MHD_K_OTHER);
+  launch_advance_time(c->misc() + M_T, (long long*)(c->misc() + M_STEP), dt, c->st);
+  c->mark(-1);
+}
+
+template <class T>
+void enqueue_cfl(mhd_ctx* c) {
+  c->mark(MHD_K_CFL);
+  launch_cfl<T>(c->g, c->ph, c->cons<T>(0), c->cfl_part(), c->misc() + M_DT, c->counters(),
+                c->st);
+  c->mark(-1);
+}
+
+int sync_status(mhd_ctx* c) {
+  unsigned int st = 0;
+  if (hipMemcpyAsync(&st, c->misc() + M_STATUS, sizeof(st), hipMemcpyDeviceToHost, c->st) !=
+      hipSuccess)
+    return MHD_E_HIP;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+  if (st & MHD_ST_BAD_STATE) c->sticky = true;
+  return c->sticky ? MHD_E_STATE : MHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mhd_abi_version(void) { return MHD_ABI_VERSION; }
+
+const char* mhd_strerror(int code) {
+  switch (code) {
+    case MHD_OK: return "ok";
+    case MHD_E_ARG: return "invalid argument or configuration";
+    case MHD_E_HIP: return "HIP runtime error";
+    case MHD_E_STATE: return "invalid state: non-finite value, rho <= 0 or P <= 0";
+    case MHD_E_UNSUPPORTED: return "unsupported configuration";
+    case MHD_E_WS: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+int mhd_workspace_bytes(const mhd_config* cfg, size_t* out) {
+  if (!out || !config_ok(cfg)) return MHD_E_ARG;
+  *out = layout_of(cfg).total;
+  return MHD_OK;
+}
+
+int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_cell5,
+             const void* d_bx, const void* d_by, const void* d_bz, void* hip_stream,
+             mhd_ctx** out) {
+  if (!out || !config_ok(cfg) || !d_cell5 || !d_bx || !d_by || !d_bz) return MHD_E_ARG;
+  *out = nullptr;
+  const Layout L = layout_of(cfg);
+  if (!d_ws || ws_bytes < L.total || ((uintptr_t)d_ws % kAlign) != 0) return MHD_E_WS;
+  mhd_ctx* c = new (std::nothrow) mhd_ctx();
+  if (!c) return MHD_E_HIP;
+  c->cfg = *cfg;
+  geo_of(cfg, &c->g);
+  c->ph = physics_of(cfg);
+  c->st = (hipStream_t)hip_stream;
+  c->ws = (char*)d_ws;
+  c->L = L;
+  c->sticky = false;
+  if (hipMemsetAsync(c->misc(), 0, 64 * sizeof(double), c->st) != hipSuccess) {
+    delete c;
+    return MHD_E_HIP;
+  }
+  if (cfg->precision == MHD_FP64) {
+    launch_scatter<double>(c->g, (const double*)d_cell5, (const double*)d_bx,
+                           (const double*)d_by, (const double*)d_bz, c->cons<double>(0), c->st);
+    launch_ghosts<double>(c->g, c->ph, c->cons<double>(0), c->st);
+    enqueue_cfl<double>(c);
+  } else {
+    launch_scatter<float>(c->g, (const float*)d_cell5, (const float*)d_bx, (const float*)d_by,
+                          (const float*)d_bz, c->cons<float>(0), c->st);
+    launch_ghosts<float>(c->g, c->ph, c->cons<float>(0), c->st);
+    enqueue_cfl<float>(c);
+  }
+  int rc = hip_status();
+  if (rc == MHD_OK) rc = sync_status(c);
+  if (rc != MHD_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return MHD_OK;
+}
+
+int mhd_step(mhd_ctx* c, const double* dt_host, int nsteps) {
+  if (!c || nsteps < 0) return MHD_E_ARG;
+  if (c->sticky) return MHD_E_STATE;
+  if (dt_host)
+    for (int s = 0; s < nsteps; ++s)
+      if (!(dt_host[s] > 0.0) || !isfinite(dt_host[s])) return MHD_E_ARG;
+  for (int s = 0; s < nsteps; ++s) {
+    DtRef dt;
+    dt.factor = 1.0;
+    if (dt_host) {
+      dt.value = dt_host[s];
+      dt.ptr = nullptr;
+    } else {
+      dt.value = 0.0;
+      dt.ptr = c->misc() + M_DT;
+    }
+    if (c->cfg.precision == MHD_FP64) {
+      if (!dt_host) enqueue_cfl<double>(c);
+      enqueue_step<double>(c, dt);
+    } else {
+      if (!dt_host) enqueue_cfl<float>(c);
+      enqueue_step<float>(c, dt);
+    }
+  }
+  return hip_status();
+}
+
+int mhd_dt(mhd_ctx* c, double* out) {
+  if (!c || !out) return MHD_E_ARG;
+  if (c->cfg.precision == MHD_FP64)
+    enqueue_cfl<double>(c);
+  else
+    enqueue_cfl<float>(c);
+  if (hip_status() != MHD_OK) return MHD_E_HIP;
+  if (hipMemcpyAsync(out, c->misc() + M_DT, sizeof(double), hipMemcpyDeviceToHost, c->st) !=
+      hipSuccess)
+    return MHD_E_HIP;
+  return sync_status(c);
+}
+
+int mhd_diag(mhd_ctx* c, mhd_diag_t* out) {
+  if (!c || !out) return MHD_E_ARG;
+  memset(out, 0, sizeof(*out));
+  if (c->cfg.precision == MHD_FP64) {
+    enqueue_cfl<double>(c);
+    launch_diag<double>(c->g, c->ph, c->cons<double>(0), c->diag_part(), c->misc() + M_DIAG,
+                        c->st);
+  } else {
+    enqueue_cfl<float>(c);
+    launch_diag<float>(c->g, c->ph, c->cons<float>(0), c->diag_part(), c->misc() + M_DIAG, c->st);
+  }
+  if (hip_status() != MHD_OK) return MHD_E_HIP;
+  double m[32];
+  if (hipMemcpyAsync(m, c->misc(), sizeof(m), hipMemcpyDeviceToHost, c->st) != hipSuccess)
+    return MHD_E_HIP;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+  const double* d = m + M_DIAG;
+  const unsigned long long* cn = (const unsigned long long*)(m + M_CNT);
+  out->dt = m[M_DT];
+  out->t = m[M_T];
+  memcpy(&out->step, &m[M_STEP], sizeof(int64_t));
+  out->mass = d[0];
+  for (int a = 0; a < 3; ++a) out->mom[a] = d[1 + a];
+  out->energy = d[4];
+  for (int a = 0; a < 3; ++a) out->bsum[a] = d[5 + a];
+  const double h = fmin(c->g.d[0], fmin(c->g.d[1], c->g.d[2]));
+  out->divb_max = d[11] > 0.0 ? d[8] * h / d[11] : d[8] * h;
+  out->rho_min = d[9];
+  out->p_min = d[10];
+  out->n_hll_fallback = (int64_t)cn[0];
+  out->n_degenerate = (int64_t)cn[1];
+  out->n_floor = (int64_t)cn[2];
+  out->n_fp64_recovery = (int64_t)cn[3];
+  unsigned int st;
+  memcpy(&st, &m[M_STATUS], sizeof(st));
+  out->status = st;
+  if (st & MHD_ST_BAD_STATE) c->sticky = true;
+  return c->sticky ? MHD_E_STATE : MHD_OK;
+}
+
+int mhd_get_state(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz) {
+  if (!c || !d_cell5 || !d_bx || !d_by || !d_bz) return MHD_E_ARG;
+  if (c->cfg.precision == MHD_FP64)
+    launch_gather<double>(c->g, c->cons<double>(0), (double*)d_cell5, (double*)d_bx,
+                          (double*)d_by, (double*)d_bz, c->st);
+  else
+    launch_gather<float>(c->g, c->cons<float>(0), (float*)d_cell5, (float*)d_bx, (float*)d_by,
+                         (float*)d_bz, c->st);
+  if (hip_status() != MHD_OK) return MHD_E_HIP;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+  return MHD_OK;
+}
+
+int mhd_debug_array(mhd_ctx* c, int what, void* d_out, size_t* n_out) {
+  if (!c || !d_out || what < 0 || what > 34) return MHD_E_ARG;
+  int q;
+  if (what < 21)
+    q = 27 + what;  // fluxes
+  else if (what < 24)
+    q = 48 + (what - 21);  // edges
+  else if (what < 27)
+    q = 24 + (what - 24);  // cell EMF
+  else
+    q = 16 + (what - 27);  // primitives
+  const size_t es = c->cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
+  if (hipMemcpyAsync(d_out, c->arr(q), (size_t)c->g.np * es, hipMemcpyDeviceToDevice, c->st) !=
+      hipSuccess)
+    return MHD_E_HIP;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+  if (n_out) *n_out = (size_t)c->g.np;
+  return MHD_OK;
+}
+
+int mhd_profile(mhd_ctx* c, int enable) {
+  if (!c) return MHD_E_ARG;
+  if (c->prof_on && hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+  c->ev_used = 0;
+  for (int q = 0; q < 16; ++q) {
+    c->prof_ms[q] = 0.0;
+    c->prof_n[q] = 0;
+  }
+  c->prof_on = enable != 0;
+  return MHD_OK;
+}
+
+int mhd_profile_get(mhd_ctx* c, mhd_profile_t* out) {
+  if (!c || !out) return MHD_E_ARG;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+  c->fold();
+  memset(out, 0, sizeof(*out));
+  for (int q = 0; q < 16; ++q) {
+    out->ms[q] = c->prof_ms[q];
+    out->launches[q] = c->prof_n[q];
+  }
+  out->n_kinds = MHD_K_COUNT;
+  return MHD_OK;
+}
+
+int mhd_destroy(mhd_ctx* c) {
+  if (!c) return MHD_E_ARG;
+  delete c;
+  return MHD_OK;
+}
+
+int mhd_hlld_batch(int precision, int64_t n, const void* d_wl, const void* d_wr, const void* d_bn,
+                   double gamma, void* d_flux, int8_t* d_code, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!d_wl || !d_wr || !d_bn || !d_flux)) || !(gamma > 1.0))
+    return MHD_E_ARG;
+  if (n > (1ll << 31) * 256ll) return MHD_E_ARG;
+  if (precision != MHD_FP64 && precision != MHD_FP32) return MHD_E_ARG;
+  if (n == 0) return MHD_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (precision == MHD_FP64)
+    launch_hlld_batch<double>(n, (const double*)d_wl, (const double*)d_wr, (const double*)d_bn,
+                              gamma, (double*)d_flux, d_code, st);
+  else if (precision == MHD_FP32)
+    launch_hlld_batch<float>(n, (const float*)d_wl, (const float*)d_wr, (const float*)d_bn,
+                             (float)gamma, (float*)d_flux, d_code, st);
+  else
+    return MHD_E_ARG;
+  return hip_status();
+}
+
+int mhd_recon_batch(int precision, int64_t n, const void* d_w4, int recon, double kappa,
+                    void* d_wl, void* d_wr, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!d_w4 || !d_wl || !d_wr))) return MHD_E_ARG;
+  if (recon < MHD_RECON_PAPER || recon > MHD_RECON_FIRST || !(kappa >= -1.0) || !(kappa < 1.0))
+    return MHD_E_ARG;
+  if (n > (1ll << 31) * 256ll) return MHD_E_ARG;
+  if (precision != MHD_FP64 && precision != MHD_FP32) return MHD_E_ARG;
+  if (n == 0) return MHD_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (precision == MHD_FP64)
+    launch_recon_batch<double>(n, (const double*)d_w4, muscl_of<double>(recon, kappa),
+                               (double*)d_wl, (double*)d_wr, st);
+  else if (precision == MHD_FP32)
+    launch_recon_batch<float>(n, (const float*)d_w4, muscl_of<float>(recon, kappa),
+                              (float*)d_wl, (float*)d_wr, st);
+  else
+    return MHD_E_ARG;
+  return hip_status();
+}
+
+}  // extern "C"

@@ -1,0 +1,764 @@
+// mhd_kernels.hip -- HIP kernels (gfx950, wave64) of the ideal-MHD
+// TVD-MUSCL step with constrained transport (section 2.1 of the paper).
+//
+// Structure-of-arrays padded grid (see Geo).  Each kernel maps x to the 64
+// lanes of a wave so every global access of a wave is a contiguous x-run.
+#include <float.h>
+#include <math.h>
+
+#include "mhd_kernels.hpp"
+
+namespace mhd {
+
+constexpr int BX = 64;  // block x extent = one wavefront
+constexpr int BY = 4;   // waves per block
+
+__device__ __forceinline__ int pidx(const Geo& g, int i, int j, int k) {
+  return (i + NG) + g.sy * (j + NG) + g.sz * (k + NG);
+}
+
+__device__ __forceinline__ int stride_of(const Geo& g, int a) {
+  return a == 0 ? 1 : (a == 1 ? g.sy : g.sz);
+}
+
+// Frame component of axis a that holds global conserved component m
+// (0 rho, 1..3 momentum, 4 energy).
+__device__ __forceinline__ int frame_comp(int a, int m) {
+  if (m == 0 || m == 4) return m;
+  const int d = m - 1;
+  return d == a ? 1 : (d == (a + 1) % 3 ? 2 : 3);
+}
+
+static dim3 grid_for(int nx, int ny, int nz) {
+  return dim3((unsigned)((nx + BX - 1) / BX), (unsigned)((ny + BY - 1) / BY), (unsigned)nz);
+}
+
+// Count lanes with `flag` set into *ctr with one atomic per wave.  Must be
+// reached by every lane of the wave.
+__device__ __forceinline__ void wave_count(bool flag, unsigned long long* ctr) {
+  const unsigned long long m = __ballot(flag);
+  if (m != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(1)) - 1))
+    atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
+// ------------------------------------------------------------------------
+// Ghost fill.  Every ghost point takes the value of the interior point found
+// by mapping each coordinate on its own (periodic wrap / outflow clamp), or
+// the inflow state if any coordinate lies in an inflow ghost zone.  This is
+// the result of filling x, then y, then z over the full extended ranges.
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ int map_axis(int c, int m, int n, int bclo, int bchi, bool& inflow) {
+  if (c >= 0 && c < m) return c;
+  const int bc = c < 0 ? bclo : bchi;
+  if (bc == 0) {
+    int r = c % n;
+    return r < 0 ? r + n : r;
+  }
+  if (bc == 1) return c < 0 ? 0 : m - 1;
+  inflow = true;
+  return c;
+}
+
+template <class T>
+__global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long E0 = g.ext[0], E1 = g.ext[1], E2 = g.ext[2];
+  const long long nx5 = 5 * E1 * E2, ny5 = 5 * E0 * E2, nz5 = 5 * E0 * E1;
+  int c[3];
+  long long r;
+  if (t < nx5) {
+    const int l = (int)(t % 5);
+    r = t / 5;
+    c[0] = l < 2 ? l - 2 : g.n[0] + (l - 2);
+    c[1] = (int)(r % E1) - NG;
+    c[2] = (int)(r / E1) - NG;
+  } else if (t < nx5 + ny5) {
+    r = t - nx5;
+    const int l = (int)(r % 5);
+    r /= 5;
+    c[1] = l < 2 ? l - 2 : g.n[1] + (l - 2);
+    c[0] = (int)(r % E0) - NG;
+    c[2] = (int)(r / E0) - NG;
+  } else if (t < nx5 + ny5 + nz5) {
+    r = t - nx5 - ny5;
+    const int l = (int)(r % 5);
+    r /= 5;
+    c[2] = l < 2 ? l - 2 : g.n[2] + (l - 2);
+    c[0] = (int)(r % E0) - NG;
+    c[1] = (int)(r / E0) - NG;
+  } else {
+    return;
+  }
+  const int p = pidx(g, c[0], c[1], c[2]);
+  // cell arrays
+  {
+    bool inflow = false;
+    int m[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      m[a] = map_axis(c[a], g.n[a], g.n[a], g.bc[2 * a], g.bc[2 * a + 1], inflow);
+    if (inflow) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) s.u[q][p] = (T)ph.inflow_u[q];
+    } else if (m[0] != c[0] || m[1] != c[1] || m[2] != c[2]) {
+      const int q0 = pidx(g, m[0], m[1], m[2]);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) s.u[q][p] = s.u[q][q0];
+    }
+  }
+  // face arrays: the normal axis has nf interior entries
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    bool inflow = false;
+    int m[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      m[a] = map_axis(c[a], a == f ? g.nf[a] : g.n[a], g.n[a], g.bc[2 * a], g.bc[2 * a + 1],
+                      inflow);
+    if (inflow)
+      s.b[f][p] = (T)ph.inflow_b[f];
+    else if (m[0] != c[0] || m[1] != c[1] || m[2] != c[2])
+      s.b[f][p] = s.b[f][pidx(g, m[0], m[1], m[2])];
+  }
+}
+
+template <class T>
+void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, hipStream_t st) {
+  const long long tot = 5ll * ((long long)g.ext[1] * g.ext[2] + (long long)g.ext[0] * g.ext[2] +
+                               (long long)g.ext[0] * g.ext[1]);
+  const int bs = 256;
+  hipLaunchKernelGGL(k_ghosts<T>, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, st, g, ph,
+                     s);
+}
+
+// ------------------------------------------------------------------------
+// Primitive recovery (Eq. 6 cell-centred B, P from Eq. 3) and cell EMF
+// E = -v x B (Eq. 9) on all cells that have both faces: [-NG, n+NG-1]^3.
+// FP32: cells that lose more than 6 bits in E - KE - ME (E/(E-KE-ME) > 64)
+// redo KE, ME and P in FP64 from the stored FP32 values.
+// ------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ T pressure(T gam, T rho, T mx, T my, T mz, T E, T b0x, T b1x, T b0y,
+                                      T b1y, T b0z, T b1z, T& bcx, T& bcy, T& bcz, bool& rec) {
+  bcx = T(0.5) * (b0x + b1x);
+  bcy = T(0.5) * (b0y + b1y);
+  bcz = T(0.5) * (b0z + b1z);
+  const T ke = T(0.5) * (mx * mx + my * my + mz * mz) / rho;
+  const T me = T(0.5) * (bcx * bcx + bcy * bcy + bcz * bcz);
+  const T eint = E - ke - me;
+  rec = false;
+  if constexpr (sizeof(T) == 4) {
+    if (!(T(64) * eint > E)) {
+      const double bx = 0.5 * ((double)b0x + (double)b1x);
+      const double by = 0.5 * ((double)b0y + (double)b1y);
+      const double bz = 0.5 * ((double)b0z + (double)b1z);
+      const double ked = 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / (double)rho;
+      const double med = 0.5 * (bx * bx + by * by + bz * bz);
+      rec = true;
+      return (T)(((double)gam - 1.0) * ((double)E - ked - med));
+    }
+  }
+  return (gam - T(1)) * eint;
+}
+
+template <class T>
+__global__ void __launch_bounds__(BX* BY) k_prim(Geo g, Physics ph, Cons<T> s, Prim<T> w,
+                                                 Counters cnt) {
+  const int i = blockIdx.x * BX + threadIdx.x - NG;
+  const int j = blockIdx.y * BY + threadIdx.y - NG;
+  const int k = blockIdx.z - NG;
+  const bool valid = i <= g.n[0] + NG - 1 && j <= g.n[1] + NG - 1;
+  bool rec = false;
+  if (valid) {
+    const int p = pidx(g, i, j, k);
+    const T gam = (T)ph.gamma;
+    const T rho = s.u[0][p], mx = s.u[1][p], my = s.u[2][p], mz = s.u[3][p], E = s.u[4][p];
+    T bcx, bcy, bcz;
+    const T P = pressure(gam, rho, mx, my, mz, E, s.b[0][p], s.b[0][p + 1], s.b[1][p],
+                         s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz], bcx, bcy, bcz, rec);
+    const T vx = mx / rho, vy = my / rho, vz = mz / rho;
+    w.w[0][p] = rho;
+    w.w[1][p] = vx;
+    w.w[2][p] = vy;
+    w.w[3][p] = vz;
+    w.w[4][p] = P;
+    w.w[5][p] = bcx;
+    w.w[6][p] = bcy;
+    w.w[7][p] = bcz;
+    w.ec[0][p] = vz * bcy - vy * bcz;
+    w.ec[1][p] = vx * bcz - vz * bcx;
+    w.ec[2][p] = vy * bcx - vx * bcy;
+  }
+  if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);
+}
+
+template <class T>
+void launch_prim(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_prim<T>, grid_for(g.n[0] + 2 * NG, g.n[1] + 2 * NG, g.n[2] + 2 * NG),
+                     dim3(BX, BY), 0, st, g, ph, s, w, c);
+}
+
+// ------------------------------------------------------------------------
+// Flux sweep along axis A: faces 0..n_A along A, rows -1..n across (the
+// boundary edges' EMFs need one ghost row of transverse fluxes).
+// ------------------------------------------------------------------------
+
+template <class T, int A>
+__global__ void __launch_bounds__(BX* BY) k_flux(Geo g, Physics ph, Prim<T> w,
+                                                 const T* __restrict__ bn, Flux<T> f,
+                                                 Muscl<T> mu, Counters cnt) {
+  constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
+  const int i = blockIdx.x * BX + threadIdx.x + (A == 0 ? 0 : -1);
+  const int j = blockIdx.y * BY + threadIdx.y + (A == 1 ? 0 : -1);
+  const int k = blockIdx.z + (A == 2 ? 0 : -1);
+  const bool valid = i <= g.n[0] && j <= g.n[1];
+  int code = 0;
+  if (valid) {
+    const int p = pidx(g, i, j, k);
+    const int s = stride_of(g, A);
+    const T* __restrict__ src[7] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2],
+                                    w.w[4], w.w[5 + A1], w.w[5 + A2]};
+    T l[7], r[7];
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      const T* q = src[v];
+      muscl_lr(mu, q[p - 2 * s], q[p - s], q[p], q[p + s], l[v], r[v]);
+    }
+    const Face<T> L{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
+    const Face<T> R{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+    T F[7];
+    code = hlld(L, R, bn[p], (T)ph.gamma, F);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f.f[A][m][p] = F[m];
+    f.sg[A][p] = (int8_t)(F[0] > T(0) ? 1 : (F[0] < T(0) ? -1 : 0));
+  }
+  wave_count((code & 1) != 0, cnt.hll);
+  wave_count((code & 2) != 0, cnt.deg);
+}
+
+template <class T>
+void launch_flux(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
+                 Muscl<T> m, Counters c, hipStream_t st) {
+  int r[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
+  r[axis] = g.n[axis] + 1;
+  const dim3 gr = grid_for(r[0], r[1], r[2]);
+  if (axis == 0)
+    hipLaunchKernelGGL((k_flux<T, 0>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
+  else if (axis == 1)
+    hipLaunchKernelGGL((k_flux<T, 1>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
+  else
+    hipLaunchKernelGGL((k_flux<T, 2>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
+}
+
+// ------------------------------------------------------------------------
+// Corner EMF (Eq. 10 with the derivative correction taken as the 3/4-point
+// minus the 1/4-point value, the four faces touching the edge, and Eq. 11
+// upwinding by the sign of the Riemann mass flux).  Edge component c is
+// staggered along a = c+1 and b = c+2 (cyclic); edge index p sits at
+// p - e_a/2 - e_b/2.  Face EMFs: at an a-face E_c = -F_a[B_b], at a b-face
+// E_c = +F_b[B_a].
+// ------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ T upwind(int8_t sgn, T from_low, T from_high) {
+  return sgn > 0 ? from_low : (sgn < 0 ? from_high : T(0.5) * (from_low + from_high));
+}
+
+template <class T, int C>
+__device__ __forceinline__ void corner(const Geo& g, const Prim<T>& w, const Flux<T>& f,
+                                       const Edge<T>& e, int p) {
+  constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
+  const int sa = stride_of(g, A), sb = stride_of(g, B);
+  const T* __restrict__ fa = f.f[A][5];  // B_b flux at a-faces (t1 of the a-frame)
+  const T* __restrict__ fb = f.f[B][6];  // B_a flux at b-faces (t2 of the b-frame)
+  const int8_t* __restrict__ ga = f.sg[A];
+  const int8_t* __restrict__ gb = f.sg[B];
+  const T* __restrict__ cc = w.ec[C];
+  const T X0 = -fa[p], X1 = -fa[p - sb];
+  const T Y0 = fb[p], Y1 = fb[p - sa];
+  const T c00 = cc[p - sa - sb], c10 = cc[p - sb], c01 = cc[p - sa], c11 = cc[p];
+  const T db1 = upwind(ga[p], c01 - Y1, c11 - Y0);
+  const T db3 = upwind(ga[p - sb], Y1 - c00, Y0 - c10);
+  const T da1 = upwind(gb[p], c10 - X1, c11 - X0);
+  const T da3 = upwind(gb[p - sa], X1 - c00, X0 - c01);
+  e.e[C][p] = T(0.25) * (X0 + X1 + Y0 + Y1) + T(0.25) * (db3 - db1) + T(0.25) * (da3 - da1);
+}
+
+template <class T>
+__global__ void __launch_bounds__(BX* BY) k_emf(Geo g, Prim<T> w, Flux<T> f, Edge<T> e) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i > g.n[0] || j > g.n[1]) return;
+  const int p = pidx(g, i, j, k);
+  if (i < g.n[0]) corner<T, 0>(g, w, f, e, p);
+  if (j < g.n[1]) corner<T, 1>(g, w, f, e, p);
+  if (k < g.n[2]) corner<T, 2>(g, w, f, e, p);
+}
+
+template <class T>
+void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st) {
+  hipLaunchKernelGGL(k_emf<T>, grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1), dim3(BX, BY), 0, st,
+                     g, w, f, e);
+}
+
+// ------------------------------------------------------------------------
+// Conservative update (Eq. 7, plus dt S at cell centres) and CT induction
+// update (Eq. 8: dB_a/dt = -(dE_c/db - dE_b/dc), (a,b,c) cyclic).
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ void grad_phi(const Physics& ph, double x, double y, double z,
+                                         double gp[3]) {
+  gp[0] = gp[1] = gp[2] = 0.0;
+  if (ph.source == 1) {
+    const double v0 = ph.src[0], rc = ph.src[1], q = ph.src[2];
+    const double den = rc * rc + x * x + y * y + z * z / (q * q);
+    gp[0] = v0 * v0 * x / den;
+    gp[1] = v0 * v0 * y / den;
+    gp[2] = v0 * v0 * (z / (q * q)) / den;
+  } else if (ph.source == 2) {
+    gp[0] = ph.src[0];
+    gp[1] = ph.src[1];
+    gp[2] = ph.src[2];
+  } else if (ph.source == 3) {
+    const double A = ph.src[0], wd = ph.src[1];
+    gp[0] = 2.0 * A * x / (wd * wd) * exp(-(x / wd) * (x / wd));
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(BX* BY) k_update(Geo g, Physics ph, Cons<T> s0, Cons<T> s1,
+                                                   Prim<T> w, Flux<T> f, Edge<T> e, DtRef dtr,
+                                                   Counters cnt) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  const bool valid = i <= g.n[0] && j <= g.n[1];
+  bool hit = false;
+  if (valid) {
+    const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
+    const int p = pidx(g, i, j, k);
+    const int cc[3] = {i, j, k};
+    const int st[3] = {1, g.sy, g.sz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) {
+        const T rb = (T)(dt / g.d[b]), rc = (T)(dt / g.d[c]);
+        const T* Ec = e.e[c];
+        const T* Eb = e.e[b];
+        s1.b[a][p] = s0.b[a][p] - rb * (Ec[p + st[b]] - Ec[p]) + rc * (Eb[p + st[c]] - Eb[p]);
+      }
+    }
+    if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+      T S[5] = {T(0), T(0), T(0), T(0), T(0)};
+      if (ph.source != 0) {
+        double gp[3];
+        grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
+                 g.x0[2] + (k + 0.5) * g.d[2], gp);
+        const T rho = w.w[0][p];
+        const T gx = (T)gp[0], gy = (T)gp[1], gz = (T)gp[2];
+        S[1] = -rho * gx;
+        S[2] = -rho * gy;
+        S[3] = -rho * gz;
+        S[4] = -rho * (w.w[1][p] * gx + w.w[2][p] * gy + w.w[3][p] * gz);
+      }
+      const T rx = (T)(dt / g.d[0]), ry = (T)(dt / g.d[1]), rz = (T)(dt / g.d[2]);
+      const T dtT = (T)dt;
+      T u[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const T* fx = f.f[0][frame_comp(0, m)];
+        const T* fy = f.f[1][frame_comp(1, m)];
+        const T* fz = f.f[2][frame_comp(2, m)];
+        T v = s0.u[m][p];
+        v -= rx * (fx[p + 1] - fx[p]);
+        v -= ry * (fy[p + g.sy] - fy[p]);
+        v -= rz * (fz[p + g.sz] - fz[p]);
+        v += dtT * S[m];
+        u[m] = v;
+      }
+      if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
+        if (u[0] < (T)ph.rho_floor) {
+          u[0] = (T)ph.rho_floor;
+          hit = true;
+        }
+        // new cell-centred B from the updated faces of this cell
+        T bf[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int b = (a + 1) % 3, c = (a + 2) % 3;
+          const T rb = (T)(dt / g.d[b]), rc = (T)(dt / g.d[c]);
+          const T* Ec = e.e[c];
+          const T* Eb = e.e[b];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int q = p + h * st[a];
+            bf[a][h] = s0.b[a][q] - rb * (Ec[q + st[b]] - Ec[q]) + rc * (Eb[q + st[c]] - Eb[q]);
+          }
+        }
+        T bcx, bcy, bcz;
+        bool rec;
+        const T gam = (T)ph.gamma;
+        const T P = pressure(gam, u[0], u[1], u[2], u[3], u[4], bf[0][0], bf[0][1], bf[1][0],
+                             bf[1][1], bf[2][0], bf[2][1], bcx, bcy, bcz, rec);
+        if (P < (T)ph.p_floor) {
+          u[4] += ((T)ph.p_floor - P) / (gam - T(1));
+          hit = true;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 5; ++m) s1.u[m][p] = u[m];
+    }
+  }
+  wave_count(hit, cnt.floor_hits);
+}
+
+template <class T>
+void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
+                   Flux<T> f, Edge<T> e, DtRef dt, Counters c, hipStream_t st) {
+  hipLaunchKernelGGL(k_update<T>, grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1), dim3(BX, BY), 0,
+                     st, g, ph, s0, s1, w, f, e, dt, c);
+}
+
+// ------------------------------------------------------------------------
+// Block reductions (256 threads = 4 waves of 64): wave shuffles, then the
+// four wave results in fixed order.  Deterministic for a fixed launch.
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------------
+// CFL time step in FP64 (per-direction fast speed of the start-of-step
+// state) and the sticky state check of interior cells.
+// ------------------------------------------------------------------------
+
+template <class T>
+__global__ void __launch_bounds__(BX* BY) k_cfl(Geo g, Physics ph, Cons<T> s, double* part,
+                                                Counters cnt) {
+  __shared__ double red[BY];
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  double r = INFINITY;
+  if (i < g.n[0] && j < g.n[1]) {
+    const int p = pidx(g, i, j, k);
+    const double rho = s.u[0][p];
+    const double mx = s.u[1][p], my = s.u[2][p], mz = s.u[3][p], E = s.u[4][p];
+    const double bc[3] = {0.5 * ((double)s.b[0][p] + (double)s.b[0][p + 1]),
+                          0.5 * ((double)s.b[1][p] + (double)s.b[1][p + g.sy]),
+                          0.5 * ((double)s.b[2][p] + (double)s.b[2][p + g.sz])};
+    const double ke = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+    const double me = 0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
+    const double P = (ph.gamma - 1.0) * (E - ke - me);
+    const double v[3] = {mx / rho, my / rho, mz / rho};
+    const bool ok = rho > 0.0 && P > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
+                    isfinite(mz) && isfinite(bc[0]) && isfinite(bc[1]) && isfinite(bc[2]);
+    if (!ok) atomicOr(cnt.status, 1u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double cf = fast_speed<double>(rho, P, bc[a], bc[(a + 1) % 3], bc[(a + 2) % 3],
+                                           ph.gamma);
+      const double t = g.d[a] / (fabs(v[a]) + cf);
+      r = t < r ? t : r;
+    }
+    if (!ok) r = INFINITY;
+  }
+  r = wave_min(r);
+  if (threadIdx.x == 0) red[threadIdx.y] = r;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    double m = red[0];
+    for (int q = 1; q < BY; ++q) m = fmin(m, red[q]);
+    part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = m;
+  }
+}
+
+__global__ void k_cfl_final(const double* part, int nb, double cfl, double* dt_out) {
+  __shared__ double red[4];
+  double m = INFINITY;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) m = fmin(m, part[q]);
+  m = wave_min(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = fmin(r, red[q]);
+    *dt_out = cfl * r;
+  }
+}
+
+int cfl_blocks(const Geo& g) {
+  const dim3 gr = grid_for(g.n[0], g.n[1], g.n[2]);
+  return (int)(gr.x * gr.y * gr.z);
+}
+
+template <class T>
+void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
+                Counters c, hipStream_t st) {
+  hipLaunchKernelGGL(k_cfl<T>, grid_for(g.n[0], g.n[1], g.n[2]), dim3(BX, BY), 0, st, g, ph, s,
+                     part, c);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, part, cfl_blocks(g), ph.cfl, dt_out);
+}
+
+__global__ void k_advance_time(double* t, long long* step, DtRef dtr) {
+  const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
+  *t += dt;
+  *step += 1;
+}
+
+void launch_advance_time(double* t, long long* step, DtRef dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(1), 0, st, t, step, dt);
+}
+
+// ------------------------------------------------------------------------
+// Diagnostics: FP64 sums of the conserved cell fields and of each face-B
+// component, min rho, min P, max |div_h B| and max |B_face|.  Per-block
+// partials (fixed shuffle order), then one block sums them in fixed order.
+// ------------------------------------------------------------------------
+
+constexpr int kDiagCols = 16;
+
+template <class T>
+__global__ void __launch_bounds__(BX* BY) k_diag(Geo g, Physics ph, Cons<T> s, double* part) {
+  __shared__ double red[kDiagCols][BY];
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  double v[kDiagCols];
+#pragma unroll
+  for (int q = 0; q < kDiagCols; ++q) v[q] = 0.0;
+  v[9] = INFINITY;   // rho min
+  v[10] = INFINITY;  // P min
+  if (i <= g.n[0] && j <= g.n[1]) {
+    const int p = pidx(g, i, j, k);
+    const int cc[3] = {i, j, k};
+    if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) v[m] = (double)s.u[m][p];
+      const double b0[3] = {(double)s.b[0][p], (double)s.b[1][p], (double)s.b[2][p]};
+      const double b1[3] = {(double)s.b[0][p + 1], (double)s.b[1][p + g.sy],
+                            (double)s.b[2][p + g.sz]};
+      double bc[3], div = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bc[a] = 0.5 * (b0[a] + b1[a]);
+        div += (b1[a] - b0[a]) / g.d[a];
+      }
+      const double rho = v[0];
+      const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
+      const double me = 0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
+      v[8] = fabs(div);
+      v[9] = rho;
+      v[10] = (ph.gamma - 1.0) * (v[4] - ke - me);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) {
+        const double x = (double)s.b[a][p];
+        v[5 + a] = x;
+        v[11] = fmax(v[11], fabs(x));
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kDiagCols; ++q) {
+    double x = v[q];
+    if (q == 9 || q == 10)
+      x = wave_min(x);
+    else if (q == 8 || q == 11)
+      x = wave_max(x);
+    else
+      x = wave_sum(x);
+    if (threadIdx.x == 0) red[q][threadIdx.y] = x;
+  }
+  __syncthreads();
+  if (threadIdx.y == 0 && threadIdx.x < kDiagCols) {
+    const int q = threadIdx.x;
+    double x = red[q][0];
+    for (int w = 1; w < BY; ++w) {
+      const double y = red[q][w];
+      if (q == 9 || q == 10)
+        x = fmin(x, y);
+      else if (q == 8 || q == 11)
+        x = fmax(x, y);
+      else
+        x += y;
+    }
+    part[(size_t)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) * kDiagCols +
+         q] = x;
+  }
+}
+
+__global__ void k_diag_final(const double* part, int nb, double dv, double* out) {
+  // one wave per column, 16 waves
+  const int q = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const bool is_min = q == 9 || q == 10;
+  const bool is_max = q == 8 || q == 11;
+  double x = is_min ? INFINITY : 0.0;
+  for (int b = lane; b < nb; b += 64) {
+    const double y = part[(size_t)b * kDiagCols + q];
+    x = is_min ? fmin(x, y) : (is_max ? fmax(x, y) : x + y);
+  }
+  x = is_min ? wave_min(x) : (is_max ? wave_max(x) : wave_sum(x));
+  if (lane == 0) out[q] = (q < 8) ? x * dv : x;
+}
+
+int diag_blocks(const Geo& g) {
+  const dim3 gr = grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1);
+  return (int)(gr.x * gr.y * gr.z);
+}
+
+template <class T>
+void launch_diag(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* out,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_diag<T>, grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1), dim3(BX, BY), 0, st,
+                     g, ph, s, part);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64 * kDiagCols), 0, st, part, diag_blocks(g),
+                     g.d[0] * g.d[1] * g.d[2], out);
+}
+
+// ------------------------------------------------------------------------
+// Interior <-> padded copies.
+// ------------------------------------------------------------------------
+
+template <class T, bool IN>
+__global__ void __launch_bounds__(BX* BY) k_copy(Geo g, T* cell5, T* bx, T* by, T* bz,
+                                                 Cons<T> s) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i > g.n[0] || j > g.n[1]) return;
+  const int p = pidx(g, i, j, k);
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  if (i < nx && j < ny && k < nz) {
+    const size_t ncell = (size_t)nx * ny * nz;
+    const size_t q = ((size_t)k * ny + j) * nx + i;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      if (IN)
+        s.u[m][p] = cell5[m * ncell + q];
+      else
+        cell5[m * ncell + q] = s.u[m][p];
+    }
+  }
+  T* arr[3] = {bx, by, bz};
+  const int cc[3] = {i, j, k};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int e[3] = {nx, ny, nz};
+    e[a] = g.nf[a];
+    if (cc[0] < e[0] && cc[1] < e[1] && cc[2] < e[2]) {
+      const size_t q = ((size_t)k * e[1] + j) * e[0] + i;
+      if (IN)
+        s.b[a][p] = arr[a][q];
+      else
+        arr[a][q] = s.b[a][p];
+    }
+  }
+}
+
+template <class T>
+void launch_scatter(const Geo& g, const T* cell5, const T* bx, const T* by, const T* bz,
+                    Cons<T> s, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy<T, true>), grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1),
+                     dim3(BX, BY), 0, st, g, const_cast<T*>(cell5), const_cast<T*>(bx),
+                     const_cast<T*>(by), const_cast<T*>(bz), s);
+}
+
+template <class T>
+void launch_gather(const Geo& g, Cons<T> s, T* cell5, T* bx, T* by, T* bz, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy<T, false>), grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1),
+                     dim3(BX, BY), 0, st, g, cell5, bx, by, bz, s);
+}
+
+// ------------------------------------------------------------------------
+// Batch entry points for kernel-level parity tests.
+// ------------------------------------------------------------------------
+
+template <class T>
+__global__ void k_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T gam, T* flux,
+                             int8_t* code) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const T* a = wl + 7 * t;
+  const T* b = wr + 7 * t;
+  const Face<T> L{a[0], a[1], a[2], a[3], a[4], a[5], a[6]};
+  const Face<T> R{b[0], b[1], b[2], b[3], b[4], b[5], b[6]};
+  T F[7];
+  const int c = hlld(L, R, bn[t], gam, F);
+#pragma unroll
+  for (int m = 0; m < 7; ++m) flux[7 * t + m] = F[m];
+  if (code) code[t] = (int8_t)c;
+}
+
+template <class T>
+void launch_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T gam, T* flux,
+                       int8_t* code, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_hlld_batch<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, wl,
+                     wr, bn, gam, flux, code);
+}
+
+template <class T>
+__global__ void k_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const T* w = w4 + 4 * t;
+  muscl_lr(m, w[0], w[1], w[2], w[3], wl[t], wr[t]);
+}
+
+template <class T>
+void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_recon_batch<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                     w4, m, wl, wr);
+}
+
+// ------------------------------------------------------------------------
+// Explicit instantiations.
+// ------------------------------------------------------------------------
+
+#define MHD_INST(T)                                                                              \
+  template void launch_ghosts<T>(const Geo&, const Physics&, Cons<T>, hipStream_t);              \
+  template void launch_prim<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,           \
+                               hipStream_t);                                                     \
+  template void launch_flux<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>, Muscl<T>,  \
+                               Counters, hipStream_t);                                           \
+  template void launch_emf<T>(const Geo&, Prim<T>, Flux<T>, Edge<T>, hipStream_t);              \
+  template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Flux<T>, \
+                                 Edge<T>, DtRef, Counters, hipStream_t);                         \
+  template void launch_cfl<T>(const Geo&, const Physics&, Cons<T>, double*, double*, Counters,   \
+                              hipStream_t);                                                      \
+  template void launch_diag<T>(const Geo&, const Physics&, Cons<T>, double*, double*,           \
+                               hipStream_t);                                                     \
+  template void launch_scatter<T>(const Geo&, const T*, const T*, const T*, const T*, Cons<T>,  \
+                                  hipStream_t);                                                  \
+  template void launch_gather<T>(const Geo&, Cons<T>, T*, T*, T*, T*, hipStream_t);             \
+  template void launch_hlld_batch<T>(int64_t, const T*, const T*, const T*, T, T*, int8_t*,     \
+                                     hipStream_t);                                               \
+  template void launch_recon_batch<T>(int64_t, const T*, Muscl<T>, T*, T*, hipStream_t);
+
+MHD_INST(double)
+MHD_INST(float)
+
+}  // namespace mhd

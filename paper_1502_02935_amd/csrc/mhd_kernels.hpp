@@ -1,0 +1,118 @@
+// mhd_kernels.hpp -- grid description, array bundles and kernel launchers
+// of the ideal-MHD step (section 2.1 of the paper).  The kernels themselves
+// live in mhd_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mhd_physics.hpp"
+
+namespace mhd {
+
+constexpr int NG = 2;  // ghost layers: MUSCL needs cells i-2..i+1 of face i
+
+// Padded grid: every array (cells, faces, edges) has extent n + 2 NG + 1 per
+// axis, x fastest; interior cell (i,j,k) is at (i+NG) + sy (j+NG) + sz (k+NG).
+// Face (i,j,k) of the x-face arrays sits at x_{i-1/2}; edge (i,j,k) of the
+// z-edge arrays at (x_{i-1/2}, y_{j-1/2}, z_k) (cyclically for x and y).
+struct Geo {
+  int n[3];
+  int ext[3];
+  int sy, sz;
+  int np;       // points per padded array
+  int nf[3];    // interior faces along each axis' own normal (n or n+1)
+  int bc[6];
+  double d[3];
+  double x0[3];
+};
+
+template <class T>
+struct Cons {  // conserved state: 5 cell arrays + 3 face arrays
+  T* u[5];
+  T* b[3];
+};
+
+template <class T>
+struct Prim {  // primitives rho, vx, vy, vz, P, Bcx, Bcy, Bcz and cell EMF
+  T* w[8];
+  T* ec[3];
+};
+
+template <class T>
+struct Flux {  // per axis, face frame rho, Mn, Mt1, Mt2, E, Bt1, Bt2
+  T* f[3][7];
+  int8_t* sg[3];  // sign of the mass flux
+};
+
+template <class T>
+struct Edge {
+  T* e[3];
+};
+
+struct Counters {  // device counters (unsigned long long)
+  unsigned long long* hll;
+  unsigned long long* deg;
+  unsigned long long* floor_hits;
+  unsigned long long* fp64_rec;
+  unsigned int* status;
+};
+
+struct Physics {
+  double gamma;
+  double cfl;
+  int source;
+  double src[4];
+  double rho_floor, p_floor;
+  double inflow_u[5];  // conserved ghost state of inflow sides
+  double inflow_b[3];
+};
+
+// Time-step source: a value, or (if ptr != nullptr) a device scalar.
+struct DtRef {
+  double value;
+  const double* ptr;
+  double factor;  // 0.5 for the predictor, 1 for the corrector
+};
+
+template <class T>
+void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, hipStream_t st);
+template <class T>
+void launch_prim(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
+                 hipStream_t st);
+template <class T>
+void launch_flux(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
+                 Muscl<T> m, Counters c, hipStream_t st);
+template <class T>
+void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
+template <class T>
+void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
+                   Flux<T> f, Edge<T> e, DtRef dt, Counters c, hipStream_t st);
+// CFL: per-block minima into part (size cfl_blocks(g)), then dt_out = cfl min.
+int cfl_blocks(const Geo& g);
+template <class T>
+void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
+                Counters c, hipStream_t st);
+void launch_advance_time(double* t, long long* step, DtRef dt, hipStream_t st);
+
+// Diagnostics: writes 14 doubles to out: mass, M(3), E, bsum(3), divb_max,
+// rho_min, p_min, bmax, (2 spare).
+int diag_blocks(const Geo& g);
+template <class T>
+void launch_diag(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* out,
+                 hipStream_t st);
+
+// Interior layout <-> padded layout.
+template <class T>
+void launch_scatter(const Geo& g, const T* cell5, const T* bx, const T* by, const T* bz,
+                    Cons<T> s, hipStream_t st);
+template <class T>
+void launch_gather(const Geo& g, Cons<T> s, T* cell5, T* bx, T* by, T* bz, hipStream_t st);
+
+template <class T>
+void launch_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T gam, T* flux,
+                       int8_t* code, hipStream_t st);
+template <class T>
+void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStream_t st);
+
+}  // namespace mhd

@@ -1,0 +1,199 @@
+// mhd_physics.hpp -- device functions of one face: minmod-limited MUSCL
+// reconstruction (Eq. 12-14) and the HLLD approximate Riemann solver
+// (Miyoshi & Kusano 2005, the MHD solver of section 2.1), templated on the
+// arithmetic type (double, or float for the FP32 bulk path).
+//
+// A face state is given in the face-normal frame (n, t1, t2) with
+// (n, t1, t2) a cyclic permutation of (x, y, z):
+//   w = rho, vn, vt1, vt2, P, Bt1, Bt2   plus the face-normal field Bn.
+// The flux is returned in the same frame: rho, Mn, Mt1, Mt2, E, Bt1, Bt2
+// (the Bn flux is identically zero, Eq. 3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mhd {
+
+// Relative size below which an HLLD star-state denominator is treated as
+// zero (the outer and Alfven waves coincide); same constant in both
+// precisions.
+constexpr double kDegenerate = 1.0e-8;
+
+template <class T>
+struct Face {
+  T d, vn, vt1, vt2, p, bt1, bt2;
+};
+
+// minmod: the argument of smaller magnitude when both share a strict sign,
+// else zero.  Signs are compared, never multiplied (a*b underflows in FP32).
+template <class T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  T lo = a < b ? a : b;
+  T hi = a < b ? b : a;
+  return (a > T(0) && b > T(0)) ? lo : ((a < T(0) && b < T(0)) ? hi : T(0));
+}
+
+// Coefficients of dW = cA mm(dw_back, bA dw_mid) + cB mm(dw_mid, bB dw_back).
+template <class T>
+struct Muscl {
+  T cA, bA, cB, bB;
+  int first_order;
+};
+
+// Left/right interface values at the face between cells 1 and 2 of the
+// stencil w0..w3 (Eq. 12-14).
+template <class T>
+__device__ __forceinline__ void muscl_lr(const Muscl<T>& m, T w0, T w1, T w2, T w3, T& wl,
+                                         T& wr) {
+  if (m.first_order) {
+    wl = w1;
+    wr = w2;
+    return;
+  }
+  const T back = w1 - w0, mid = w2 - w1, fwd = w3 - w2;
+  const T dl = m.cA * minmod(back, m.bA * mid) + m.cB * minmod(mid, m.bB * back);
+  const T dr = m.cA * minmod(fwd, m.bA * mid) + m.cB * minmod(mid, m.bB * fwd);
+  wl = w1 + dl;
+  wr = w2 - dr;
+}
+
+// Fast magnetosonic speed along n; the discriminant is written as
+// (a^2 - b^2)^2 + 4 a^2 bt^2 so it never goes negative by cancellation.
+template <class T>
+__device__ __forceinline__ T fast_speed(T d, T p, T bn, T bt1, T bt2, T gam) {
+  const T a2 = gam * p / d;
+  const T bt2s = (bt1 * bt1 + bt2 * bt2) / d;
+  const T b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) / d;
+  const T q = a2 - b2;
+  return sqrt(T(0.5) * ((a2 + b2) + sqrt(q * q + T(4) * a2 * bt2s)));
+}
+
+// Conserved vector and physical flux (Eq. 3) of a face state.
+template <class T>
+__device__ __forceinline__ void cons_flux(const Face<T>& s, T bn, T gam, T u[7], T f[7]) {
+  const T v2 = s.vn * s.vn + s.vt1 * s.vt1 + s.vt2 * s.vt2;
+  const T b2 = bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2;
+  const T pt = s.p + T(0.5) * b2;
+  const T vb = s.vn * bn + s.vt1 * s.bt1 + s.vt2 * s.bt2;
+  u[0] = s.d;
+  u[1] = s.d * s.vn;
+  u[2] = s.d * s.vt1;
+  u[3] = s.d * s.vt2;
+  u[4] = s.p / (gam - T(1)) + T(0.5) * s.d * v2 + T(0.5) * b2;
+  u[5] = s.bt1;
+  u[6] = s.bt2;
+  f[0] = u[1];
+  f[1] = u[1] * s.vn + pt - bn * bn;
+  f[2] = u[1] * s.vt1 - bn * s.bt1;
+  f[3] = u[1] * s.vt2 - bn * s.bt2;
+  f[4] = (u[4] + pt) * s.vn - vb * bn;
+  f[5] = s.bt1 * s.vn - bn * s.vt1;
+  f[6] = s.bt2 * s.vn - bn * s.vt2;
+}
+
+// Star state of one side: density, transverse v and B, energy, v.B.
+template <class T>
+struct Star {
+  T d, v1, v2, b1, b2, e, vb;
+};
+
+template <class T>
+__device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T SM, T pts,
+                                             int& degenerate) {
+  Star<T> r;
+  const T sv = S - s.vn;
+  const T sm = S - SM;
+  const T pt = s.p + T(0.5) * (bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2);
+  r.d = s.d * sv / sm;
+  const T den = s.d * sv * sm - bn * bn;
+  if (fabs(den) > T(kDegenerate) * pts) {
+    const T kv = bn * (SM - s.vn) / den;
+    const T kb = (s.d * sv * sv - bn * bn) / den;
+    r.v1 = s.vt1 - s.bt1 * kv;
+    r.v2 = s.vt2 - s.bt2 * kv;
+    r.b1 = s.bt1 * kb;
+    r.b2 = s.bt2 * kb;
+  } else {
+    r.v1 = s.vt1;
+    r.v2 = s.vt2;
+    r.b1 = s.bt1;
+    r.b2 = s.bt2;
+    degenerate = 1;
+  }
+  const T vb = s.vn * bn + s.vt1 * s.bt1 + s.vt2 * s.bt2;
+  r.vb = SM * bn + r.v1 * r.b1 + r.v2 * r.b2;
+  r.e = (sv * e - pt * s.vn + pts * SM + bn * (vb - r.vb)) / sm;
+  return r;
+}
+
+// HLLD flux.  Returns bit0 if the HLL flux was used (S_M outside
+// (S_L, S_R)), bit1 if a star state was degenerate.
+template <class T>
+__device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T gam, T f[7]) {
+  T ul[7], fl[7], ur[7], fr[7];
+  cons_flux(L, bn, gam, ul, fl);
+  cons_flux(R, bn, gam, ur, fr);
+  const T cfl = fast_speed(L.d, L.p, bn, L.bt1, L.bt2, gam);
+  const T cfr = fast_speed(R.d, R.p, bn, R.bt1, R.bt2, gam);
+  const T cmax = cfl > cfr ? cfl : cfr;
+  const T SL = (L.vn < R.vn ? L.vn : R.vn) - cmax;
+  const T SR = (L.vn > R.vn ? L.vn : R.vn) + cmax;
+  if (SL > T(0)) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = fl[m];
+    return 0;
+  }
+  if (SR < T(0)) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = fr[m];
+    return 0;
+  }
+  const T ptl = L.p + T(0.5) * (bn * bn + L.bt1 * L.bt1 + L.bt2 * L.bt2);
+  const T ptr = R.p + T(0.5) * (bn * bn + R.bt1 * R.bt1 + R.bt2 * R.bt2);
+  const T al = L.d * (SL - L.vn);
+  const T ar = R.d * (SR - R.vn);
+  const T SM = (ar * R.vn - al * L.vn - ptr + ptl) / (ar - al);
+  const T pts = (ar * ptl - al * ptr + al * ar * (R.vn - L.vn)) / (ar - al);
+  if (!(SL < SM && SM < SR)) {
+    const T inv = T(1) / (SR - SL);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = (SR * fl[m] - SL * fr[m] + SL * SR * (ur[m] - ul[m])) * inv;
+    return 1;
+  }
+  int deg = 0;
+  const Star<T> sl = star_side(L, ul[4], bn, SL, SM, pts, deg);
+  const Star<T> sr = star_side(R, ur[4], bn, SR, SM, pts, deg);
+  const T ql = sqrt(sl.d), qr = sqrt(sr.d);
+  const T SsL = SM - fabs(bn) / ql;
+  const T SsR = SM + fabs(bn) / qr;
+  const bool left = SM >= T(0);
+  const Star<T> s = left ? sl : sr;
+  const T S = left ? SL : SR;
+  // F*_a = F_a + S_a (U*_a - U_a)
+  const T us[7] = {s.d, s.d * SM, s.d * s.v1, s.d * s.v2, s.e, s.b1, s.b2};
+#pragma unroll
+  for (int m = 0; m < 7; ++m) {
+    const T u0 = left ? ul[m] : ur[m];
+    const T f0 = left ? fl[m] : fr[m];
+    f[m] = f0 + S * (us[m] - u0);
+  }
+  const bool inner = left ? (SsL < T(0)) : (SsR < T(0) ? false : true);
+  if (inner) {
+    // double-star state across the rotational discontinuity on this side
+    const T sg = bn > T(0) ? T(1) : (bn < T(0) ? T(-1) : T(0));
+    const T inv = T(1) / (ql + qr);
+    const T v1 = (ql * sl.v1 + qr * sr.v1 + sg * (sr.b1 - sl.b1)) * inv;
+    const T v2 = (ql * sl.v2 + qr * sr.v2 + sg * (sr.b2 - sl.b2)) * inv;
+    const T b1 = (qr * sl.b1 + ql * sr.b1 + sg * ql * qr * (sr.v1 - sl.v1)) * inv;
+    const T b2 = (qr * sl.b2 + ql * sr.b2 + sg * ql * qr * (sr.v2 - sl.v2)) * inv;
+    const T vb = SM * bn + v1 * b1 + v2 * b2;
+    const T ess = left ? (s.e - ql * sg * (s.vb - vb)) : (s.e + qr * sg * (s.vb - vb));
+    const T Ss = left ? SsL : SsR;
+    const T uss[7] = {s.d, s.d * SM, s.d * v1, s.d * v2, ess, b1, b2};
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] += Ss * (uss[m] - us[m]);
+  }
+  return deg ? 2 : 0;
+}
+
+}  // namespace mhd

@@ -1,0 +1,50 @@
+"""Helpers of the GPU parity tests: run the HIP library and the oracle on the
+same seeded input with the same time steps, and compare element by element."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+try:
+    import torch
+    HAVE_GPU = torch.cuda.is_available()
+except Exception:  # pragma: no cover
+    HAVE_GPU = False
+
+needs_gpu = pytest.mark.skipif(not HAVE_GPU, reason="no GPU visible")
+
+
+def gpu_sim(pb, precision=0, recon=0, kappa=1.0 / 3.0, state=None):
+    from paper_1502_02935_amd import Sim, config_from_problem
+    cfg = config_from_problem(pb, precision=precision, recon=recon, kappa=kappa)
+    c5, bx, by, bz = state if state is not None else (pb.cell5, pb.bx, pb.by, pb.bz)
+    return Sim(cfg, c5, bx, by, bz)
+
+
+def host_state(sim):
+    return [t.double().cpu().numpy() for t in sim.get_state()]
+
+
+def rel_err(a, b):
+    """max |a - b| / max |b| (b the reference); absolute if b is all zero."""
+    s = float(np.abs(b).max())
+    d = float(np.abs(a - b).max())
+    return d / s if s > 0 else d
+
+
+FIELDS = ("rho", "Mx", "My", "Mz", "E", "Bx", "By", "Bz")
+
+
+def field_errors(gpu_state, orc_state):
+    c5g, *bg = gpu_state
+    c5o, *bo = orc_state
+    out = {}
+    for m in range(5):
+        out[FIELDS[m]] = rel_err(c5g[m], c5o[m])
+    for a in range(3):
+        out[FIELDS[5 + a]] = rel_err(bg[a], bo[a])
+    return out
+
+
+def l1_rel(a, b):
+    return float(np.abs(a - b).mean() / np.abs(b).mean())

@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every symbol include/mhd.h declares;
+host-side argument checking (no GPU needed: these calls never touch HIP)."""
+import ctypes as C
+
+import pytest
+
+from paper_1502_02935_amd import _lib as L
+from paper_1502_02935_amd.sim import MHDConfig, workspace_bytes
+
+
+def test_library_exports_header_symbols():
+    lib = L.load()
+    syms = L.declared_symbols()
+    assert len(syms) >= 10
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert lib.mhd_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, 7):
+        assert isinstance(L.strerror(code), str) and L.strerror(code)
+
+
+def _cfg(**kw):
+    c = MHDConfig(nx=16, ny=8, nz=4, dx=0.1, dy=0.1, dz=0.1)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_workspace_bytes_valid():
+    n64 = workspace_bytes(_cfg())
+    n32 = workspace_bytes(_cfg(precision=1))
+    assert n64 > n32 > 0
+    assert n64 % 256 == 0
+    # 51 padded arrays of 21 x 13 x 9 points at least
+    assert n64 >= 51 * 21 * 13 * 9 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-3), dict(dx=0.0), dict(dz=-1.0), dict(gamma=1.0), dict(cfl=0.0),
+    dict(cfl=1.5), dict(precision=2), dict(recon=5), dict(kappa=1.0), dict(source=9),
+    dict(rho_floor=-1.0), dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(7, 7, 0, 0, 0, 0)),
+    dict(nx=1 << 21), dict(nx=2048, ny=2048, nz=1024),
+])
+def test_workspace_bytes_rejects(bad):
+    c = _cfg(**bad).to_c()
+    n = C.c_size_t(12345)
+    assert L.load().mhd_workspace_bytes(C.byref(c), C.byref(n)) == L.MHD_E_ARG
+
+
+def test_null_arguments_rejected():
+    lib = L.load()
+    c = _cfg().to_c()
+    assert lib.mhd_workspace_bytes(C.byref(c), None) == L.MHD_E_ARG
+    assert lib.mhd_workspace_bytes(None, None) == L.MHD_E_ARG
+    assert lib.mhd_step(None, None, 1) == L.MHD_E_ARG
+    assert lib.mhd_dt(None, None) == L.MHD_E_ARG
+    assert lib.mhd_diag(None, None) == L.MHD_E_ARG
+    assert lib.mhd_destroy(None) == L.MHD_E_ARG
+    assert lib.mhd_get_state(None, None, None, None, None) == L.MHD_E_ARG
+    ctx = C.c_void_p()
+    assert lib.mhd_init(C.byref(c), None, 0, None, None, None, None, None,
+                        C.byref(ctx)) == L.MHD_E_ARG
+    assert lib.mhd_hlld_batch(0, -1, None, None, None, 1.4, None, None, None) == L.MHD_E_ARG
+    assert lib.mhd_hlld_batch(3, 1, None, None, None, 1.4, None, None, None) == L.MHD_E_ARG
+    assert lib.mhd_recon_batch(0, 1, None, 0, 0.3, None, None, None) == L.MHD_E_ARG
+    # zero-length batches are valid no-ops
+    assert lib.mhd_hlld_batch(0, 0, None, None, None, 1.4, None, None, None) == L.MHD_OK
+    assert lib.mhd_recon_batch(1, 0, None, 0, 0.3, None, None, None) == L.MHD_OK
