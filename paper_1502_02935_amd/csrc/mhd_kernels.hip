@@ -331,13 +331,11 @@ __device__ __forceinline__ void grad_phi(const Physics& ph, double x, double y, 
 
 template <class T>
 __global__ void __launch_bounds__(BX* BY) k_update(Geo g, Physics ph, Cons<T> s0, Cons<T> s1,
-                                                   Prim<T> w, Flux<T> f, Edge<T> e, DtRef dtr,
-                                                   Counters cnt) {
+                                                   Prim<T> w, Flux<T> f, Edge<T> e, DtRef dtr) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z;
   const bool valid = i <= g.n[0] && j <= g.n[1];
-  bool hit = false;
   if (valid) {
     const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
     const int p = pidx(g, i, j, k);
@@ -381,37 +379,40 @@ __global__ void __launch_bounds__(BX* BY) k_update(Geo g, Physics ph, Cons<T> s0
         v += dtT * S[m];
         u[m] = v;
       }
-      if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
-        if (u[0] < (T)ph.rho_floor) {
-          u[0] = (T)ph.rho_floor;
-          hit = true;
-        }
-        // new cell-centred B from the updated faces of this cell
-        T bf[3][2];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int b = (a + 1) % 3, c = (a + 2) % 3;
-          const T rb = (T)(dt / g.d[b]), rc = (T)(dt / g.d[c]);
-          const T* Ec = e.e[c];
-          const T* Eb = e.e[b];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int q = p + h * st[a];
-            bf[a][h] = s0.b[a][q] - rb * (Ec[q + st[b]] - Ec[q]) + rc * (Eb[q + st[c]] - Eb[q]);
-          }
-        }
-        T bcx, bcy, bcz;
-        bool rec;
-        const T gam = (T)ph.gamma;
-        const T P = pressure(gam, u[0], u[1], u[2], u[3], u[4], bf[0][0], bf[0][1], bf[1][0],
-                             bf[1][1], bf[2][0], bf[2][1], bcx, bcy, bcz, rec);
-        if (P < (T)ph.p_floor) {
-          u[4] += ((T)ph.p_floor - P) / (gam - T(1));
-          hit = true;
-        }
-      }
 #pragma unroll
       for (int m = 0; m < 5; ++m) s1.u[m][p] = u[m];
+    }
+  }
+}
+
+// Density and pressure floors on the updated state: rho is raised to
+// rho_floor; then E is raised so that P >= p_floor, with the cell-centred B
+// of the updated faces.  A pass of its own, after every face of the stage
+// has been written.
+template <class T>
+__global__ void __launch_bounds__(BX* BY) k_floors(Geo g, Physics ph, Cons<T> s, Counters cnt) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  bool hit = false;
+  if (i < g.n[0] && j < g.n[1]) {
+    const int p = pidx(g, i, j, k);
+    T rho = s.u[0][p];
+    if (rho < (T)ph.rho_floor) {
+      rho = (T)ph.rho_floor;
+      s.u[0][p] = rho;
+      hit = true;
+    }
+    const T gam = (T)ph.gamma;
+    T bcx, bcy, bcz;
+    bool rec;
+    const T E = s.u[4][p];
+    const T P = pressure(gam, rho, s.u[1][p], s.u[2][p], s.u[3][p], E, s.b[0][p], s.b[0][p + 1],
+                         s.b[1][p], s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz], bcx, bcy, bcz,
+                         rec);
+    if (P < (T)ph.p_floor) {
+      s.u[4][p] = E + ((T)ph.p_floor - P) / (gam - T(1));
+      hit = true;
     }
   }
   wave_count(hit, cnt.floor_hits);
@@ -421,7 +422,10 @@ template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Flux<T> f, Edge<T> e, DtRef dt, Counters c, hipStream_t st) {
   hipLaunchKernelGGL(k_update<T>, grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1), dim3(BX, BY), 0,
-                     st, g, ph, s0, s1, w, f, e, dt, c);
+                     st, g, ph, s0, s1, w, f, e, dt);
+  if (ph.rho_floor > 0.0 || ph.p_floor > 0.0)
+    hipLaunchKernelGGL(k_floors<T>, grid_for(g.n[0], g.n[1], g.n[2]), dim3(BX, BY), 0, st, g, ph,
+                       s1, c);
 }
 
 // ------------------------------------------------------------------------
