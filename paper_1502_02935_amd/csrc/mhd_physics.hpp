@@ -14,10 +14,13 @@
 
 namespace mhd {
 
-// Relative size below which an HLLD star-state denominator is treated as
-// zero (the outer and Alfven waves coincide); same constant in both
-// precisions.
-constexpr double kDegenerate = 1.0e-8;
+// Relative size (to the star total pressure) below which an HLLD star-state
+// denominator rho (S - u)(S - S_M) - Bn^2 is treated as zero: the outer
+// fast-speed estimate meets the star-region Alfven speed and the star
+// transverse v and B formulas diverge (their v*.B* term like 1/den^2, the
+// energy flux like 1/den).  Same constant in both precisions; it sits far
+// above the FP32 rounding level of den.
+constexpr double kDegenerate = 1.0e-3;
 
 template <class T>
 struct Face {
