@@ -43,6 +43,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -163,6 +165,14 @@ def main():
     pb = P.turbulent_ism(n, seed=args.seed).astype("float32")
     cells = pb.ncell
 
+    if args.calib_copy:
+        # a plain copy of known size: 2^28 floats read and written once
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log("FP32 timed run: %d warmup + %d steps" % (args.warmup, args.steps))
     el32, prof32, d32, _ = timed_run(pb, 1, args.steps, args.warmup)
     rate32 = cells * args.steps / el32

@@ -30,7 +30,8 @@ struct Layout {
   size_t arr8;      // bytes per padded int8 array
   size_t off_t;     // T arrays
   size_t off_sg;    // sign arrays
-  size_t off_misc;  // dt, t, step, counters, status, diag_out
+  size_t off_misc;  // dt, t, step, status, diag_out
+  size_t off_cnt;   // event counter slots
   size_t off_cfl;   // cfl partials
   size_t off_diag;  // diag partials
   size_t total;
@@ -92,15 +93,17 @@ Layout layout_of(const mhd_config* c) {
   L.off_t = 0;
   L.off_sg = L.off_t + kNumT * L.arr;
   L.off_misc = L.off_sg + 3 * L.arr8;
-  L.off_cfl = L.off_misc + align_up(64 * sizeof(double));
+  L.off_cnt = L.off_misc + align_up(64 * sizeof(double));
+  L.off_cfl = L.off_cnt + align_up((size_t)kNumCounters * kCounterSlots * kCounterStride *
+                                   sizeof(unsigned long long));
   L.off_diag = L.off_cfl + align_up((size_t)cfl_blocks(g) * sizeof(double));
   L.total = L.off_diag + align_up((size_t)diag_blocks(g) * 16 * sizeof(double));
   return L;
 }
 
-// misc block (doubles): [0] dt, [1] t, [2] step (int64), [3..6] counters,
-// [7] status (uint32), [16..31] diag output
-enum { M_DT = 0, M_T = 1, M_STEP = 2, M_CNT = 3, M_STATUS = 7, M_DIAG = 16 };
+// misc block (doubles): [0] dt, [1] t, [2] step (int64), [7] status
+// (uint32), [16..31] diag output
+enum { M_DT = 0, M_T = 1, M_STEP = 2, M_STATUS = 7, M_DIAG = 16 };
 
 }  // namespace
 
@@ -155,13 +158,15 @@ struct mhd_ctx {
   double* misc() const { return (double*)(ws + L.off_misc); }
   double* cfl_part() const { return (double*)(ws + L.off_cfl); }
   double* diag_part() const { return (double*)(ws + L.off_diag); }
+  unsigned long long* counter_slots() const { return (unsigned long long*)(ws + L.off_cnt); }
   Counters counters() const {
     Counters c;
-    unsigned long long* base = (unsigned long long*)(misc() + M_CNT);
+    unsigned long long* base = counter_slots();
+    const size_t span = (size_t)kCounterSlots * kCounterStride;
     c.hll = base;
-    c.deg = base + 1;
-    c.floor_hits = base + 2;
-    c.fp64_rec = base + 3;
+    c.deg = base + span;
+    c.floor_hits = base + 2 * span;
+    c.fp64_rec = base + 3 * span;
     c.status = (unsigned int*)(misc() + M_STATUS);
     return c;
   }
@@ -343,7 +348,8 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
   c->ws = (char*)d_ws;
   c->L = L;
   c->sticky = false;
-  if (hipMemsetAsync(c->misc(), 0, 64 * sizeof(double), c->st) != hipSuccess) {
+  if (hipMemsetAsync(c->misc(), 0, 64 * sizeof(double), c->st) != hipSuccess ||
+      hipMemsetAsync(c->counter_slots(), 0, L.off_cfl - L.off_cnt, c->st) != hipSuccess) {
     delete c;
     return MHD_E_HIP;
   }
@@ -421,11 +427,17 @@ int mhd_diag(mhd_ctx* c, mhd_diag_t* out) {
   }
   if (hip_status() != MHD_OK) return MHD_E_HIP;
   double m[32];
-  if (hipMemcpyAsync(m, c->misc(), sizeof(m), hipMemcpyDeviceToHost, c->st) != hipSuccess)
+  std::vector<unsigned long long> slots((size_t)kNumCounters * kCounterSlots * kCounterStride);
+  if (hipMemcpyAsync(m, c->misc(), sizeof(m), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+      hipMemcpyAsync(slots.data(), c->counter_slots(), slots.size() * sizeof(unsigned long long),
+                     hipMemcpyDeviceToHost, c->st) != hipSuccess)
     return MHD_E_HIP;
   if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
   const double* d = m + M_DIAG;
-  const unsigned long long* cn = (const unsigned long long*)(m + M_CNT);
+  unsigned long long cn[kNumCounters] = {0, 0, 0, 0};
+  for (int q = 0; q < kNumCounters; ++q)
+    for (int sl = 0; sl < kCounterSlots; ++sl)
+      cn[q] += slots[((size_t)q * kCounterSlots + sl) * kCounterStride];
   out->dt = m[M_DT];
   out->t = m[M_T];
   memcpy(&out->step, &m[M_STEP], sizeof(int64_t));

@@ -33,12 +33,15 @@ static dim3 grid_for(int nx, int ny, int nz) {
   return dim3((unsigned)((nx + BX - 1) / BX), (unsigned)((ny + BY - 1) / BY), (unsigned)nz);
 }
 
-// Count lanes with `flag` set into *ctr with one atomic per wave.  Must be
-// reached by every lane of the wave.
+// Count lanes with `flag` set into the counter's slot of this block, with
+// one atomic per wave.  Must be reached by every lane of the wave.
 __device__ __forceinline__ void wave_count(bool flag, unsigned long long* ctr) {
   const unsigned long long m = __ballot(flag);
-  if (m != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(1)) - 1))
-    atomicAdd(ctr, (unsigned long long)__popcll(m));
+  if (m != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(1)) - 1)) {
+    const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    atomicAdd(ctr + (size_t)(b % kCounterSlots) * kCounterStride,
+              (unsigned long long)__popcll(m));
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -145,7 +148,7 @@ __device__ __forceinline__ T pressure(T gam, T rho, T mx, T my, T mz, T E, T b0x
   bcx = T(0.5) * (b0x + b1x);
   bcy = T(0.5) * (b0y + b1y);
   bcz = T(0.5) * (b0z + b1z);
-  const T ke = T(0.5) * (mx * mx + my * my + mz * mz) / rho;
+  const T ke = T(0.5) * (mx * mx + my * my + mz * mz) * rcp(rho);
   const T me = T(0.5) * (bcx * bcx + bcy * bcy + bcz * bcz);
   const T eint = E - ke - me;
   rec = false;
@@ -178,7 +181,8 @@ __global__ void __launch_bounds__(BX* BY) k_prim(Geo g, Physics ph, Cons<T> s, P
     T bcx, bcy, bcz;
     const T P = pressure(gam, rho, mx, my, mz, E, s.b[0][p], s.b[0][p + 1], s.b[1][p],
                          s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz], bcx, bcy, bcz, rec);
-    const T vx = mx / rho, vy = my / rho, vz = mz / rho;
+    const T ir = rcp(rho);
+    const T vx = mx * ir, vy = my * ir, vz = mz * ir;
     w.w[0][p] = rho;
     w.w[1][p] = vx;
     w.w[2][p] = vy;

@@ -50,7 +50,14 @@ struct Edge {
   T* e[3];
 };
 
-struct Counters {  // device counters (unsigned long long)
+// Event counters.  Each counter is spread over kCounterSlots slots, one
+// 64-byte line apart, and a block adds into slot (block id mod kCounterSlots):
+// a single shared address would serialise every wave's atomic in L2.
+constexpr int kCounterSlots = 256;
+constexpr int kCounterStride = 8;  // unsigned long longs per slot (64 bytes)
+constexpr int kNumCounters = 4;    // hll, degenerate, floor hits, FP64 recoveries
+
+struct Counters {
   unsigned long long* hll;
   unsigned long long* deg;
   unsigned long long* floor_hits;

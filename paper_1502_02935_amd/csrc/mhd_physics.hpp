@@ -8,6 +8,10 @@
 //   w = rho, vn, vt1, vt2, P, Bt1, Bt2   plus the face-normal field Bn.
 // The flux is returned in the same frame: rho, Mn, Mt1, Mt2, E, Bt1, Bt2
 // (the Bn flux is identically zero, Eq. 3).
+//
+// Divisions are grouped so that each denominator is inverted once.  In FP32
+// the reciprocal is the hardware v_rcp_f32 (1 ulp); in FP64 it is the
+// correctly rounded 1/x.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,18 +26,21 @@ namespace mhd {
 // above the FP32 rounding level of den.
 constexpr double kDegenerate = 1.0e-3;
 
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+
 template <class T>
 struct Face {
   T d, vn, vt1, vt2, p, bt1, bt2;
 };
 
-// minmod: the argument of smaller magnitude when both share a strict sign,
-// else zero.  Signs are compared, never multiplied (a*b underflows in FP32).
-template <class T>
-__device__ __forceinline__ T minmod(T a, T b) {
-  T lo = a < b ? a : b;
-  T hi = a < b ? b : a;
-  return (a > T(0) && b > T(0)) ? lo : ((a < T(0) && b < T(0)) ? hi : T(0));
+// minmod(a, b): the argument of smaller magnitude when both share a strict
+// sign, else zero -- which is the median of (a, b, 0).
+__device__ __forceinline__ float minmod(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
+__device__ __forceinline__ double minmod(double a, double b) {
+  return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
 // Coefficients of dW = cA mm(dw_back, bA dw_mid) + cB mm(dw_mid, bB dw_back).
@@ -64,16 +71,18 @@ __device__ __forceinline__ void muscl_lr(const Muscl<T>& m, T w0, T w1, T w2, T 
 // (a^2 - b^2)^2 + 4 a^2 bt^2 so it never goes negative by cancellation.
 template <class T>
 __device__ __forceinline__ T fast_speed(T d, T p, T bn, T bt1, T bt2, T gam) {
-  const T a2 = gam * p / d;
-  const T bt2s = (bt1 * bt1 + bt2 * bt2) / d;
-  const T b2 = (bn * bn + bt1 * bt1 + bt2 * bt2) / d;
+  const T id = rcp(d);
+  const T a2 = gam * p * id;
+  const T bt2s = (bt1 * bt1 + bt2 * bt2) * id;
+  const T b2 = bt2s + bn * bn * id;
   const T q = a2 - b2;
   return sqrt(T(0.5) * ((a2 + b2) + sqrt(q * q + T(4) * a2 * bt2s)));
 }
 
-// Conserved vector and physical flux (Eq. 3) of a face state.
+// Conserved vector and physical flux (Eq. 3) of a face state; igm1 =
+// 1/(gamma - 1).
 template <class T>
-__device__ __forceinline__ void cons_flux(const Face<T>& s, T bn, T gam, T u[7], T f[7]) {
+__device__ __forceinline__ void cons_flux(const Face<T>& s, T bn, T igm1, T u[7], T f[7]) {
   const T v2 = s.vn * s.vn + s.vt1 * s.vt1 + s.vt2 * s.vt2;
   const T b2 = bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2;
   const T pt = s.p + T(0.5) * b2;
@@ -82,7 +91,7 @@ __device__ __forceinline__ void cons_flux(const Face<T>& s, T bn, T gam, T u[7],
   u[1] = s.d * s.vn;
   u[2] = s.d * s.vt1;
   u[3] = s.d * s.vt2;
-  u[4] = s.p / (gam - T(1)) + T(0.5) * s.d * v2 + T(0.5) * b2;
+  u[4] = s.p * igm1 + T(0.5) * s.d * v2 + T(0.5) * b2;
   u[5] = s.bt1;
   u[6] = s.bt2;
   f[0] = u[1];
@@ -105,13 +114,15 @@ __device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T
                                              int& degenerate) {
   Star<T> r;
   const T sv = S - s.vn;
-  const T sm = S - SM;
+  const T ism = rcp(S - SM);
   const T pt = s.p + T(0.5) * (bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2);
-  r.d = s.d * sv / sm;
-  const T den = s.d * sv * sm - bn * bn;
+  const T dsv = s.d * sv;
+  r.d = dsv * ism;
+  const T den = dsv * (S - SM) - bn * bn;
   if (fabs(den) > T(kDegenerate) * pts) {
-    const T kv = bn * (SM - s.vn) / den;
-    const T kb = (s.d * sv * sv - bn * bn) / den;
+    const T iden = rcp(den);
+    const T kv = bn * (SM - s.vn) * iden;
+    const T kb = (dsv * sv - bn * bn) * iden;
     r.v1 = s.vt1 - s.bt1 * kv;
     r.v2 = s.vt2 - s.bt2 * kv;
     r.b1 = s.bt1 * kb;
@@ -125,7 +136,7 @@ __device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T
   }
   const T vb = s.vn * bn + s.vt1 * s.bt1 + s.vt2 * s.bt2;
   r.vb = SM * bn + r.v1 * r.b1 + r.v2 * r.b2;
-  r.e = (sv * e - pt * s.vn + pts * SM + bn * (vb - r.vb)) / sm;
+  r.e = (sv * e - pt * s.vn + pts * SM + bn * (vb - r.vb)) * ism;
   return r;
 }
 
@@ -133,9 +144,10 @@ __device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T
 // (S_L, S_R)), bit1 if a star state was degenerate.
 template <class T>
 __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T gam, T f[7]) {
+  const T igm1 = rcp(gam - T(1));
   T ul[7], fl[7], ur[7], fr[7];
-  cons_flux(L, bn, gam, ul, fl);
-  cons_flux(R, bn, gam, ur, fr);
+  cons_flux(L, bn, igm1, ul, fl);
+  cons_flux(R, bn, igm1, ur, fr);
   const T cfl = fast_speed(L.d, L.p, bn, L.bt1, L.bt2, gam);
   const T cfr = fast_speed(R.d, R.p, bn, R.bt1, R.bt2, gam);
   const T cmax = cfl > cfr ? cfl : cfr;
@@ -155,10 +167,11 @@ __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T 
   const T ptr = R.p + T(0.5) * (bn * bn + R.bt1 * R.bt1 + R.bt2 * R.bt2);
   const T al = L.d * (SL - L.vn);
   const T ar = R.d * (SR - R.vn);
-  const T SM = (ar * R.vn - al * L.vn - ptr + ptl) / (ar - al);
-  const T pts = (ar * ptl - al * ptr + al * ar * (R.vn - L.vn)) / (ar - al);
+  const T ia = rcp(ar - al);
+  const T SM = (ar * R.vn - al * L.vn - ptr + ptl) * ia;
+  const T pts = (ar * ptl - al * ptr + al * ar * (R.vn - L.vn)) * ia;
   if (!(SL < SM && SM < SR)) {
-    const T inv = T(1) / (SR - SL);
+    const T inv = rcp(SR - SL);
 #pragma unroll
     for (int m = 0; m < 7; ++m) f[m] = (SR * fl[m] - SL * fr[m] + SL * SR * (ur[m] - ul[m])) * inv;
     return 1;
@@ -167,8 +180,9 @@ __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T 
   const Star<T> sl = star_side(L, ul[4], bn, SL, SM, pts, deg);
   const Star<T> sr = star_side(R, ur[4], bn, SR, SM, pts, deg);
   const T ql = sqrt(sl.d), qr = sqrt(sr.d);
-  const T SsL = SM - fabs(bn) / ql;
-  const T SsR = SM + fabs(bn) / qr;
+  const T abn = fabs(bn);
+  const T SsL = SM - abn * rcp(ql);
+  const T SsR = SM + abn * rcp(qr);
   const bool left = SM >= T(0);
   const Star<T> s = left ? sl : sr;
   const T S = left ? SL : SR;
@@ -184,7 +198,7 @@ __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T 
   if (inner) {
     // double-star state across the rotational discontinuity on this side
     const T sg = bn > T(0) ? T(1) : (bn < T(0) ? T(-1) : T(0));
-    const T inv = T(1) / (ql + qr);
+    const T inv = rcp(ql + qr);
     const T v1 = (ql * sl.v1 + qr * sr.v1 + sg * (sr.b1 - sl.b1)) * inv;
     const T v2 = (ql * sl.v2 + qr * sr.v2 + sg * (sr.b2 - sl.b2)) * inv;
     const T b1 = (qr * sl.b1 + ql * sr.b1 + sg * ql * qr * (sr.v1 - sl.v1)) * inv;

@@ -60,6 +60,16 @@ def test_minmod_properties():
     assert O.minmod(1e-200, 1e-200) == 1e-200  # sign by comparison, no underflow
 
 
+def test_minmod_is_median_with_zero():
+    """minmod(a, b) equals the median of (a, b, 0): the form the GPU kernels
+    evaluate with one med3 instruction."""
+    rng = np.random.default_rng(4)
+    vals = np.concatenate([rng.normal(size=300), [0.0, -0.0, 1e-300, -1e-300, 5.0, -5.0]])
+    for a in vals[::3]:
+        for b in vals[::5]:
+            assert O.minmod(a, b) == float(np.median([a, b, 0.0]))
+
+
 # ---------------------------------------------------------- Eq. 12-14 -----
 
 def _phi_paper(r):
