@@ -106,12 +106,61 @@ def error_run(pb, nsteps):
                  "fp64_recovery_cell_evals": d32["n_fp64_recovery"]}
 
 
-def flux_kernel_bytes(n, elem):
-    """Algorithmic HBM bytes of one flux-sweep launch: each face reads the 7
-    reconstructed primitive fields once (neighbour reuse is on chip) and its
-    normal B, and writes 7 flux components and a sign byte."""
+# Algorithmic work of one flux-sweep launch.  Faces per launch: n+1 along
+# the sweep, n+2 across (one ghost row each side for the corner EMFs).
+# Bytes per face: the 7 face primitives and the face-normal B read once,
+# 7 flux components and the mass-flux sign byte written once.
+# Flops per face, counted on the FP64 oracle over the turbulent-box face
+# states (oracle/count_flops.py): HLLD 400.6, MUSCL of 7 variables 154.0.
+FLUX_BYTES_PER_FACE_FP32 = 8 * 4 + 7 * 4 + 1
+HLLD_FLOPS_PER_FACE = 400.6
+MUSCL_FLOPS_PER_FACE = 154.0
+# Whole step per cell-update (both stages, every part), same count.
+STEP_FLOPS_PER_CELL_UPDATE = 3162.0
+STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
+# Measured HBM traffic (TCC FETCH_SIZE + WRITE_SIZE, calibration factor
+# 1.000) of the flux sweeps at n = 256, mean over x, y, z, valid only for
+# the kernel sources with this hash.
+PROFILED_FLUX = {"sources_sha256_16": "9dba0f083c75bdce", "n": 256,
+                 "bytes_per_launch": 1316.7e6}
+KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_kernels.hip",
+                  "paper_1502_02935_amd/csrc/mhd_physics.hpp",
+                  "paper_1502_02935_amd/csrc/mhd_kernels.hpp")
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def flux_roofline(n, prof):
+    """Roofline of the flux sweeps (the dominant kernel class): their mean
+    launch time from HIP events over the timed region, algorithmic bytes and
+    flops per launch.  Arithmetic intensity is 6.6 (first order) to 9.1
+    (MUSCL) flop/byte, below the FP32 ridge of 157.3/8 = 19.7: HBM bound."""
+    launches = [prof[k] for k in ("flux_x", "flux_y", "flux_z") if prof.get(k, (0, 0))[1]]
+    tot_ms = sum(v[0] for v in launches)
+    nl = sum(v[1] for v in launches)
+    ms = tot_ms / nl
     faces = (n + 1) * (n + 2) * (n + 2)
-    return faces * (8 * elem + 7 * elem + 1)
+    byts = faces * FLUX_BYTES_PER_FACE_FP32
+    flops = faces * (HLLD_FLOPS_PER_FACE + 0.5 * MUSCL_FLOPS_PER_FACE)  # mean of both stages
+    ach = byts / (ms * 1e-3) / 1e9
+    traffic = None
+    if kernel_sources_hash() == PROFILED_FLUX["sources_sha256_16"] and n == PROFILED_FLUX["n"]:
+        traffic = PROFILED_FLUX["bytes_per_launch"]
+    return {"kernel": "k_flux (x, y, z sweeps; first-order and MUSCL + HLLD)", "bound": "hbm",
+            "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+            "traffic": traffic, "ms_per_launch": ms, "bytes_per_launch": byts,
+            "faces_per_launch": faces,
+            "alu_view": {"flops_per_launch": flops,
+                         "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                         "peak_tflops": PEAK_FP32_TFLOPS,
+                         "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}}
 
 
 def cpu_baseline(pb, seconds):
@@ -201,18 +250,15 @@ def main():
     kern = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1], "share": v[0] / sum(
         x[0] for x in prof32.values())} for k, v in prof32.items() if v[1]}
     result["kernel_profile_fp32"] = kern
-    # dominant kernel class
-    flux = {k: v for k, v in kern.items() if k.startswith("flux")}
-    fx = flux.get("flux_x")
-    if fx:
-        ms = sum(v["ms_per_launch"] * v["launches"] for v in flux.values()) / sum(
-            v["launches"] for v in flux.values())
-        byts = flux_kernel_bytes(n, 4)
-        ach = byts / (ms * 1e-3) / 1e9
-        result["roofline"] = {"kernel": "k_flux (MUSCL/first-order + HLLD sweep)", "bound": "hbm",
-                              "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                              "frac": ach / PEAK_HBM_GBS, "traffic": None,
-                              "ms_per_launch": ms, "bytes_per_launch": byts}
+    result["roofline"] = flux_roofline(n, prof32)
+    # the whole path: arithmetic intensity 3162 flop / 64 B = 49 flop/byte
+    result["path_roofline"] = {
+        "bound": "alu", "flops_per_cell_update": STEP_FLOPS_PER_CELL_UPDATE,
+        "achieved_tflops": rate32 * STEP_FLOPS_PER_CELL_UPDATE / 1e12,
+        "peak_tflops": PEAK_FP32_TFLOPS,
+        "frac": rate32 * STEP_FLOPS_PER_CELL_UPDATE / 1e12 / PEAK_FP32_TFLOPS,
+        "bound_cell_updates_per_s": PEAK_FP32_TFLOPS * 1e12 / STEP_FLOPS_PER_CELL_UPDATE,
+        "hbm_bound_cell_updates_per_s": PEAK_HBM_GBS * 1e9 / STEP_BYTES_PER_CELL_UPDATE_FP32}
 
     if not args.no_fp64:
         log("FP64 timed run")

@@ -97,6 +97,35 @@ def build_oracle(force: bool = False) -> str:
     return _LIB
 
 
+_OPC_SRC = os.path.join(_HERE, "opcount.cpp")
+_OPC_LIB = os.path.join(_HERE, "libopcount.so")
+
+
+def build_opcount(force: bool = False) -> str:
+    """Compile the operation-counting build of the oracle (libopcount.so)."""
+    import re
+    import tempfile
+    if not force and os.path.exists(_OPC_LIB) and os.path.getmtime(_OPC_LIB) >= max(
+            os.path.getmtime(_SRC), os.path.getmtime(_OPC_SRC)):
+        return _OPC_LIB
+    with open(_SRC) as f:
+        src = f.read()
+    with open(os.path.join(_HERE, "orc.h")) as f:
+        hdr = f.read()
+    with tempfile.TemporaryDirectory() as d:
+        with open(os.path.join(d, "orc.h"), "w") as f:
+            f.write(re.sub(r"\bdouble\b", "orc_real", hdr))
+        gen = os.path.join(d, "orc_real.c")
+        with open(gen, "w") as f:
+            f.write(re.sub(r"\bdouble\b", "orc_real", src))
+        tmp = _OPC_LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["g++", "-std=c++17", "-O1", "-fPIC", "-shared", "-w",
+                        "-DORC_REAL_SOURCE=\"%s\"" % gen, "-I", d, "-o", tmp, _OPC_SRC],
+                       check=True)
+        os.replace(tmp, _OPC_LIB)
+    return _OPC_LIB
+
+
 _lib = None
 
 
