@@ -67,6 +67,11 @@ struct orc_grid {
   double t;
   int64_t step;
   int64_t n_floor, n_hll, n_deg;
+  /* learned correction of the corrector fluxes */
+  double *mlp;            /* NULL = off; else ORC_MLP_NPARAM values */
+  double mlp_tau, mlp_jump;
+  unsigned char *shock;   /* per cell: 1 = shock cell (no correction on its faces) */
+  int64_t n_mlp, n_gated;
 };
 
 static long at(const orc_grid *g, int i, int j, int k) {
@@ -288,6 +293,170 @@ void orc_recon(const double w[4], int recon, double kappa, double *wl,
   *wr = w[2] - dWi1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Learned flux correction: 32-64-64-8 MLP, GELU hidden layers.             */
+/* ------------------------------------------------------------------------ */
+
+double orc_bf16(double x) {
+  float f = (float)x;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf / nan */
+  u += 0x7fffu + ((u >> 16) & 1u);                         /* ties to even */
+  u &= 0xffff0000u;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+static double gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
+static double gelu_d(double x) {
+  return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * 3.14159265358979323846);
+}
+
+/* parameter offsets */
+#define P_W1 0
+#define P_B1 (P_W1 + 64 * 32)
+#define P_W2 (P_B1 + 64)
+#define P_B2 (P_W2 + 64 * 64)
+#define P_W3 (P_B2 + 64)
+#define P_B3 (P_W3 + 8 * 64)
+
+static double rnd(int bf16, double v) { return bf16 ? orc_bf16(v) : v; }
+
+/* One sample: activations a1, h1, a2, h2 (h rounded when bf16) and y. */
+static void mlp_one(const double *P, int bf16, const double *x, double *a1, double *h1,
+                    double *a2, double *h2, double *y) {
+  double xr[32];
+  int i, j;
+  for (j = 0; j < 32; ++j) xr[j] = rnd(bf16, x[j]);
+  for (i = 0; i < 64; ++i) {
+    double acc = P[P_B1 + i];
+    for (j = 0; j < 32; ++j) acc += rnd(bf16, P[P_W1 + i * 32 + j]) * xr[j];
+    a1[i] = acc;
+    h1[i] = rnd(bf16, gelu(acc));
+  }
+  for (i = 0; i < 64; ++i) {
+    double acc = P[P_B2 + i];
+    for (j = 0; j < 64; ++j) acc += rnd(bf16, P[P_W2 + i * 64 + j]) * h1[j];
+    a2[i] = acc;
+    h2[i] = rnd(bf16, gelu(acc));
+  }
+  for (i = 0; i < 8; ++i) {
+    double acc = P[P_B3 + i];
+    for (j = 0; j < 64; ++j) acc += rnd(bf16, P[P_W3 + i * 64 + j]) * h2[j];
+    y[i] = acc;
+  }
+}
+
+void orc_mlp_forward(const double *params, int bf16, long n, const double *x, double *y) {
+  long b;
+#pragma omp parallel for schedule(static)
+  for (b = 0; b < n; ++b) {
+    double a1[64], h1[64], a2[64], h2[64];
+    mlp_one(params, bf16, x + 32 * b, a1, h1, a2, h2, y + 8 * b);
+  }
+}
+
+void orc_mlp_backward(const double *params, int bf16, long n, const double *x,
+                      const double *dy, double *grad) {
+  const double *P = params;
+  long b;
+  int i, j;
+  memset(grad, 0, sizeof(double) * ORC_MLP_NPARAM);
+  for (b = 0; b < n; ++b) {
+    double a1[64], h1[64], a2[64], h2[64], y[8], xr[32];
+    double dz3[8], dh2[64], dz2[64], dh1[64], dz1[64];
+    mlp_one(P, bf16, x + 32 * b, a1, h1, a2, h2, y);
+    for (j = 0; j < 32; ++j) xr[j] = rnd(bf16, x[32 * b + j]);
+    /* output layer: y = W3 h2 + b3 */
+    for (i = 0; i < 8; ++i) {
+      grad[P_B3 + i] += dy[8 * b + i];
+      dz3[i] = rnd(bf16, dy[8 * b + i]);
+      for (j = 0; j < 64; ++j) grad[P_W3 + i * 64 + j] += dz3[i] * h2[j];
+    }
+    for (j = 0; j < 64; ++j) {
+      double acc = 0.0;
+      for (i = 0; i < 8; ++i) acc += rnd(bf16, P[P_W3 + i * 64 + j]) * dz3[i];
+      dh2[j] = acc;
+    }
+    /* second hidden layer */
+    for (i = 0; i < 64; ++i) {
+      double dz = dh2[i] * gelu_d(a2[i]);
+      grad[P_B2 + i] += dz;
+      dz2[i] = rnd(bf16, dz);
+      for (j = 0; j < 64; ++j) grad[P_W2 + i * 64 + j] += dz2[i] * h1[j];
+    }
+    for (j = 0; j < 64; ++j) {
+      double acc = 0.0;
+      for (i = 0; i < 64; ++i) acc += rnd(bf16, P[P_W2 + i * 64 + j]) * dz2[i];
+      dh1[j] = acc;
+    }
+    /* first hidden layer */
+    for (i = 0; i < 64; ++i) {
+      double dz = dh1[i] * gelu_d(a1[i]);
+      grad[P_B1 + i] += dz;
+      dz1[i] = rnd(bf16, dz);
+      for (j = 0; j < 32; ++j) grad[P_W1 + i * 32 + j] += dz1[i] * xr[j];
+    }
+  }
+}
+
+/* Face means of cells 1 and 2 of the stencil: rho_m, v_m[3], c_m. */
+static void face_means(const double w8[32], double gamma, double *rm, double vm[3], double *cm) {
+  const double *c1 = w8 + 8, *c2 = w8 + 16;
+  int d;
+  *rm = 0.5 * (c1[0] + c2[0]);
+  for (d = 0; d < 3; ++d) vm[d] = 0.5 * (c1[1 + d] + c2[1 + d]);
+  *cm = sqrt(gamma * 0.5 * (c1[4] + c2[4]) / *rm);
+}
+
+void orc_mlp_features(const double w8[32], double gamma, double x[32]) {
+  double rm, vm[3], cm;
+  int c, d;
+  face_means(w8, gamma, &rm, vm, &cm);
+  for (c = 0; c < 4; ++c) {
+    const double *w = w8 + 8 * c;
+    double *o = x + 8 * c;
+    o[0] = w[0] / rm;
+    for (d = 0; d < 3; ++d) o[1 + d] = (w[1 + d] - vm[d]) / cm;
+    o[4] = w[4] / (rm * cm * cm);
+    for (d = 0; d < 3; ++d) o[5 + d] = w[5 + d] / (sqrt(rm) * cm);
+  }
+}
+
+void orc_mlp_out_to_flux(const double w8[32], double gamma, const double y[8], double df[7]) {
+  double rm, vm[3], cm;
+  int d;
+  face_means(w8, gamma, &rm, vm, &cm);
+  double fr = rm * cm * y[0];              /* mass flux correction */
+  double fm[3];                            /* momentum, mean-flow frame */
+  for (d = 0; d < 3; ++d) fm[d] = rm * cm * cm * y[1 + d];
+  double fe = rm * cm * cm * cm * y[4];    /* energy, mean-flow frame */
+  double v2 = vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2];
+  df[0] = fr;
+  for (d = 0; d < 3; ++d) df[1 + d] = fm[d] + vm[d] * fr;
+  df[4] = fe + (vm[0] * fm[0] + vm[1] * fm[1] + vm[2] * fm[2]) + 0.5 * v2 * fr;
+  df[5] = sqrt(rm) * cm * cm * y[6];
+  df[6] = sqrt(rm) * cm * cm * y[7];
+}
+
+void orc_mlp_flux_to_out(const double w8[32], double gamma, const double df[7], double y[8]) {
+  double rm, vm[3], cm;
+  int d;
+  face_means(w8, gamma, &rm, vm, &cm);
+  double fr = df[0];
+  double fm[3];
+  for (d = 0; d < 3; ++d) fm[d] = df[1 + d] - vm[d] * fr;
+  double v2 = vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2];
+  double fe = df[4] - (vm[0] * fm[0] + vm[1] * fm[1] + vm[2] * fm[2]) - 0.5 * v2 * fr;
+  y[0] = fr / (rm * cm);
+  for (d = 0; d < 3; ++d) y[1 + d] = fm[d] / (rm * cm * cm);
+  y[4] = fe / (rm * cm * cm * cm);
+  y[5] = 0.0;
+  y[6] = df[5] / (sqrt(rm) * cm * cm);
+  y[7] = df[6] / (sqrt(rm) * cm * cm);
+}
+
 void orc_hlld_batch(long n, const double *wl, const double *wr, const double *bn,
                     double gamma, double *flux, int32_t *code) {
   long t;
@@ -339,7 +508,19 @@ orc_grid *orc_create(const orc_config *cfg) {
     for (m = 0; m < 8; ++m) g->fl[a][m] = alloc_arr(g->np);
   }
   for (m = 0; m < 8; ++m) g->w[m] = alloc_arr(g->np);
+  g->shock = (unsigned char *)calloc((size_t)g->np, 1);
   return g;
+}
+
+int orc_set_mlp(orc_grid *g, const double *params, double tau, double jump) {
+  free(g->mlp);
+  g->mlp = NULL;
+  if (!params) return 0;
+  g->mlp = (double *)malloc(sizeof(double) * ORC_MLP_NPARAM);
+  memcpy(g->mlp, params, sizeof(double) * ORC_MLP_NPARAM);
+  g->mlp_tau = tau;
+  g->mlp_jump = jump;
+  return 0;
 }
 
 void orc_destroy(orc_grid *g) {
@@ -351,6 +532,8 @@ void orc_destroy(orc_grid *g) {
     for (m = 0; m < 8; ++m) free(g->fl[a][m]);
   }
   for (m = 0; m < 8; ++m) free(g->w[m]);
+  free(g->shock);
+  free(g->mlp);
   free(g);
 }
 
@@ -470,6 +653,61 @@ static void primitives(orc_grid *g, double *const u[5], double *const b[3]) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Shock cells of the stage state: some neighbour's pressure differs by     */
+/* more than `jump` times the cell's, and the flow converges (central       */
+/* div v < 0).  The learned correction is not applied on their faces.       */
+/* ------------------------------------------------------------------------ */
+
+static void shock_cells(orc_grid *g) {
+  int k;
+#pragma omp parallel for schedule(static)
+  for (k = -1; k <= g->n[2]; ++k) {
+    int i, j, a;
+    for (j = -1; j <= g->n[1]; ++j)
+      for (i = -1; i <= g->n[0]; ++i) {
+        long p = at(g, i, j, k);
+        double P = g->w[4][p], jmax = 0.0, div = 0.0;
+        for (a = 0; a < 3; ++a) {
+          long s = g->st[a];
+          double jl = fabs(g->w[4][p - s] - P) / P, jh = fabs(g->w[4][p + s] - P) / P;
+          if (jl > jmax) jmax = jl;
+          if (jh > jmax) jmax = jh;
+          div += (g->w[1 + a][p + s] - g->w[1 + a][p - s]) / (2.0 * g->d[a]);
+        }
+        g->shock[p] = (jmax > g->mlp_jump && div < 0.0) ? 1 : 0;
+      }
+  }
+}
+
+/* Learned correction of one corrector face flux f (frame order).  Faces
+   touching a shock cell keep the plain flux; elsewhere each component of
+   the correction is clipped to tau (|F| + a_max |U_R - U_L|). */
+static int mlp_correct(const orc_grid *g, const double w8[32], const double wl[7],
+                       const double wr[7], double bn, double f[7]) {
+  double x[32], y[8], df[7], ul[7], ur[7];
+  double gam = g->c.gamma;
+  int m;
+  orc_mlp_features(w8, gam, x);
+  orc_mlp_forward(g->mlp, 1, 1, x, y);
+  orc_mlp_out_to_flux(w8, gam, y, df);
+  orc_prim_to_cons(wl, bn, gam, ul);
+  orc_prim_to_cons(wr, bn, gam, ur);
+  double cfl = orc_fast_speed(wl, bn, gam), cfr = orc_fast_speed(wr, bn, gam);
+  double cmax = cfl > cfr ? cfl : cfr;
+  double sl = fabs((wl[1] < wr[1] ? wl[1] : wr[1]) - cmax);
+  double sr = fabs((wl[1] > wr[1] ? wl[1] : wr[1]) + cmax);
+  double amax = sl > sr ? sl : sr;
+  for (m = 0; m < 7; ++m) {
+    double lim = g->mlp_tau * (fabs(f[m]) + amax * fabs(ur[m] - ul[m]));
+    double d = df[m];
+    if (d > lim) d = lim;
+    if (d < -lim) d = -lim;
+    f[m] += d;
+  }
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* O4 / O9: flux sweep along axis a.                                        */
 /* ------------------------------------------------------------------------ */
 
@@ -480,14 +718,15 @@ static void sweep(orc_grid *g, int a, double *const bf[3], int recon) {
   double *src[7] = {g->w[0], g->w[1 + a], g->w[1 + t1], g->w[1 + t2], g->w[4],
                     g->w[5 + t1], g->w[5 + t2]};
   int lo[3], hi[3], k;
-  int64_t nhll = 0, ndeg = 0;
+  int64_t nhll = 0, ndeg = 0, nmlp = 0, ngate = 0;
+  int learned = g->mlp != NULL && recon != ORC_RECON_FIRST;
   /* normal: faces 0..n; transverse: rows -1..n, which the corner EMFs of
      the boundary edges need */
   for (k = 0; k < 3; ++k) { lo[k] = -1; hi[k] = g->n[k]; }
   lo[a] = 0; hi[a] = g->n[a];
-#pragma omp parallel for schedule(static) reduction(+ : nhll, ndeg)
+#pragma omp parallel for schedule(static) reduction(+ : nhll, ndeg, nmlp, ngate)
   for (k = lo[2]; k <= hi[2]; ++k) {
-    int i, j, v;
+    int i, j, v, c;
     for (j = lo[1]; j <= hi[1]; ++j)
       for (i = lo[0]; i <= hi[0]; ++i) {
         long p = at(g, i, j, k); /* face between cells p - s and p */
@@ -499,6 +738,26 @@ static void sweep(orc_grid *g, int a, double *const bf[3], int recon) {
         int code = orc_hlld(wl, wr, bf[a][p], g->c.gamma, f);
         if (code & 1) nhll++;
         if (code & 2) ndeg++;
+        if (learned) {
+          if (g->shock[p - s] || g->shock[p]) {
+            ngate++;
+          } else {
+            /* stencil of 8 frame primitives: rho, vn, vt1, vt2, P, Bn, Bt1, Bt2 */
+            double w8[32];
+            for (c = 0; c < 4; ++c) {
+              long q = p + (c - 2) * s;
+              w8[8 * c + 0] = g->w[0][q];
+              w8[8 * c + 1] = g->w[1 + a][q];
+              w8[8 * c + 2] = g->w[1 + t1][q];
+              w8[8 * c + 3] = g->w[1 + t2][q];
+              w8[8 * c + 4] = g->w[4][q];
+              w8[8 * c + 5] = g->w[5 + a][q];
+              w8[8 * c + 6] = g->w[5 + t1][q];
+              w8[8 * c + 7] = g->w[5 + t2][q];
+            }
+            nmlp += mlp_correct(g, w8, wl, wr, bf[a][p], f);
+          }
+        }
         g->fl[a][0][p] = f[0];
         g->fl[a][1 + a][p] = f[1];
         g->fl[a][1 + t1][p] = f[2];
@@ -512,6 +771,8 @@ static void sweep(orc_grid *g, int a, double *const bf[3], int recon) {
   }
   g->n_hll += nhll;
   g->n_deg += ndeg;
+  g->n_mlp += nmlp;
+  g->n_gated += ngate;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -710,6 +971,7 @@ double orc_step(orc_grid *g, double dt) {
   fill_ghosts(g, g->us, g->bs);
   /* corrector: MUSCL fluxes of U*, full step from U^n */
   primitives(g, g->us, g->bs);
+  if (g->mlp) shock_cells(g);
   for (a = 0; a < 3; ++a) sweep(g, a, g->bs, g->c.recon);
   for (a = 0; a < 3; ++a) corner_emf(g, a);
   update(g, dt, g->u, g->b, g->u, g->b);
@@ -845,6 +1107,8 @@ void orc_diag_get(orc_grid *g, orc_diag *out) {
   out->n_floor = g->n_floor;
   out->n_hll_fallback = g->n_hll;
   out->n_degenerate = g->n_deg;
+  out->n_mlp_faces = g->n_mlp;
+  out->n_mlp_gated = g->n_gated;
 }
 
 /* ------------------------------------------------------------------------ */

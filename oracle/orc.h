@@ -72,6 +72,7 @@ typedef struct orc_diag {
   double divb_max;              /* max over interior cells |div_h B| * min(dx) / max|B| */
   double rho_min, p_min;
   int64_t n_floor, n_hll_fallback, n_degenerate;
+  int64_t n_mlp_faces, n_mlp_gated;  /* corrected faces, faces gated to the plain flux */
 } orc_diag;
 
 typedef struct orc_grid orc_grid;
@@ -121,6 +122,43 @@ double orc_minmod(double a, double b);
    w[0..3].  recon/kappa as in orc_config. */
 void orc_recon(const double w[4], int recon, double kappa, double *wl,
                double *wr);
+
+/* ---- learned flux correction (a 32-64-64-8 MLP with GELU) ---- */
+
+#define ORC_MLP_NIN 32
+#define ORC_MLP_NH 64
+#define ORC_MLP_NOUT 8
+/* parameter vector order: W1[64][32], b1[64], W2[64][64], b2[64], W3[8][64], b3[8] */
+#define ORC_MLP_NPARAM 6792
+
+/* Round to the nearest bfloat16 (via the nearest float, ties to even). */
+double orc_bf16(double x);
+/* y[n][8] = MLP(x[n][32]).  bf16 != 0 rounds weights, inputs and hidden
+   activations to bfloat16 at the points the GPU kernels do (biases and
+   accumulation stay in full precision). */
+void orc_mlp_forward(const double *params, int bf16, long n, const double *x, double *y);
+/* grad[6792] = d/dparams of sum_b dy[b] . y[b] (same rounding points as the
+   GPU backward when bf16 != 0: dz and activations rounded before each
+   matrix product, bias gradients from the unrounded dz). */
+void orc_mlp_backward(const double *params, int bf16, long n, const double *x,
+                      const double *dy, double *grad);
+/* Face features: w8[4][8] = rho, vn, vt1, vt2, P, Bn, Bt1, Bt2 (cell-centred,
+   face-normal frame) of cells i-2..i+1 around face i-1/2.  With the face
+   means rho_m, v_m, P_m of cells i-1, i and c_m = sqrt(gamma P_m / rho_m):
+   x = rho/rho_m, (v - v_m)/c_m (3), P/(rho_m c_m^2), B/(sqrt(rho_m) c_m) (3)
+   per cell. */
+void orc_mlp_features(const double w8[32], double gamma, double x[32]);
+/* MLP output y[8] -> flux correction in the face frame dflux[7] = rho, Mn,
+   Mt1, Mt2, E, Bt1, Bt2: scales rho_m c_m, rho_m c_m^2, rho_m c_m^3,
+   sqrt(rho_m) c_m^2, and the Galilean shift by the face-mean velocity for the
+   momentum and energy rows; y[5] (normal B) is ignored.  flux_to_out is the
+   inverse (training targets). */
+void orc_mlp_out_to_flux(const double w8[32], double gamma, const double y[8], double dflux[7]);
+void orc_mlp_flux_to_out(const double w8[32], double gamma, const double dflux[7], double y[8]);
+/* Enables (params != NULL) the gated correction of the corrector fluxes:
+   params holds ORC_MLP_NPARAM values (used with bfloat16 rounding), tau the
+   clip factor, jump the relative pressure jump that marks a shock cell. */
+int orc_set_mlp(orc_grid *g, const double *params, double tau, double jump);
 
 /* Loops over n faces / stencils of the two functions above (arrays [n][7],
    [n][4], contiguous).  code may be NULL. */

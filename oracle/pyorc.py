@@ -18,6 +18,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_PAPER, RECON_KAPPA, RECON_FIRST = 0, 1, 2
+MLP_NPARAM = 6792
 SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X = 0, 1, 2, 3
 
 
@@ -43,6 +44,7 @@ class _Diag(C.Structure):
         ("rho_min", C.c_double), ("p_min", C.c_double),
         ("n_floor", C.c_int64), ("n_hll_fallback", C.c_int64),
         ("n_degenerate", C.c_int64),
+        ("n_mlp_faces", C.c_int64), ("n_mlp_gated", C.c_int64),
     ]
 
 
@@ -164,6 +166,15 @@ def load_oracle():
     L.orc_minmod.argtypes = [C.c_double, C.c_double]
     L.orc_recon.argtypes = [dp, C.c_int, C.c_double, dp, dp]
     L.orc_hlld_batch.argtypes = [C.c_long, dp, dp, dp, C.c_double, dp, C.POINTER(C.c_int32)]
+    L.orc_bf16.restype = C.c_double
+    L.orc_bf16.argtypes = [C.c_double]
+    L.orc_mlp_forward.argtypes = [dp, C.c_int, C.c_long, dp, dp]
+    L.orc_mlp_backward.argtypes = [dp, C.c_int, C.c_long, dp, dp, dp]
+    L.orc_mlp_features.argtypes = [dp, C.c_double, dp]
+    L.orc_mlp_out_to_flux.argtypes = [dp, C.c_double, dp, dp]
+    L.orc_mlp_flux_to_out.argtypes = [dp, C.c_double, dp, dp]
+    L.orc_set_mlp.restype = C.c_int
+    L.orc_set_mlp.argtypes = [C.c_void_p, dp, C.c_double, C.c_double]
     L.orc_recon_batch.argtypes = [C.c_long, dp, C.c_int, C.c_double, dp, dp]
     _lib = L
     return L
@@ -236,7 +247,18 @@ class Oracle:
             "energy": d.energy, "bsum": tuple(d.bsum), "divb_max": d.divb_max,
             "rho_min": d.rho_min, "p_min": d.p_min, "n_floor": d.n_floor,
             "n_hll_fallback": d.n_hll_fallback, "n_degenerate": d.n_degenerate,
+            "n_mlp_faces": d.n_mlp_faces, "n_mlp_gated": d.n_mlp_gated,
         }
+
+    def set_mlp(self, params, tau: float = 0.5, jump: float = 0.5):
+        """Enable (params: 6792 values) or disable (None) the learned
+        correction of the corrector fluxes."""
+        if params is None:
+            self.L.orc_set_mlp(self.h, None, tau, jump)
+            return
+        p = _f64(params)
+        assert p.shape == (MLP_NPARAM,)
+        self.L.orc_set_mlp(self.h, _ptr(p), tau, jump)
 
     def debug_array(self, what: int) -> np.ndarray:
         """Padded array [nz+5][ny+5][nx+5] of the last corrector stage."""
@@ -311,3 +333,63 @@ def recon_batch(w4, recon: int = RECON_PAPER, kappa: float = 1.0 / 3.0):
     wl, wr = np.empty(n), np.empty(n)
     L.orc_recon_batch(n, _ptr(w4), recon, kappa, _ptr(wl), _ptr(wr))
     return wl, wr
+
+
+# ---- learned correction -----------------------------------------------------
+
+def bf16(x: float) -> float:
+    return load_oracle().orc_bf16(float(x))
+
+
+def mlp_forward(params, x, bf16_round: bool = False):
+    L = load_oracle()
+    p, x = _f64(params), _f64(x)
+    n = x.shape[0]
+    y = np.empty((n, 8))
+    L.orc_mlp_forward(_ptr(p), 1 if bf16_round else 0, n, _ptr(x), _ptr(y))
+    return y
+
+
+def mlp_backward(params, x, dy, bf16_round: bool = False):
+    L = load_oracle()
+    p, x, dy = _f64(params), _f64(x), _f64(dy)
+    g = np.empty(MLP_NPARAM)
+    L.orc_mlp_backward(_ptr(p), 1 if bf16_round else 0, x.shape[0], _ptr(x), _ptr(dy), _ptr(g))
+    return g
+
+
+def mlp_features(w8, gamma):
+    L = load_oracle()
+    w8 = _f64(w8).reshape(32)
+    x = np.empty(32)
+    L.orc_mlp_features(_ptr(w8), gamma, _ptr(x))
+    return x
+
+
+def mlp_out_to_flux(w8, gamma, y):
+    L = load_oracle()
+    w8, y = _f64(w8).reshape(32), _f64(y)
+    f = np.empty(7)
+    L.orc_mlp_out_to_flux(_ptr(w8), gamma, _ptr(y), _ptr(f))
+    return f
+
+
+def mlp_flux_to_out(w8, gamma, df):
+    L = load_oracle()
+    w8, df = _f64(w8).reshape(32), _f64(df)
+    y = np.empty(8)
+    L.orc_mlp_flux_to_out(_ptr(w8), gamma, _ptr(df), _ptr(y))
+    return y
+
+
+def coarsen(cell5, bx, by, bz):
+    """2x coarse-graining of a periodic state: volume means of the cell
+    fields over 2^3 fine cells, area means of each face field over the 2^2
+    fine faces that tile a coarse face (plain definition, numpy)."""
+    c5 = np.asarray(cell5, dtype=np.float64)
+    nz, ny, nx = c5.shape[1:]
+    cc = c5.reshape(5, nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(2, 4, 6))
+    bx = np.asarray(bx, dtype=np.float64)[:, :, 0::2].reshape(nz // 2, 2, ny // 2, 2, nx // 2)
+    by = np.asarray(by, dtype=np.float64)[:, 0::2, :].reshape(nz // 2, 2, ny // 2, nx // 2, 2)
+    bz = np.asarray(bz, dtype=np.float64)[0::2, :, :].reshape(nz // 2, ny // 2, 2, nx // 2, 2)
+    return cc, bx.mean(axis=(1, 3)), by.mean(axis=(1, 4)), bz.mean(axis=(2, 4))
