@@ -104,6 +104,8 @@ typedef struct mhd_diag_t {
   int64_t n_hll_fallback; /* faces where HLLD fell back to HLL */
   int64_t n_degenerate;   /* faces with a degenerate HLLD star state */
   int64_t n_fp64_recovery;/* FP32 mode: cell evaluations whose pressure was redone in FP64 */
+  int64_t n_mlp_faces;    /* corrector faces that received the learned correction */
+  int64_t n_mlp_gated;    /* corrector faces kept plain because they touch a shock cell */
   uint32_t status;        /* MHD_ST_* bits */
   uint32_t pad;
 } mhd_diag_t;
@@ -194,6 +196,72 @@ int mhd_profile_get(mhd_ctx *ctx, mhd_profile_t *out);
 
 /* Releases the host context (not the caller's device memory). */
 int mhd_destroy(mhd_ctx *ctx);
+
+/* ---- learned flux correction (2x-coarsened runs) ------------------------
+   A 32-64-64-8 MLP with GELU hidden layers (parameter vector of
+   MHD_MLP_NPARAM FP32 values: W1[64][32], b1[64], W2[64][64], b2[64],
+   W3[8][64], b3[8]; weights used in bfloat16, FP32 accumulation on the
+   matrix cores) maps the 32 normalised primitives of a face's 4-cell stencil
+   (rho, vn, vt1, vt2, P, Bn, Bt1, Bt2 per cell, divided by the two-cell face
+   means: rho/rho_m, (v - v_m)/c_m, P/(rho_m c_m^2), B/(sqrt(rho_m) c_m)) to a
+   correction of the face's corrector flux (scales rho_m c_m, rho_m c_m^2,
+   rho_m c_m^3, sqrt(rho_m) c_m^2, Galilean shift by v_m; output 5, the normal
+   B, unused).  It is added to the HLLD flux before constrained transport,
+   except on faces touching a shock cell (a neighbour's pressure differs by
+   more than `jump` times the cell's and div v < 0), and clipped per component
+   to tau (|F| + a_max |U_R - U_L|). */
+#define MHD_MLP_NPARAM 6792
+
+typedef struct mhd_gate {
+  double tau;   /* clip factor, >= 0 (0.5 in the reference setup) */
+  double jump;  /* relative pressure jump marking a shock cell, > 0 (0.5) */
+} mhd_gate;
+
+/* Enables the fused correction in the corrector sweeps (d_params: device
+   FP32 [MHD_MLP_NPARAM], caller-owned, read at every step while enabled) or
+   disables it (d_params NULL). */
+int mhd_set_mlp(mhd_ctx *ctx, const float *d_params, const mhd_gate *gate);
+
+/* While d_acc is non-NULL, every step adds dt times the mean corrector flux
+   over the 2x2 fine faces tiling each face of the 2x-coarsened grid:
+   d_acc [3][7][nz/2][ny/2][nx/2] (context precision; components in the face
+   frame rho, Mn, Mt1, Mt2, E, Bt1, Bt2).  The caller zeroes it.  Needs even
+   extents and periodic boundaries (else MHD_E_UNSUPPORTED). */
+int mhd_flux_accumulate(mhd_ctx *ctx, void *d_acc);
+
+/* Writes the 2x-coarsened state (2^3 volume means, 2^2 face means) in the
+   interior layout of this header for the half-size grid.  Even extents and
+   periodic boundaries.  Synchronises. */
+int mhd_coarsen(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_bz);
+
+/* Training samples from the last step of a (coarse, periodic) context:
+   for n faces d_faces [n][4] = (axis, i, j, k) with 0 <= i,j,k < n_axis,
+   d_x [n][32] = features of the corrector state, d_t [n][8] = the MLP
+   output that would turn its corrector flux into d_acc/dt_coarse (d_acc
+   from mhd_flux_accumulate on the fine run over the same interval),
+   d_mask [n] = 1 if the face touches a shock cell, 2 if the face index is
+   invalid (then x, t are zero).  Asynchronous. */
+int mhd_mlp_samples(mhd_ctx *ctx, const void *d_acc, double dt_coarse, int64_t n,
+                    const int32_t *d_faces, float *d_x, float *d_t, uint8_t *d_mask);
+
+/* y [n][8] = MLP(x [n][32]) with the parameters d_params.  Asynchronous. */
+int mhd_mlp_forward(int64_t n, const float *d_x, const float *d_params, float *d_y,
+                    void *hip_stream);
+
+/* Scratch bytes for mhd_mlp_grad on n samples. */
+int mhd_mlp_grad_workspace_bytes(int64_t n, size_t *out);
+
+/* d_grad [MHD_MLP_NPARAM] = gradient of L = mean over samples and outputs
+   of (MLP(x) - t)^2; *d_loss = L (device float).  Deterministic (fixed
+   reduction order).  d_ws: scratch of mhd_mlp_grad_workspace_bytes(n).
+   Asynchronous. */
+int mhd_mlp_grad(int64_t n, const float *d_x, const float *d_t, const float *d_params,
+                 float *d_grad, float *d_loss, void *d_ws, size_t ws_bytes, void *hip_stream);
+
+/* One Adam update (bias-corrected, step >= 1) of d_params with moments
+   d_m, d_v (zero-initialised by the caller).  Asynchronous. */
+int mhd_mlp_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, int64_t step,
+                 double lr, double beta1, double beta2, double eps, void *hip_stream);
 
 /* ---- kernel-level entry points used by the parity tests ---------------- */
 

@@ -1121,6 +1121,7 @@ long orc_debug_array(const orc_grid *g, int what, double *out) {
   if (what >= 0 && what < 24) src = g->fl[what / 8][what % 8];
   else if (what >= 24 && what < 27) src = g->e[what - 24];
   else if (what >= 27 && what < 30) src = g->ec[what - 27];
+  else if (what >= 33 && what < 41) src = g->w[what - 33];
   else if (what >= 30 && what < 33) {
     for (p = 0; p < g->np; ++p) out[p] = (double)g->sg[what - 30][p];
     return g->np;

@@ -100,6 +100,8 @@ int orc_threads(void);
           24..26: edge EMF Ex, Ey, Ez
           27..29: cell EMF of the corrector state
           30..32: mass-flux sign of x, y, z faces (as doubles)
+          33..40: primitives of the corrector state (rho, vx, vy, vz, P,
+                  Bcx, Bcy, Bcz)
    Returns the number of doubles written (padded size), or -1. */
 long orc_debug_array(const orc_grid *g, int what, double *out);
 long orc_padded_size(const orc_grid *g);

@@ -50,6 +50,13 @@ class mhd_diag_t(C.Structure):
     ]
 
 
+MLP_NPARAM = 6792
+
+
+class mhd_gate(C.Structure):
+    _fields_ = [("tau", C.c_double), ("jump", C.c_double)]
+
+
 class mhd_profile_t(C.Structure):
     _fields_ = [("ms", C.c_double * 16), ("launches", C.c_int64 * 16),
                 ("n_kinds", C.c_int32), ("pad", C.c_int32)]
@@ -99,6 +106,23 @@ def load() -> C.CDLL:
     L.mhd_profile.argtypes = [vp, C.c_int]
     L.mhd_profile_get.restype = C.c_int
     L.mhd_profile_get.argtypes = [vp, C.POINTER(mhd_profile_t)]
+    L.mhd_set_mlp.restype = C.c_int
+    L.mhd_set_mlp.argtypes = [vp, vp, C.POINTER(mhd_gate)]
+    L.mhd_flux_accumulate.restype = C.c_int
+    L.mhd_flux_accumulate.argtypes = [vp, vp]
+    L.mhd_coarsen.restype = C.c_int
+    L.mhd_coarsen.argtypes = [vp, vp, vp, vp, vp]
+    L.mhd_mlp_samples.restype = C.c_int
+    L.mhd_mlp_samples.argtypes = [vp, vp, C.c_double, i64, vp, vp, vp, vp]
+    L.mhd_mlp_forward.restype = C.c_int
+    L.mhd_mlp_forward.argtypes = [i64, vp, vp, vp, vp]
+    L.mhd_mlp_grad_workspace_bytes.restype = C.c_int
+    L.mhd_mlp_grad_workspace_bytes.argtypes = [i64, C.POINTER(sz)]
+    L.mhd_mlp_grad.restype = C.c_int
+    L.mhd_mlp_grad.argtypes = [i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mhd_mlp_adam.restype = C.c_int
+    L.mhd_mlp_adam.argtypes = [vp, vp, vp, vp, i64, C.c_double, C.c_double, C.c_double,
+                               C.c_double, vp]
     L.mhd_destroy.restype = C.c_int
     L.mhd_destroy.argtypes = [vp]
     L.mhd_hlld_batch.restype = C.c_int

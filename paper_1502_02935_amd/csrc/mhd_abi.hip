@@ -92,7 +92,7 @@ Layout layout_of(const mhd_config* c) {
   L.arr8 = align_up((size_t)g.np);
   L.off_t = 0;
   L.off_sg = L.off_t + kNumT * L.arr;
-  L.off_misc = L.off_sg + 3 * L.arr8;
+  L.off_misc = L.off_sg + 4 * L.arr8;  // 3 sign arrays + shock flags
   L.off_cnt = L.off_misc + align_up(64 * sizeof(double));
   L.off_cfl = L.off_cnt + align_up((size_t)kNumCounters * kCounterSlots * kCounterStride *
                                    sizeof(unsigned long long));
@@ -155,6 +155,19 @@ struct mhd_ctx {
   }
   void* arr(int q) const { return ws + L.off_t + (size_t)q * L.arr; }
   int8_t* sg(int a) const { return (int8_t*)(ws + L.off_sg + (size_t)a * L.arr8); }
+  uint8_t* shock() const { return (uint8_t*)(ws + L.off_sg + 3 * L.arr8); }
+  // learned correction and fine-flux accumulation
+  const float* mlp_params = nullptr;
+  double mlp_tau = 0.5, mlp_jump = 0.5;
+  void* flux_acc = nullptr;
+  MlpRef mlp_ref() const {
+    MlpRef m;
+    m.params = mlp_params;
+    m.tau = mlp_tau;
+    m.jump = mlp_jump;
+    m.shock = shock();
+    return m;
+  }
   double* misc() const { return (double*)(ws + L.off_misc); }
   double* cfl_part() const { return (double*)(ws + L.off_cfl); }
   double* diag_part() const { return (double*)(ws + L.off_diag); }
@@ -167,6 +180,8 @@ struct mhd_ctx {
     c.deg = base + span;
     c.floor_hits = base + 2 * span;
     c.fp64_rec = base + 3 * span;
+    c.mlp_faces = base + 4 * span;
+    c.mlp_gated = base + 5 * span;
     c.status = (unsigned int*)(misc() + M_STATUS);
     return c;
   }
@@ -275,9 +290,20 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   // corrector: MUSCL fluxes of U*, full step from U^n
   c->mark(MHD_K_PRIM);
   launch_prim<T>(g, c->ph, Us, W, cnt, c->st);
+  if (c->mlp_params) {
+    c->mark(MHD_K_OTHER);
+    launch_shock<T>(g, W, c->shock(), c->mlp_jump, c->st);
+  }
   for (int a = 0; a < 3; ++a) {
     c->mark(MHD_K_FLUX_X + a);
-    launch_flux<T>(g, c->ph, a, W, Us.b[a], F, second, cnt, c->st);
+    if (c->mlp_params)
+      launch_flux_mlp<T>(g, c->ph, a, W, Us.b[a], F, second, cnt, c->mlp_ref(), c->st);
+    else
+      launch_flux<T>(g, c->ph, a, W, Us.b[a], F, second, cnt, c->st);
+  }
+  if (c->flux_acc) {
+    c->mark(MHD_K_OTHER);
+    launch_fluxacc<T>(g, F, (T*)c->flux_acc, dt, c->st);
   }
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, W, F, E, c->st);
@@ -434,7 +460,7 @@ int mhd_diag(mhd_ctx* c, mhd_diag_t* out) {
     return MHD_E_HIP;
   if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
   const double* d = m + M_DIAG;
-  unsigned long long cn[kNumCounters] = {0, 0, 0, 0};
+  unsigned long long cn[kNumCounters] = {0, 0, 0, 0, 0, 0};
   for (int q = 0; q < kNumCounters; ++q)
     for (int sl = 0; sl < kCounterSlots; ++sl)
       cn[q] += slots[((size_t)q * kCounterSlots + sl) * kCounterStride];
@@ -453,6 +479,8 @@ int mhd_diag(mhd_ctx* c, mhd_diag_t* out) {
   out->n_degenerate = (int64_t)cn[1];
   out->n_floor = (int64_t)cn[2];
   out->n_fp64_recovery = (int64_t)cn[3];
+  out->n_mlp_faces = (int64_t)cn[4];
+  out->n_mlp_gated = (int64_t)cn[5];
   unsigned int st;
   memcpy(&st, &m[M_STATUS], sizeof(st));
   out->status = st;
@@ -522,6 +550,100 @@ int mhd_destroy(mhd_ctx* c) {
   if (!c) return MHD_E_ARG;
   delete c;
   return MHD_OK;
+}
+
+static bool even_periodic(const mhd_ctx* c) {
+  for (int a = 0; a < 3; ++a)
+    if (c->g.n[a] % 2 != 0 || c->g.bc[2 * a] != MHD_BC_PERIODIC) return false;
+  return true;
+}
+
+int mhd_set_mlp(mhd_ctx* c, const float* d_params, const mhd_gate* gate) {
+  if (!c) return MHD_E_ARG;
+  if (!d_params) {
+    c->mlp_params = nullptr;
+    return MHD_OK;
+  }
+  if (!gate || !(gate->tau >= 0.0) || !(gate->jump > 0.0)) return MHD_E_ARG;
+  c->mlp_params = d_params;
+  c->mlp_tau = gate->tau;
+  c->mlp_jump = gate->jump;
+  return MHD_OK;
+}
+
+int mhd_flux_accumulate(mhd_ctx* c, void* d_acc) {
+  if (!c) return MHD_E_ARG;
+  if (d_acc && !even_periodic(c)) return MHD_E_UNSUPPORTED;
+  c->flux_acc = d_acc;
+  return MHD_OK;
+}
+
+int mhd_coarsen(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz) {
+  if (!c || !d_cell5 || !d_bx || !d_by || !d_bz) return MHD_E_ARG;
+  if (!even_periodic(c)) return MHD_E_UNSUPPORTED;
+  if (c->cfg.precision == MHD_FP64)
+    launch_coarsen<double>(c->g, c->cons<double>(0), (double*)d_cell5, (double*)d_bx,
+                           (double*)d_by, (double*)d_bz, c->st);
+  else
+    launch_coarsen<float>(c->g, c->cons<float>(0), (float*)d_cell5, (float*)d_bx, (float*)d_by,
+                          (float*)d_bz, c->st);
+  if (hip_status() != MHD_OK) return MHD_E_HIP;
+  return hipStreamSynchronize(c->st) == hipSuccess ? MHD_OK : MHD_E_HIP;
+}
+
+int mhd_mlp_samples(mhd_ctx* c, const void* d_acc, double dt_coarse, int64_t n,
+                    const int32_t* d_faces, float* d_x, float* d_t, uint8_t* d_mask) {
+  if (!c || n < 0 || !(dt_coarse > 0.0)) return MHD_E_ARG;
+  if (n > 0 && (!d_acc || !d_faces || !d_x || !d_t || !d_mask)) return MHD_E_ARG;
+  if (!even_periodic(c)) {
+    for (int a = 0; a < 3; ++a)
+      if (c->g.bc[2 * a] != MHD_BC_PERIODIC) return MHD_E_UNSUPPORTED;
+  }
+  if (n == 0) return MHD_OK;
+  if (c->cfg.precision == MHD_FP64) {
+    launch_shock<double>(c->g, c->prim<double>(), c->shock(), c->mlp_jump, c->st);
+    launch_mlp_samples<double>(c->g, c->prim<double>(), c->flux<double>(), c->shock(),
+                               (const double*)d_acc, dt_coarse, c->ph.gamma, n, d_faces, d_x, d_t,
+                               d_mask, c->st);
+  } else {
+    launch_shock<float>(c->g, c->prim<float>(), c->shock(), c->mlp_jump, c->st);
+    launch_mlp_samples<float>(c->g, c->prim<float>(), c->flux<float>(), c->shock(),
+                              (const float*)d_acc, dt_coarse, c->ph.gamma, n, d_faces, d_x, d_t,
+                              d_mask, c->st);
+  }
+  return hip_status();
+}
+
+int mhd_mlp_forward(int64_t n, const float* d_x, const float* d_params, float* d_y,
+                    void* hip_stream) {
+  if (n < 0 || (n > 0 && (!d_x || !d_params || !d_y))) return MHD_E_ARG;
+  if (n == 0) return MHD_OK;
+  launch_mlp_forward(n, d_x, d_params, d_y, (hipStream_t)hip_stream);
+  return hip_status();
+}
+
+int mhd_mlp_grad_workspace_bytes(int64_t n, size_t* out) {
+  if (n <= 0 || !out) return MHD_E_ARG;
+  *out = mlp_grad_workspace(n);
+  return MHD_OK;
+}
+
+int mhd_mlp_grad(int64_t n, const float* d_x, const float* d_t, const float* d_params,
+                 float* d_grad, float* d_loss, void* d_ws, size_t ws_bytes, void* hip_stream) {
+  if (n <= 0 || !d_x || !d_t || !d_params || !d_grad || !d_ws) return MHD_E_ARG;
+  if (ws_bytes < mlp_grad_workspace(n)) return MHD_E_WS;
+  launch_mlp_grad(n, d_x, d_t, d_params, d_grad, d_loss, (float*)d_ws, (hipStream_t)hip_stream);
+  return hip_status();
+}
+
+int mhd_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t step,
+                 double lr, double beta1, double beta2, double eps, void* hip_stream) {
+  if (!d_params || !d_m || !d_v || !d_grad || step < 1 || !(lr >= 0.0) || !(beta1 >= 0.0) ||
+      !(beta1 < 1.0) || !(beta2 >= 0.0) || !(beta2 < 1.0) || !(eps > 0.0))
+    return MHD_E_ARG;
+  launch_mlp_adam(d_params, d_m, d_v, d_grad, step, lr, beta1, beta2, eps,
+                  (hipStream_t)hip_stream);
+  return hip_status();
 }
 
 int mhd_hlld_batch(int precision, int64_t n, const void* d_wl, const void* d_wr, const void* d_bn,

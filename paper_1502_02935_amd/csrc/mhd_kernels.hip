@@ -7,6 +7,7 @@
 #include <math.h>
 
 #include "mhd_kernels.hpp"
+#include "mhd_mlp.hpp"
 
 namespace mhd {
 
@@ -255,6 +256,159 @@ void launch_flux(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Fl
     hipLaunchKernelGGL((k_flux<T, 1>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
   else
     hipLaunchKernelGGL((k_flux<T, 2>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
+}
+
+// ------------------------------------------------------------------------
+// Corrector flux sweep with the learned correction (coarse runs).  Same
+// faces and HLLD flux as k_flux; then per face the 32 features of the
+// 4-cell stencil go through the MLP on the matrix cores (one 64-face batch
+// per wave), and outside shock cells the correction, clipped per component
+// to tau (|F| + a_max |U_R - U_L|), is added before the fluxes are stored
+// (so constrained transport sees the corrected B fluxes).
+// ------------------------------------------------------------------------
+
+constexpr int BY_MLP = 2;
+
+struct MlpWaveLds {
+  unsigned short X[64 * kXs];
+  unsigned short H1[64 * kHs];
+  unsigned short H2[64 * kHs];
+  float Y[64 * 8];
+};
+
+template <class T, int A>
+__global__ void __launch_bounds__(BX* BY_MLP) k_flux_mlp(Geo g, Physics ph, Prim<T> w,
+                                                         const T* __restrict__ bn, Flux<T> f,
+                                                         Muscl<T> mu, Counters cnt, MlpRef mlp) {
+  __shared__ MlpWaveLds lds[BY_MLP];
+  MlpWaveLds& L = lds[threadIdx.y];
+  constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * BX + threadIdx.x + (A == 0 ? 0 : -1);
+  const int j = blockIdx.y * BY_MLP + threadIdx.y + (A == 1 ? 0 : -1);
+  const int k = blockIdx.z + (A == 2 ? 0 : -1);
+  const bool valid = i <= g.n[0] && j <= g.n[1];
+  const int s = stride_of(g, A);
+  const int p = valid ? pidx(g, i, j, k) : 0;
+  int code = 0;
+  T F[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  Face<T> Lf{}, Rf{};
+  float w8[32];
+  const float gam = (float)ph.gamma;
+  if (valid) {
+    const T* __restrict__ src[8] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2],
+                                    w.w[4], w.w[5 + A], w.w[5 + A1], w.w[5 + A2]};
+    T st4[8][4];
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        st4[v][c] = src[v][p + (c - 2) * s];
+        w8[8 * c + v] = (float)st4[v][c];
+      }
+    T l[7], r[7];
+    const int map[7] = {0, 1, 2, 3, 4, 6, 7};  // skip the cell-centred normal B
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      const int q = map[v];
+      muscl_lr(mu, st4[q][0], st4[q][1], st4[q][2], st4[q][3], l[v], r[v]);
+    }
+    Lf = Face<T>{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
+    Rf = Face<T>{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+    code = hlld(Lf, Rf, bn[p], (T)ph.gamma, F);
+    float x[32];
+    face_features(w8, face_scale(w8, gam), x);
+#pragma unroll
+    for (int c = 0; c < 32; ++c) L.X[lane * kXs + c] = bf16_bits(x[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 32; ++c) L.X[lane * kXs + c] = 0;
+  }
+  __syncthreads();
+  wave_mlp_forward(mlp.params, L.X, L.H1, L.H2, L.Y, nullptr, nullptr);
+  bool corrected = false, gated = false;
+  if (valid) {
+    if (mlp.shock[p - s] || mlp.shock[p]) {
+      gated = true;
+    } else {
+      float y[8], df[7];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) y[o] = L.Y[lane * 8 + o];
+      out_to_flux(face_scale(w8, gam), y, df);
+      const T b = bn[p];
+      const T igm1 = T(1) / ((T)ph.gamma - T(1));
+      T ul[7], fl[7], ur[7], fr[7];
+      cons_flux(Lf, b, igm1, ul, fl);
+      cons_flux(Rf, b, igm1, ur, fr);
+      const T cfl = fast_speed(Lf.d, Lf.p, b, Lf.bt1, Lf.bt2, (T)ph.gamma);
+      const T cfr = fast_speed(Rf.d, Rf.p, b, Rf.bt1, Rf.bt2, (T)ph.gamma);
+      const T cmax = cfl > cfr ? cfl : cfr;
+      const T sl = fabs((Lf.vn < Rf.vn ? Lf.vn : Rf.vn) - cmax);
+      const T sr = fabs((Lf.vn > Rf.vn ? Lf.vn : Rf.vn) + cmax);
+      const T amax = sl > sr ? sl : sr;
+      const T tau = (T)mlp.tau;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) {
+        const T lim = tau * (fabs(F[m]) + amax * fabs(ur[m] - ul[m]));
+        T d = (T)df[m];
+        d = d > lim ? lim : (d < -lim ? -lim : d);
+        F[m] += d;
+      }
+      corrected = true;
+    }
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f.f[A][m][p] = F[m];
+    f.sg[A][p] = (int8_t)(F[0] > T(0) ? 1 : (F[0] < T(0) ? -1 : 0));
+  }
+  wave_count((code & 1) != 0, cnt.hll);
+  wave_count((code & 2) != 0, cnt.deg);
+  wave_count(corrected, cnt.mlp_faces);
+  wave_count(gated, cnt.mlp_gated);
+}
+
+template <class T>
+void launch_flux_mlp(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
+                     Muscl<T> m, Counters c, MlpRef mlp, hipStream_t st) {
+  int r[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
+  r[axis] = g.n[axis] + 1;
+  const dim3 gr((unsigned)((r[0] + BX - 1) / BX), (unsigned)((r[1] + BY_MLP - 1) / BY_MLP),
+                (unsigned)r[2]);
+  const dim3 bl(BX, BY_MLP);
+  if (axis == 0)
+    hipLaunchKernelGGL((k_flux_mlp<T, 0>), gr, bl, 0, st, g, ph, w, bn, f, m, c, mlp);
+  else if (axis == 1)
+    hipLaunchKernelGGL((k_flux_mlp<T, 1>), gr, bl, 0, st, g, ph, w, bn, f, m, c, mlp);
+  else
+    hipLaunchKernelGGL((k_flux_mlp<T, 2>), gr, bl, 0, st, g, ph, w, bn, f, m, c, mlp);
+}
+
+// Shock cells of the stage state on cells [-1, n]^3: some neighbour's
+// pressure differs by more than `jump` times the cell's and the central
+// divergence of v is negative.
+template <class T>
+__global__ void __launch_bounds__(BX* BY) k_shock(Geo g, Prim<T> w, uint8_t* shock, double jump) {
+  const int i = blockIdx.x * BX + threadIdx.x - 1;
+  const int j = blockIdx.y * BY + threadIdx.y - 1;
+  const int k = blockIdx.z - 1;
+  if (i > g.n[0] || j > g.n[1]) return;
+  const int p = pidx(g, i, j, k);
+  const int st[3] = {1, g.sy, g.sz};
+  const T P = w.w[4][p];
+  T jmax = T(0), div = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T jl = fabs(w.w[4][p - st[a]] - P) / P, jh = fabs(w.w[4][p + st[a]] - P) / P;
+    jmax = jl > jmax ? jl : jmax;
+    jmax = jh > jmax ? jh : jmax;
+    div += (w.w[1 + a][p + st[a]] - w.w[1 + a][p - st[a]]) / (T(2) * (T)g.d[a]);
+  }
+  shock[p] = (jmax > (T)jump && div < T(0)) ? 1 : 0;
+}
+
+template <class T>
+void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, hipStream_t st) {
+  hipLaunchKernelGGL(k_shock<T>, grid_for(g.n[0] + 2, g.n[1] + 2, g.n[2] + 2), dim3(BX, BY), 0, st,
+                     g, w, shock, jump);
 }
 
 // ------------------------------------------------------------------------
@@ -753,6 +907,9 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_flux<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>, Muscl<T>,  \
                                Counters, hipStream_t);                                           \
   template void launch_emf<T>(const Geo&, Prim<T>, Flux<T>, Edge<T>, hipStream_t);              \
+  template void launch_flux_mlp<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>,        \
+                                   Muscl<T>, Counters, MlpRef, hipStream_t);                     \
+  template void launch_shock<T>(const Geo&, Prim<T>, uint8_t*, double, hipStream_t);           \
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Flux<T>, \
                                  Edge<T>, DtRef, Counters, hipStream_t);                         \
   template void launch_cfl<T>(const Geo&, const Physics&, Cons<T>, double*, double*, Counters,   \

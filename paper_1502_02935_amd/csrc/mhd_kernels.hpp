@@ -55,14 +55,24 @@ struct Edge {
 // a single shared address would serialise every wave's atomic in L2.
 constexpr int kCounterSlots = 256;
 constexpr int kCounterStride = 8;  // unsigned long longs per slot (64 bytes)
-constexpr int kNumCounters = 4;    // hll, degenerate, floor hits, FP64 recoveries
+constexpr int kNumCounters = 6;  // hll, degenerate, floors, FP64 recoveries, MLP faces, gated
 
 struct Counters {
   unsigned long long* hll;
   unsigned long long* deg;
   unsigned long long* floor_hits;
   unsigned long long* fp64_rec;
+  unsigned long long* mlp_faces;
+  unsigned long long* mlp_gated;
   unsigned int* status;
+};
+
+// Learned correction of the corrector fluxes (null params = off).
+struct MlpRef {
+  const float* params;  // FP32 master weights, 6792
+  double tau;           // clip factor
+  double jump;          // relative pressure jump of a shock cell
+  uint8_t* shock;       // per padded cell
 };
 
 struct Physics {
@@ -91,6 +101,11 @@ template <class T>
 void launch_flux(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
                  Muscl<T> m, Counters c, hipStream_t st);
 template <class T>
+void launch_flux_mlp(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
+                     Muscl<T> m, Counters c, MlpRef mlp, hipStream_t st);
+template <class T>
+void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, hipStream_t st);
+template <class T>
 void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
@@ -115,6 +130,22 @@ void launch_scatter(const Geo& g, const T* cell5, const T* bx, const T* by, cons
                     Cons<T> s, hipStream_t st);
 template <class T>
 void launch_gather(const Geo& g, Cons<T> s, T* cell5, T* bx, T* by, T* bz, hipStream_t st);
+
+// learned correction: training and data pipeline (mhd_mlp.hip)
+void launch_mlp_forward(int64_t n, const float* x, const float* P, float* y, hipStream_t st);
+size_t mlp_grad_workspace(int64_t n);
+void launch_mlp_grad(int64_t n, const float* x, const float* t, const float* P, float* grad,
+                     float* loss, float* part, hipStream_t st);
+void launch_mlp_adam(float* P, float* m, float* v, const float* g, int64_t step, double lr,
+                     double b1, double b2, double eps, hipStream_t st);
+template <class T>
+void launch_fluxacc(const Geo& g, Flux<T> f, T* acc, DtRef dt, hipStream_t st);
+template <class T>
+void launch_coarsen(const Geo& g, Cons<T> s, T* c5, T* bx, T* by, T* bz, hipStream_t st);
+template <class T>
+void launch_mlp_samples(const Geo& g, Prim<T> w, Flux<T> f, const uint8_t* shock, const T* acc,
+                        double dt_c, double gam, int64_t n, const int32_t* faces, float* x,
+                        float* t, uint8_t* mask, hipStream_t st);
 
 template <class T>
 void launch_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T gam, T* flux,

@@ -153,8 +153,60 @@ class Sim:
             "energy": d.energy, "bsum": tuple(d.bsum), "divb_max": d.divb_max,
             "rho_min": d.rho_min, "p_min": d.p_min, "n_floor": d.n_floor,
             "n_hll_fallback": d.n_hll_fallback, "n_degenerate": d.n_degenerate,
-            "n_fp64_recovery": d.n_fp64_recovery, "status": d.status, "rc": rc,
+            "n_fp64_recovery": d.n_fp64_recovery, "n_mlp_faces": d.n_mlp_faces,
+            "n_mlp_gated": d.n_mlp_gated, "status": d.status, "rc": rc,
         }
+
+    # ---- learned correction ------------------------------------------------
+
+    def set_mlp(self, params=None, tau: float = 0.5, jump: float = 0.5):
+        """Enable the fused correction with FP32 device params [6792] (kept
+        referenced here), or disable it with None."""
+        if params is None:
+            L.check(self.L.mhd_set_mlp(self.ctx, None, None), "mhd_set_mlp")
+            self._mlp = None
+            return
+        assert params.dtype == torch.float32 and params.is_contiguous()
+        assert params.numel() == L.MLP_NPARAM and params.device == self.device
+        self._mlp = params
+        gate = L.mhd_gate(tau, jump)
+        L.check(self.L.mhd_set_mlp(self.ctx, _ptr(params), C.byref(gate)), "mhd_set_mlp")
+
+    def flux_accumulator(self, enable: bool = True):
+        """Start (zeroed) or stop accumulating dt-weighted corrector fluxes on
+        the 2x-coarsened faces; returns the accumulator tensor
+        [3][7][nz/2][ny/2][nx/2]."""
+        if not enable:
+            L.check(self.L.mhd_flux_accumulate(self.ctx, None), "mhd_flux_accumulate")
+            return getattr(self, "_acc", None)
+        cfg = self.cfg
+        self._acc = torch.zeros((3, 7, cfg.nz // 2, cfg.ny // 2, cfg.nx // 2), dtype=cfg.dtype,
+                                device=self.device)
+        L.check(self.L.mhd_flux_accumulate(self.ctx, _ptr(self._acc)), "mhd_flux_accumulate")
+        return self._acc
+
+    def coarsen(self):
+        cfg = self.cfg
+        dt = cfg.dtype
+        nx, ny, nz = cfg.nx // 2, cfg.ny // 2, cfg.nz // 2
+        c5 = torch.empty((5, nz, ny, nx), dtype=dt, device=self.device)
+        b = [torch.empty((nz, ny, nx), dtype=dt, device=self.device) for _ in range(3)]
+        L.check(self.L.mhd_coarsen(self.ctx, _ptr(c5), _ptr(b[0]), _ptr(b[1]), _ptr(b[2])),
+                "mhd_coarsen")
+        return c5, b[0], b[1], b[2]
+
+    def mlp_samples(self, acc: torch.Tensor, dt_coarse: float, faces: torch.Tensor):
+        """Features, targets and masks of faces [n][4] (axis, i, j, k) from
+        this context's last step."""
+        n = faces.shape[0]
+        assert faces.dtype == torch.int32 and faces.is_contiguous() and faces.shape == (n, 4)
+        assert acc.dtype == self.cfg.dtype and acc.is_contiguous()
+        x = torch.empty((n, 32), dtype=torch.float32, device=self.device)
+        t = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        m = torch.empty(n, dtype=torch.uint8, device=self.device)
+        L.check(self.L.mhd_mlp_samples(self.ctx, _ptr(acc), dt_coarse, n, _ptr(faces), _ptr(x),
+                                       _ptr(t), _ptr(m)), "mhd_mlp_samples")
+        return x, t, m
 
     def get_state(self):
         cfg = self.cfg
@@ -214,3 +266,57 @@ def recon_batch(w4: torch.Tensor, recon: int = L.RECON_PAPER, kappa: float = 1.0
     L.check(lib.mhd_recon_batch(prec, n, _ptr(w4), recon, kappa, _ptr(wl), _ptr(wr),
                                 C.c_void_p(st.cuda_stream)), "mhd_recon_batch")
     return wl, wr
+
+
+# ---- learned correction: training kernels ----------------------------------
+
+def _stream(dev, stream=None):
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    return C.c_void_p(st.cuda_stream)
+
+
+def mlp_forward(x: torch.Tensor, params: torch.Tensor, stream=None) -> torch.Tensor:
+    lib = L.load()
+    assert x.dtype == torch.float32 and x.is_contiguous() and x.shape[1] == 32
+    assert params.dtype == torch.float32 and params.numel() == L.MLP_NPARAM
+    y = torch.empty((x.shape[0], 8), dtype=torch.float32, device=x.device)
+    L.check(lib.mhd_mlp_forward(x.shape[0], _ptr(x), _ptr(params), _ptr(y),
+                                _stream(x.device, stream)), "mhd_mlp_forward")
+    return y
+
+
+class MlpTrainer:
+    """Adam on the MSE loss, every pass in the library's MFMA kernels."""
+
+    def __init__(self, params: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        assert params.dtype == torch.float32 and params.numel() == L.MLP_NPARAM
+        self.lib = L.load()
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.grad = torch.zeros_like(params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self.lr, self.b1, self.b2, self.eps = lr, beta1, beta2, eps
+        self.step_count = 0
+        self._ws = None
+
+    def gradient(self, x: torch.Tensor, t: torch.Tensor):
+        n = x.shape[0]
+        assert x.shape == (n, 32) and t.shape == (n, 8)
+        assert x.is_contiguous() and t.is_contiguous()
+        nb = C.c_size_t()
+        L.check(self.lib.mhd_mlp_grad_workspace_bytes(n, C.byref(nb)), "mhd_mlp_grad_workspace_bytes")
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+        L.check(self.lib.mhd_mlp_grad(n, _ptr(x), _ptr(t), _ptr(self.params), _ptr(self.grad),
+                                      _ptr(self.loss), _ptr(self._ws), self._ws.numel(),
+                                      _stream(x.device)), "mhd_mlp_grad")
+        return self.grad, self.loss
+
+    def step(self, x: torch.Tensor, t: torch.Tensor):
+        self.gradient(x, t)
+        self.step_count += 1
+        L.check(self.lib.mhd_mlp_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                      _ptr(self.grad), self.step_count, self.lr, self.b1, self.b2,
+                                      self.eps, _stream(self.params.device)), "mhd_mlp_adam")
+        return self.loss

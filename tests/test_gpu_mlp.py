@@ -1,0 +1,224 @@
+"""GPU parity of the learned flux correction: MFMA forward and backward
+against the oracle's FP64 MLP with the same bfloat16 rounding points (and
+against pure FP64), Adam, a training run, the data pipeline (coarsening,
+time-weighted fine fluxes on coarse faces, features/targets) and the fused
+gated correction inside the corrector step."""
+import numpy as np
+import pytest
+
+from mhd_inputs import problems as P
+from oracle import pyorc as O
+from tests.gpu_util import field_errors, gpu_sim, host_state, needs_gpu
+from tests.helpers import oracle_of
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float32, device="cuda")
+
+
+def _params(seed, scale=0.3):
+    return np.random.default_rng(seed).normal(0, scale, O.MLP_NPARAM)
+
+
+def test_mlp_forward_matches_oracle():
+    from paper_1502_02935_amd import mlp_forward
+    p = _params(1).astype(np.float32).astype(np.float64)
+    x = np.random.default_rng(2).normal(size=(4096 + 37, 32)).astype(np.float32).astype(np.float64)
+    y = mlp_forward(_t(x), _t(p)).cpu().numpy().astype(np.float64)
+    yb = O.mlp_forward(p, x, bf16_round=True)
+    y64 = O.mlp_forward(p, x, bf16_round=False)
+    scale = np.abs(yb).max()
+    # same bf16 rounding points; an activation whose FP32 and FP64 values
+    # straddle a bf16 rounding boundary differs by one bf16 ulp (2^-8)
+    assert np.abs(y - yb).max() <= 5e-3 * scale
+    assert np.abs(y - yb).mean() <= 2e-4 * scale
+    assert np.abs(y - y64).max() <= 5e-2 * scale
+
+
+def test_mlp_gradient_matches_oracle():
+    import torch
+    from paper_1502_02935_amd import MlpTrainer
+    rng = np.random.default_rng(3)
+    p = _params(4).astype(np.float32).astype(np.float64)
+    n = 1000
+    x = rng.normal(size=(n, 32)).astype(np.float32).astype(np.float64)
+    t = rng.normal(size=(n, 8)).astype(np.float32).astype(np.float64)
+    tr = MlpTrainer(_t(p))
+    g, loss = tr.gradient(_t(x), _t(t))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    yb = O.mlp_forward(p, x, bf16_round=True)
+    dy = 2.0 * (yb - t) / (n * 8)
+    gb = O.mlp_backward(p, x, dy, bf16_round=True)
+    g64 = O.mlp_backward(p, x, 2.0 * (O.mlp_forward(p, x) - t) / (n * 8))
+    assert abs(float(loss.item()) - np.mean((yb - t) ** 2)) <= 1e-3 * np.mean((yb - t) ** 2)
+    for lo, hi in ((0, 2048), (2048, 2112), (2112, 6208), (6208, 6272), (6272, 6784), (6784, 6792)):
+        sc = np.abs(gb[lo:hi]).max()
+        assert np.abs(g[lo:hi] - gb[lo:hi]).max() <= 1e-2 * sc, (lo, hi)
+        assert np.abs(g[lo:hi] - g64[lo:hi]).max() <= 5e-2 * np.abs(g64[lo:hi]).max(), (lo, hi)
+
+
+def test_adam_update():
+    import torch
+    from paper_1502_02935_amd import MlpTrainer
+    rng = np.random.default_rng(5)
+    p0 = rng.normal(size=O.MLP_NPARAM).astype(np.float32)
+    tr = MlpTrainer(_t(p0), lr=1e-2)
+    g = rng.normal(size=O.MLP_NPARAM).astype(np.float32)
+    tr.grad.copy_(_t(g))
+    from paper_1502_02935_amd import _lib as L
+    import ctypes as C
+    from paper_1502_02935_amd.sim import _ptr, _stream
+    for step in (1, 2):
+        L.check(tr.lib.mhd_mlp_adam(_ptr(tr.params), _ptr(tr.m), _ptr(tr.v), _ptr(tr.grad), step,
+                                    1e-2, 0.9, 0.999, 1e-8, _stream(tr.params.device)), "adam")
+    torch.cuda.synchronize()
+    m = np.zeros(O.MLP_NPARAM)
+    v = np.zeros(O.MLP_NPARAM)
+    p = p0.astype(np.float64)
+    for step in (1, 2):
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g * g
+        p = p - 1e-2 * (m / (1 - 0.9 ** step)) / (np.sqrt(v / (1 - 0.999 ** step)) + 1e-8)
+    np.testing.assert_allclose(tr.params.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss():
+    """Fit the outputs of a random teacher network: the MFMA backward and
+    Adam drive the loss down."""
+    import torch
+    from paper_1502_02935_amd import MlpTrainer
+    rng = np.random.default_rng(6)
+    teacher = _params(7, 0.2)
+    x = rng.normal(size=(8192, 32))
+    t = O.mlp_forward(teacher, x)
+    tr = MlpTrainer(_t(_params(8, 0.1)), lr=3e-3)
+    xt, tt = _t(x), _t(t)
+    first = None
+    for it in range(300):
+        loss = float(tr.step(xt, tt).item()) if it % 50 == 0 else tr.step(xt, tt)
+        if it == 0:
+            first = loss
+    torch.cuda.synchronize()
+    last = float(tr.gradient(xt, tt)[1].item())
+    assert last < 0.2 * first, (first, last)
+
+
+def test_coarsen_matches_definition():
+    pb = P.turbulent_ism(32, seed=9)
+    s = gpu_sim(pb)
+    s.step(2)
+    fine = host_state(s)
+    got = [t.cpu().numpy() for t in s.coarsen()]
+    want = O.coarsen(*fine)
+    for g, w in zip(got, want):
+        np.testing.assert_allclose(g, w, rtol=1e-14, atol=1e-15)
+
+
+def test_flux_accumulator_matches_oracle_fluxes():
+    """Sum over steps of dt times the mean fine corrector flux on each
+    coarse face, against the oracle's corrector fluxes."""
+    pb = P.random_smooth((16, 12, 8), seed=10)
+    o = oracle_of(pb)
+    s = gpu_sim(pb)
+    acc = s.flux_accumulator(True)
+    want = np.zeros((3, 7, 4, 6, 8))
+    dts = []
+    for _ in range(2):
+        dt = o.dt()
+        dts.append(dt)
+        o.step(dt)
+        for a in range(3):
+            t1, t2 = (a + 1) % 3, (a + 2) % 3
+            gmap = [0, 1 + a, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2]
+            for m in range(7):
+                F = o.debug_array(8 * a + gmap[m])[2:-3, 2:-3, 2:-3]  # interior faces [z][y][x]
+                F = np.moveaxis(F, (0, 1, 2), (0, 1, 2))
+                # fine face (2I, ...) along a, 2x2 transverse average
+                sl = [slice(None)] * 3
+                sl[2 - a] = slice(0, None, 2)
+                Fa = F[tuple(sl)]
+                ax_t = [2 - t1, 2 - t2]
+                for ax in sorted(ax_t):
+                    shp = list(Fa.shape)
+                    shp[ax:ax + 1] = [shp[ax] // 2, 2]
+                    Fa = Fa.reshape(shp).mean(axis=ax + 1)
+                want[a, m] += dt * Fa
+    s.step(2, dt=dts)
+    got = acc.cpu().numpy()
+    for a in range(3):
+        for m in range(7):
+            sc = np.abs(want[a, m]).max() + 1e-300
+            assert np.abs(got[a, m] - want[a, m]).max() <= 1e-11 * sc, (a, m)
+
+
+def test_samples_match_oracle_features_and_targets():
+    pb = P.random_smooth((16, 12, 10), seed=11)
+    o = oracle_of(pb)
+    s = gpu_sim(pb)
+    dt = o.dt()
+    o.step(dt)
+    s.step(1, dt=dt)
+    rng = np.random.default_rng(12)
+    n = 300
+    faces = np.stack([rng.integers(0, 3, n), rng.integers(0, 16, n), rng.integers(0, 12, n),
+                      rng.integers(0, 10, n)], axis=1).astype(np.int32)
+    import torch
+    acc = torch.as_tensor(rng.normal(0, 1e-3, (3, 7, 10, 12, 16)), dtype=torch.float64,
+                          device="cuda")
+    x, t, m = s.mlp_samples(acc, dt, _t(faces, torch.int32))
+    x, t, m = x.cpu().numpy(), t.cpu().numpy(), m.cpu().numpy()
+    W = [o.debug_array(33 + v) for v in range(8)]
+    accn = acc.cpu().numpy()
+    for b in range(n):
+        a, i, j, k = faces[b]
+        t1, t2 = (a + 1) % 3, (a + 2) % 3
+        w8 = []
+        for c in range(4):
+            idx = [k + 2, j + 2, i + 2]
+            idx[2 - a] += c - 2
+            q = tuple(idx)
+            w8 += [W[0][q], W[1 + a][q], W[1 + t1][q], W[1 + t2][q], W[4][q], W[5 + a][q],
+                   W[5 + t1][q], W[5 + t2][q]]
+        xf = O.mlp_features(np.array(w8), pb.gamma)
+        np.testing.assert_allclose(x[b], xf, rtol=1e-5, atol=1e-6)
+        gmap = [0, 1 + a, 1 + t1, 1 + t2, 4, 5 + t1, 5 + t2]
+        Fc = np.array([o.debug_array(8 * a + gmap[mm])[k + 2, j + 2, i + 2] for mm in range(7)])
+        df = accn[a, :, k, j, i] / dt - Fc
+        yt = O.mlp_flux_to_out(np.array(w8), pb.gamma, df)
+        np.testing.assert_allclose(t[b], yt, rtol=1e-4, atol=1e-5 * (np.abs(yt).max() + 1))
+    assert set(np.unique(m)) <= {0, 1}
+    # invalid faces are flagged, not read
+    bad = _t(np.array([[3, 0, 0, 0], [0, 16, 0, 0], [1, 0, -1, 0]], dtype=np.int32), torch.int32)
+    _, _, mb = s.mlp_samples(acc, dt, bad)
+    assert list(mb.cpu().numpy()) == [2, 2, 2]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_correction_matches_oracle(precision):
+    """A step with the gated, clipped MLP correction in the corrector sweep
+    against the oracle's (FP64, bf16-rounded MLP)."""
+    import torch
+    pb = P.ryu_jones(64) if precision == 0 else P.random_smooth((24, 20, 16), seed=13)
+    pb = P.random_smooth((24, 20, 16), seed=13) if precision == 1 else pb
+    params = _params(14, 0.05).astype(np.float32).astype(np.float64)
+    o = oracle_of(pb)
+    o.set_mlp(params, tau=0.5, jump=0.5)
+    s = gpu_sim(pb, precision=precision)
+    pt = _t(params)
+    s.set_mlp(pt, tau=0.5, jump=0.5)
+    dts = []
+    for _ in range(3):
+        dts.append(o.dt())
+        o.step(dts[-1])
+    s.step(3, dt=dts)
+    err = field_errors(host_state(s), o.get_state())
+    tol = 2e-5 if precision == 0 else 1e-4
+    assert max(err.values()) <= tol, err
+    dg, do = s.diag(), o.diag()
+    assert dg["n_mlp_faces"] > 0
+    assert abs(dg["n_mlp_faces"] - do["n_mlp_faces"]) <= 0.001 * do["n_mlp_faces"]
+    assert dg["n_mlp_gated"] == do["n_mlp_gated"]
