@@ -197,7 +197,7 @@ def gaussian_random_field(rng, n: int, kmin=1.0, kmax=16.0, slope=-4.0) -> np.nd
     filt = np.zeros_like(K)
     sel = (K >= kmin) & (K <= kmax)
     filt[sel] = K[sel] ** (0.5 * slope)
-    g = np.fft.irfftn(F * filt, s=(n, n, n))
+    g = np.fft.irfftn(F * filt, s=(n, n, n), axes=(0, 1, 2))
     g -= g.mean()
     g /= g.std()
     return g

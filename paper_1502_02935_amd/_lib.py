@@ -46,6 +46,7 @@ class mhd_diag_t(C.Structure):
         ("rho_min", C.c_double), ("p_min", C.c_double),
         ("n_floor", C.c_int64), ("n_hll_fallback", C.c_int64),
         ("n_degenerate", C.c_int64), ("n_fp64_recovery", C.c_int64),
+        ("n_mlp_faces", C.c_int64), ("n_mlp_gated", C.c_int64),
         ("status", C.c_uint32), ("pad", C.c_uint32),
     ]
 

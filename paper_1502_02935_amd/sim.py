@@ -98,6 +98,8 @@ class Sim:
         self.L = L.load()
         self.cfg = cfg
         self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         dt = cfg.dtype
         fs = cfg.face_shapes()
