@@ -208,13 +208,15 @@ int mhd_destroy(mhd_ctx *ctx);
    rho_m c_m^3, sqrt(rho_m) c_m^2, Galilean shift by v_m; output 5, the normal
    B, unused).  It is added to the HLLD flux before constrained transport,
    except on faces touching a shock cell (a neighbour's pressure differs by
-   more than `jump` times the cell's and div v < 0), and clipped per component
-   to tau (|F| + a_max |U_R - U_L|). */
+   more than `jump` times the cell's and div v < 0) or whose two-cell means of
+   rho or P are not positive, and clipped per component to
+   tau_flux |F| + tau a_max |U_R - U_L|. */
 #define MHD_MLP_NPARAM 6792
 
 typedef struct mhd_gate {
-  double tau;   /* clip factor, >= 0 (0.5 in the reference setup) */
-  double jump;  /* relative pressure jump marking a shock cell, > 0 (0.5) */
+  double tau;       /* clip factor of the dissipation-scale term a_max |U_R - U_L|, >= 0 */
+  double jump;      /* relative pressure jump marking a shock cell, > 0 */
+  double tau_flux;  /* clip factor of the flux-scale term |F|, >= 0 */
 } mhd_gate;
 
 /* Enables the fused correction in the corrector sweeps (d_params: device

@@ -69,7 +69,7 @@ struct orc_grid {
   int64_t n_floor, n_hll, n_deg;
   /* learned correction of the corrector fluxes */
   double *mlp;            /* NULL = off; else ORC_MLP_NPARAM values */
-  double mlp_tau, mlp_jump;
+  double mlp_tau, mlp_jump, mlp_tau_flux;
   unsigned char *shock;   /* per cell: 1 = shock cell (no correction on its faces) */
   int64_t n_mlp, n_gated;
 };
@@ -512,7 +512,7 @@ orc_grid *orc_create(const orc_config *cfg) {
   return g;
 }
 
-int orc_set_mlp(orc_grid *g, const double *params, double tau, double jump) {
+int orc_set_mlp(orc_grid *g, const double *params, double tau, double jump, double tau_flux) {
   free(g->mlp);
   g->mlp = NULL;
   if (!params) return 0;
@@ -520,6 +520,7 @@ int orc_set_mlp(orc_grid *g, const double *params, double tau, double jump) {
   memcpy(g->mlp, params, sizeof(double) * ORC_MLP_NPARAM);
   g->mlp_tau = tau;
   g->mlp_jump = jump;
+  g->mlp_tau_flux = tau_flux;
   return 0;
 }
 
@@ -680,13 +681,16 @@ static void shock_cells(orc_grid *g) {
 }
 
 /* Learned correction of one corrector face flux f (frame order).  Faces
-   touching a shock cell keep the plain flux; elsewhere each component of
-   the correction is clipped to tau (|F| + a_max |U_R - U_L|). */
+   touching a shock cell keep the plain flux (caller); a face whose two-cell
+   means of rho or P are not positive keeps it too (returns 0); elsewhere each
+   component of the correction is clipped to
+   tau_flux |F| + tau a_max |U_R - U_L|. */
 static int mlp_correct(const orc_grid *g, const double w8[32], const double wl[7],
                        const double wr[7], double bn, double f[7]) {
   double x[32], y[8], df[7], ul[7], ur[7];
   double gam = g->c.gamma;
   int m;
+  if (!(w8[8] + w8[16] > 0.0) || !(w8[12] + w8[20] > 0.0)) return 0;
   orc_mlp_features(w8, gam, x);
   orc_mlp_forward(g->mlp, 1, 1, x, y);
   orc_mlp_out_to_flux(w8, gam, y, df);
@@ -698,7 +702,7 @@ static int mlp_correct(const orc_grid *g, const double w8[32], const double wl[7
   double sr = fabs((wl[1] > wr[1] ? wl[1] : wr[1]) + cmax);
   double amax = sl > sr ? sl : sr;
   for (m = 0; m < 7; ++m) {
-    double lim = g->mlp_tau * (fabs(f[m]) + amax * fabs(ur[m] - ul[m]));
+    double lim = g->mlp_tau_flux * fabs(f[m]) + g->mlp_tau * amax * fabs(ur[m] - ul[m]);
     double d = df[m];
     if (d > lim) d = lim;
     if (d < -lim) d = -lim;
@@ -755,7 +759,10 @@ static void sweep(orc_grid *g, int a, double *const bf[3], int recon) {
               w8[8 * c + 6] = g->w[5 + t1][q];
               w8[8 * c + 7] = g->w[5 + t2][q];
             }
-            nmlp += mlp_correct(g, w8, wl, wr, bf[a][p], f);
+            if (mlp_correct(g, w8, wl, wr, bf[a][p], f))
+              nmlp++;
+            else
+              ngate++;
           }
         }
         g->fl[a][0][p] = f[0];

@@ -158,9 +158,10 @@ void orc_mlp_features(const double w8[32], double gamma, double x[32]);
 void orc_mlp_out_to_flux(const double w8[32], double gamma, const double y[8], double dflux[7]);
 void orc_mlp_flux_to_out(const double w8[32], double gamma, const double dflux[7], double y[8]);
 /* Enables (params != NULL) the gated correction of the corrector fluxes:
-   params holds ORC_MLP_NPARAM values (used with bfloat16 rounding), tau the
-   clip factor, jump the relative pressure jump that marks a shock cell. */
-int orc_set_mlp(orc_grid *g, const double *params, double tau, double jump);
+   params holds ORC_MLP_NPARAM values (used with bfloat16 rounding); each
+   correction component is clipped to tau_flux |F| + tau a_max |U_R - U_L|;
+   jump is the relative pressure jump that marks a shock cell. */
+int orc_set_mlp(orc_grid *g, const double *params, double tau, double jump, double tau_flux);
 
 /* Loops over n faces / stencils of the two functions above (arrays [n][7],
    [n][4], contiguous).  code may be NULL. */

@@ -174,7 +174,7 @@ def load_oracle():
     L.orc_mlp_out_to_flux.argtypes = [dp, C.c_double, dp, dp]
     L.orc_mlp_flux_to_out.argtypes = [dp, C.c_double, dp, dp]
     L.orc_set_mlp.restype = C.c_int
-    L.orc_set_mlp.argtypes = [C.c_void_p, dp, C.c_double, C.c_double]
+    L.orc_set_mlp.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, C.c_double]
     L.orc_recon_batch.argtypes = [C.c_long, dp, C.c_int, C.c_double, dp, dp]
     _lib = L
     return L
@@ -250,15 +250,16 @@ class Oracle:
             "n_mlp_faces": d.n_mlp_faces, "n_mlp_gated": d.n_mlp_gated,
         }
 
-    def set_mlp(self, params, tau: float = 0.5, jump: float = 0.5):
+    def set_mlp(self, params, tau: float = 0.5, jump: float = 0.5, tau_flux: float = 0.0):
         """Enable (params: 6792 values) or disable (None) the learned
-        correction of the corrector fluxes."""
+        correction of the corrector fluxes; clip tau_flux |F| +
+        tau a_max |U_R - U_L| per component."""
         if params is None:
-            self.L.orc_set_mlp(self.h, None, tau, jump)
+            self.L.orc_set_mlp(self.h, None, tau, jump, tau_flux)
             return
         p = _f64(params)
         assert p.shape == (MLP_NPARAM,)
-        self.L.orc_set_mlp(self.h, _ptr(p), tau, jump)
+        self.L.orc_set_mlp(self.h, _ptr(p), tau, jump, tau_flux)
 
     def debug_array(self, what: int) -> np.ndarray:
         """Padded array [nz+5][ny+5][nx+5] of the last corrector stage."""

@@ -55,7 +55,7 @@ MLP_NPARAM = 6792
 
 
 class mhd_gate(C.Structure):
-    _fields_ = [("tau", C.c_double), ("jump", C.c_double)]
+    _fields_ = [("tau", C.c_double), ("jump", C.c_double), ("tau_flux", C.c_double)]
 
 
 class mhd_profile_t(C.Structure):

@@ -158,13 +158,14 @@ struct mhd_ctx {
   uint8_t* shock() const { return (uint8_t*)(ws + L.off_sg + 3 * L.arr8); }
   // learned correction and fine-flux accumulation
   const float* mlp_params = nullptr;
-  double mlp_tau = 0.5, mlp_jump = 0.5;
+  double mlp_tau = 0.5, mlp_jump = 0.5, mlp_tau_flux = 0.0;
   void* flux_acc = nullptr;
   MlpRef mlp_ref() const {
     MlpRef m;
     m.params = mlp_params;
     m.tau = mlp_tau;
     m.jump = mlp_jump;
+    m.tau_flux = mlp_tau_flux;
     m.shock = shock();
     return m;
   }
@@ -564,10 +565,12 @@ int mhd_set_mlp(mhd_ctx* c, const float* d_params, const mhd_gate* gate) {
     c->mlp_params = nullptr;
     return MHD_OK;
   }
-  if (!gate || !(gate->tau >= 0.0) || !(gate->jump > 0.0)) return MHD_E_ARG;
+  if (!gate || !(gate->tau >= 0.0) || !(gate->jump > 0.0) || !(gate->tau_flux >= 0.0))
+    return MHD_E_ARG;
   c->mlp_params = d_params;
   c->mlp_tau = gate->tau;
   c->mlp_jump = gate->jump;
+  c->mlp_tau_flux = gate->tau_flux;
   return MHD_OK;
 }
 

@@ -328,7 +328,8 @@ __global__ void __launch_bounds__(BX* BY_MLP) k_flux_mlp(Geo g, Physics ph, Prim
   wave_mlp_forward(mlp.params, L.X, L.H1, L.H2, L.Y, nullptr, nullptr);
   bool corrected = false, gated = false;
   if (valid) {
-    if (mlp.shock[p - s] || mlp.shock[p]) {
+    const bool means_ok = (w8[8] + w8[16] > 0.f) && (w8[12] + w8[20] > 0.f);
+    if (mlp.shock[p - s] || mlp.shock[p] || !means_ok) {
       gated = true;
     } else {
       float y[8], df[7];
@@ -346,10 +347,10 @@ __global__ void __launch_bounds__(BX* BY_MLP) k_flux_mlp(Geo g, Physics ph, Prim
       const T sl = fabs((Lf.vn < Rf.vn ? Lf.vn : Rf.vn) - cmax);
       const T sr = fabs((Lf.vn > Rf.vn ? Lf.vn : Rf.vn) + cmax);
       const T amax = sl > sr ? sl : sr;
-      const T tau = (T)mlp.tau;
+      const T tau = (T)mlp.tau, tauf = (T)mlp.tau_flux;
 #pragma unroll
       for (int m = 0; m < 7; ++m) {
-        const T lim = tau * (fabs(F[m]) + amax * fabs(ur[m] - ul[m]));
+        const T lim = tauf * fabs(F[m]) + tau * amax * fabs(ur[m] - ul[m]);
         T d = (T)df[m];
         d = d > lim ? lim : (d < -lim ? -lim : d);
         F[m] += d;

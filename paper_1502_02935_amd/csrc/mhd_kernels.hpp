@@ -70,8 +70,9 @@ struct Counters {
 // Learned correction of the corrector fluxes (null params = off).
 struct MlpRef {
   const float* params;  // FP32 master weights, 6792
-  double tau;           // clip factor
+  double tau;           // clip factor of the dissipation-scale term
   double jump;          // relative pressure jump of a shock cell
+  double tau_flux;      // clip factor of the flux-scale term
   uint8_t* shock;       // per padded cell
 };
 

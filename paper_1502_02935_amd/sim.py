@@ -161,9 +161,10 @@ class Sim:
 
     # ---- learned correction ------------------------------------------------
 
-    def set_mlp(self, params=None, tau: float = 0.5, jump: float = 0.5):
+    def set_mlp(self, params=None, tau: float = 0.5, jump: float = 0.5, tau_flux: float = 0.0):
         """Enable the fused correction with FP32 device params [6792] (kept
-        referenced here), or disable it with None."""
+        referenced here), or disable it with None.  Each correction component
+        is clipped to tau_flux |F| + tau a_max |U_R - U_L|."""
         if params is None:
             L.check(self.L.mhd_set_mlp(self.ctx, None, None), "mhd_set_mlp")
             self._mlp = None
@@ -171,7 +172,7 @@ class Sim:
         assert params.dtype == torch.float32 and params.is_contiguous()
         assert params.numel() == L.MLP_NPARAM and params.device == self.device
         self._mlp = params
-        gate = L.mhd_gate(tau, jump)
+        gate = L.mhd_gate(tau, jump, tau_flux)
         L.check(self.L.mhd_set_mlp(self.ctx, _ptr(params), C.byref(gate)), "mhd_set_mlp")
 
     def flux_accumulator(self, enable: bool = True):

@@ -206,10 +206,10 @@ def test_fused_correction_matches_oracle(precision):
     pb = P.brio_wu(64) if precision == 0 else P.random_smooth((24, 20, 16), seed=13)
     params = _params(14, 0.05).astype(np.float32).astype(np.float64)
     o = oracle_of(pb)
-    o.set_mlp(params, tau=0.5, jump=0.5)
+    o.set_mlp(params, tau=0.5, jump=0.5, tau_flux=0.1)
     s = gpu_sim(pb, precision=precision)
     pt = _t(params)
-    s.set_mlp(pt, tau=0.5, jump=0.5)
+    s.set_mlp(pt, tau=0.5, jump=0.5, tau_flux=0.1)
     dts = []
     for _ in range(3):
         dts.append(o.dt())

@@ -113,7 +113,7 @@ def test_corrected_step_conserves_and_keeps_div_b():
     on a periodic box and div_h B stays at rounding level."""
     pb = P.random_smooth((12, 10, 8), seed=6)
     o = oracle_of(pb)
-    o.set_mlp(_params(7, 0.05), tau=0.5, jump=0.5)
+    o.set_mlp(_params(7, 0.05), tau=0.5, jump=0.5, tau_flux=0.5)
     d0 = o.diag()
     c0, *_ = o.get_state()
     for _ in range(5):
@@ -132,7 +132,7 @@ def test_shock_cells_gate_the_correction(make, gated):
     keep the plain flux (Sod, Brio-Wu); the Ryu-Jones jumps are all below
     that threshold."""
     o = oracle_of(make(64))
-    o.set_mlp(_params(8, 0.05), tau=0.5, jump=0.5)
+    o.set_mlp(_params(8, 0.05), tau=0.5, jump=0.5, tau_flux=0.5)
     for _ in range(3):
         o.step()
     d = o.diag()
