@@ -106,23 +106,25 @@ def error_run(pb, nsteps):
                  "fp64_recovery_cell_evals": d32["n_fp64_recovery"]}
 
 
-# Algorithmic work of one flux-sweep launch.  Faces per launch: n+1 along
-# the sweep, n+2 across (one ghost row each side for the corner EMFs).
-# Bytes per face: the 7 face primitives and the face-normal B read once,
-# 7 flux components and the mass-flux sign byte written once.
-# Flops per face, counted on the FP64 oracle over the turbulent-box face
-# states (oracle/count_flops.py): HLLD 400.6, MUSCL of 7 variables 154.0.
-FLUX_BYTES_PER_FACE_FP32 = 8 * 4 + 7 * 4 + 1
+# Algorithmic work of one launch of the flux kernel (all three face
+# families).  Points per launch: (n+2)^3 (cells -1..n on each axis); faces:
+# n+1 along each family's normal, n+2 across (one ghost row each side for
+# the corner EMFs), three families.  Bytes: the 8 primitive arrays read once
+# per point; per face the face-normal B read, 7 flux components and the
+# mass-flux sign byte written.  Flops per face, counted on the FP64 oracle
+# over the turbulent-box face states (oracle/count_flops.py): HLLD 400.6,
+# MUSCL of 7 variables 154.0.
+FLUX_BYTES_PER_POINT_FP32 = 8 * 4
+FLUX_BYTES_PER_FACE_FP32 = 4 + 7 * 4 + 1
 HLLD_FLOPS_PER_FACE = 400.6
 MUSCL_FLOPS_PER_FACE = 154.0
 # Whole step per cell-update (both stages, every part), same count.
 STEP_FLOPS_PER_CELL_UPDATE = 3162.0
 STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
-# Measured HBM traffic (TCC FETCH_SIZE + WRITE_SIZE, calibration factor
-# 1.000) of the flux sweeps at n = 256, mean over x, y, z, valid only for
-# the kernel sources with this hash.
-PROFILED_FLUX = {"sources_sha256_16": "9dba0f083c75bdce", "n": 256,
-                 "bytes_per_launch": 1316.7e6}
+# Measured HBM traffic (TCC FETCH_SIZE + WRITE_SIZE, scaled by the
+# calibration factor of a plain copy) of one flux-kernel launch at n = 256,
+# valid only for the kernel sources with this hash.
+PROFILED_FLUX = {"sources_sha256_16": "unprofiled", "n": 256, "bytes_per_launch": None}
 KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_kernels.hip",
                   "paper_1502_02935_amd/csrc/mhd_physics.hpp",
                   "paper_1502_02935_amd/csrc/mhd_kernels.hpp")
@@ -138,25 +140,25 @@ def kernel_sources_hash():
 
 
 def flux_roofline(n, prof):
-    """Roofline of the flux sweeps (the dominant kernel class): their mean
-    launch time from HIP events over the timed region, algorithmic bytes and
-    flops per launch.  Arithmetic intensity is 6.6 (first order) to 9.1
-    (MUSCL) flop/byte, below the FP32 ridge of 157.3/8 = 19.7: HBM bound."""
-    launches = [prof[k] for k in ("flux_x", "flux_y", "flux_z") if prof.get(k, (0, 0))[1]]
-    tot_ms = sum(v[0] for v in launches)
-    nl = sum(v[1] for v in launches)
-    ms = tot_ms / nl
-    faces = (n + 1) * (n + 2) * (n + 2)
-    byts = faces * FLUX_BYTES_PER_FACE_FP32
+    """Roofline of the flux kernel (the dominant kernel): its mean launch time
+    from HIP events over the timed region, algorithmic bytes and flops per
+    launch.  Arithmetic intensity about 9.1 (first order) to 12.6 (MUSCL)
+    flop/byte, below the FP32 ridge of 157.3/8 = 19.7: HBM bound by the
+    published peaks."""
+    ms_tot, nl = prof["flux"]
+    ms = ms_tot / nl
+    points = (n + 2) ** 3
+    faces = 3 * (n + 1) * (n + 2) * (n + 2)
+    byts = points * FLUX_BYTES_PER_POINT_FP32 + faces * FLUX_BYTES_PER_FACE_FP32
     flops = faces * (HLLD_FLOPS_PER_FACE + 0.5 * MUSCL_FLOPS_PER_FACE)  # mean of both stages
     ach = byts / (ms * 1e-3) / 1e9
     traffic = None
     if kernel_sources_hash() == PROFILED_FLUX["sources_sha256_16"] and n == PROFILED_FLUX["n"]:
         traffic = PROFILED_FLUX["bytes_per_launch"]
-    return {"kernel": "k_flux (x, y, z sweeps; first-order and MUSCL + HLLD)", "bound": "hbm",
-            "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-            "traffic": traffic, "ms_per_launch": ms, "bytes_per_launch": byts,
-            "faces_per_launch": faces,
+    return {"kernel": "k_flux (x, y and z faces in one launch; first-order and MUSCL + HLLD)",
+            "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "ms_per_launch": ms,
+            "bytes_per_launch": byts, "faces_per_launch": faces,
             "alu_view": {"flops_per_launch": flops,
                          "achieved_tflops": flops / (ms * 1e-3) / 1e12,
                          "peak_tflops": PEAK_FP32_TFLOPS,

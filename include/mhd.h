@@ -168,10 +168,13 @@ int mhd_debug_array(mhd_ctx *ctx, int what, void *d_out, size_t *n_out);
 /* Kernel classes timed by the profiling hook. */
 enum {
   MHD_K_GHOSTS = 0,
-  MHD_K_PRIM = 1,
-  MHD_K_FLUX_X = 2,
-  MHD_K_FLUX_Y = 3,
-  MHD_K_FLUX_Z = 4,
+  MHD_K_PRIM = 1,     /* primitives; in a step that computes its own dt also the
+                         CFL candidates of the start-of-step state and their
+                         reduction to dt */
+  MHD_K_FLUX = 2,     /* fluxes of all three face families, one launch */
+  MHD_K_FLUX_MLP = 3, /* corrector flux sweeps with the learned correction,
+                         one launch per axis */
+  MHD_K_SHOCK = 4,    /* shock cells of the corrector state (learned runs) */
   MHD_K_EMF = 5,
   MHD_K_UPDATE = 6,
   MHD_K_CFL = 7,

@@ -34,6 +34,7 @@ struct Layout {
   size_t off_cnt;   // event counter slots
   size_t off_cfl;   // cfl partials
   size_t off_diag;  // diag partials
+  size_t off_frag;  // learned correction: weights packed as bf16 MFMA fragments
   size_t total;
 };
 
@@ -97,7 +98,8 @@ Layout layout_of(const mhd_config* c) {
   L.off_cfl = L.off_cnt + align_up((size_t)kNumCounters * kCounterSlots * kCounterStride *
                                    sizeof(unsigned long long));
   L.off_diag = L.off_cfl + align_up((size_t)cfl_blocks(g) * sizeof(double));
-  L.total = L.off_diag + align_up((size_t)diag_blocks(g) * 16 * sizeof(double));
+  L.off_frag = L.off_diag + align_up((size_t)diag_blocks(g) * 16 * sizeof(double));
+  L.total = L.off_frag + align_up((size_t)kMlpFragBytes);
   return L;
 }
 
@@ -135,7 +137,7 @@ struct mhd_ctx {
       ev_kind.push_back(0);
     }
     ev_kind[ev_used] = kind;
-    hipEventRecord(ev_pool[ev_used], st);
+    (void)hipEventRecord(ev_pool[ev_used], st);
     ++ev_used;
   }
   // fold the recorded intervals into the per-class sums (after a sync)
@@ -151,7 +153,7 @@ struct mhd_ctx {
     ev_used = 0;
   }
   ~mhd_ctx() {
-    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
   void* arr(int q) const { return ws + L.off_t + (size_t)q * L.arr; }
   int8_t* sg(int a) const { return (int8_t*)(ws + L.off_sg + (size_t)a * L.arr8); }
@@ -167,11 +169,13 @@ struct mhd_ctx {
     m.jump = mlp_jump;
     m.tau_flux = mlp_tau_flux;
     m.shock = shock();
+    m.frags = frags();
     return m;
   }
   double* misc() const { return (double*)(ws + L.off_misc); }
   double* cfl_part() const { return (double*)(ws + L.off_cfl); }
   double* diag_part() const { return (double*)(ws + L.off_diag); }
+  unsigned* frags() const { return (unsigned*)(ws + L.off_frag); }
   unsigned long long* counter_slots() const { return (unsigned long long*)(ws + L.off_cnt); }
   Counters counters() const {
     Counters c;
@@ -242,6 +246,7 @@ Muscl<T> muscl_of(int recon, double kappa) {
 Physics physics_of(const mhd_config* c) {
   Physics ph;
   ph.gamma = c->gamma;
+  ph.igm1 = 1.0 / (c->gamma - 1.0);
   ph.cfl = c->cfl;
   ph.source = c->source;
   for (int q = 0; q < 4; ++q) ph.src[q] = c->src[q];
@@ -273,13 +278,15 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   const Edge<T> E = c->edge<T>();
   const Muscl<T> first = muscl_of<T>(MHD_RECON_FIRST, c->cfg.kappa);
   const Muscl<T> second = muscl_of<T>(c->cfg.recon, c->cfg.kappa);
-  // predictor: first-order fluxes of U^n, half step into U*
+  // predictor: first-order fluxes of U^n, half step into U*; a step that
+  // takes its dt from the device gets it from the same primitives pass
   c->mark(MHD_K_PRIM);
-  launch_prim<T>(g, c->ph, U, W, cnt, c->st);
-  for (int a = 0; a < 3; ++a) {
-    c->mark(MHD_K_FLUX_X + a);
-    launch_flux<T>(g, c->ph, a, W, U.b[a], F, first, cnt, c->st);
-  }
+  if (dt.ptr)
+    launch_prim_cfl<T>(g, c->ph, U, W, c->cfl_part(), c->misc() + M_DT, cnt, c->st);
+  else
+    launch_prim<T>(g, c->ph, U, W, cnt, c->st);
+  c->mark(MHD_K_FLUX);
+  launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, W, F, E, c->st);
   DtRef half = dt;
@@ -292,15 +299,17 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->mark(MHD_K_PRIM);
   launch_prim<T>(g, c->ph, Us, W, cnt, c->st);
   if (c->mlp_params) {
-    c->mark(MHD_K_OTHER);
+    c->mark(MHD_K_SHOCK);
     launch_shock<T>(g, W, c->shock(), c->mlp_jump, c->st);
-  }
-  for (int a = 0; a < 3; ++a) {
-    c->mark(MHD_K_FLUX_X + a);
-    if (c->mlp_params)
+    // the caller may change the weights between steps: repack every step
+    launch_mlp_pack(c->mlp_params, c->frags(), c->st);
+    for (int a = 0; a < 3; ++a) {
+      c->mark(MHD_K_FLUX_MLP);
       launch_flux_mlp<T>(g, c->ph, a, W, Us.b[a], F, second, cnt, c->mlp_ref(), c->st);
-    else
-      launch_flux<T>(g, c->ph, a, W, Us.b[a], F, second, cnt, c->st);
+    }
+  } else {
+    c->mark(MHD_K_FLUX);
+    launch_flux<T>(g, c->ph, W, Us, F, second, cnt, c->st);
   }
   if (c->flux_acc) {
     c->mark(MHD_K_OTHER);
@@ -417,13 +426,10 @@ int mhd_step(mhd_ctx* c, const double* dt_host, int nsteps) {
       dt.value = 0.0;
       dt.ptr = c->misc() + M_DT;
     }
-    if (c->cfg.precision == MHD_FP64) {
-      if (!dt_host) enqueue_cfl<double>(c);
+    if (c->cfg.precision == MHD_FP64)
       enqueue_step<double>(c, dt);
-    } else {
-      if (!dt_host) enqueue_cfl<float>(c);
+    else
       enqueue_step<float>(c, dt);
-    }
   }
   return hip_status();
 }

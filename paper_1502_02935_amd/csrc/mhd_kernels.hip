@@ -34,6 +34,71 @@ static dim3 grid_for(int nx, int ny, int nz) {
   return dim3((unsigned)((nx + BX - 1) / BX), (unsigned)((ny + BY - 1) / BY), (unsigned)nz);
 }
 
+// ------------------------------------------------------------------------
+// Sweep geometry.  A sweep visits the points lo..hi (inclusive, per axis) of
+// the padded grid.  Each z-plane's rows lo_y..hi_y are walked as one run of
+// whole padded x-rows (row stride sy), kSpanThreads points per block, so a
+// wave's 64 lanes always touch 64 consecutive addresses and only the few
+// padding columns outside lo_x..hi_x idle (a 64-wide tiling of the x-rows
+// alone leaves a mostly empty fifth wave on every row of a 256-wide box).
+// Blocks are renumbered so that each XCD -- the hardware deals blocks out
+// round-robin, block b to XCD b mod 8 -- walks a contiguous range of planes
+// and finds its neighbour planes in its own L2.
+// ------------------------------------------------------------------------
+
+constexpr int kSpanThreads = 256;
+
+struct Span {
+  int lo[3], hi[3];
+  int per_plane;  // sy * (hi_y - lo_y + 1)
+  int bpp;        // blocks per plane
+  int nblk;
+  float inv_sy, inv_bpp;
+};
+
+static Span make_span(const Geo& g, int ilo, int ihi, int jlo, int jhi, int klo, int khi) {
+  Span s;
+  s.lo[0] = ilo, s.hi[0] = ihi, s.lo[1] = jlo, s.hi[1] = jhi, s.lo[2] = klo, s.hi[2] = khi;
+  s.per_plane = g.sy * (jhi - jlo + 1);
+  s.bpp = (s.per_plane + kSpanThreads - 1) / kSpanThreads;
+  s.nblk = s.bpp * (khi - klo + 1);
+  s.inv_sy = 1.0f / (float)g.sy;
+  s.inv_bpp = 1.0f / (float)s.bpp;
+  return s;
+}
+
+static dim3 span_grid(const Span& s) { return dim3((unsigned)s.nblk); }
+
+// q = floor(a / d) for 0 <= a < 2^23 from a float estimate, corrected to
+// exact in integer arithmetic.
+__device__ __forceinline__ int div_small(int a, int d, float inv_d) {
+  int q = (int)(((float)a + 0.5f) * inv_d);
+  if (q * d > a) --q;
+  else if ((q + 1) * d <= a) ++q;
+  return q;
+}
+
+struct Pt {
+  int i, j, k, p;
+  bool valid;
+};
+
+__device__ __forceinline__ Pt span_point(const Geo& g, const Span& s) {
+  const unsigned nb = (unsigned)s.nblk, b0 = blockIdx.x;
+  const unsigned q = nb >> 3, r = nb & 7u, x = b0 & 7u;
+  const int b = (int)(x * q + (x < r ? x : r) + (b0 >> 3));
+  const int plane = div_small(b, s.bpp, s.inv_bpp);
+  const int t = (b - plane * s.bpp) * kSpanThreads + (int)threadIdx.x;
+  const int row = div_small(t, g.sy, s.inv_sy);
+  Pt o;
+  o.i = t - row * g.sy - NG;
+  o.j = s.lo[1] + row;
+  o.k = s.lo[2] + plane;
+  o.valid = t < s.per_plane && o.i >= s.lo[0] && o.i <= s.hi[0];
+  o.p = pidx(g, o.i, o.j, o.k);
+  return o;
+}
+
 // Count lanes with `flag` set into the counter's slot of this block, with
 // one atomic per wave.  Must be reached by every lane of the wave.
 __device__ __forceinline__ void wave_count(bool flag, unsigned long long* ctr) {
@@ -167,21 +232,88 @@ __device__ __forceinline__ T pressure(T gam, T rho, T mx, T my, T mz, T E, T b0x
   return (gam - T(1)) * eint;
 }
 
+// ------------------------------------------------------------------------
+// Block reductions (256 threads = 4 waves of 64): wave shuffles, then the
+// four wave results in fixed order.  Deterministic for a fixed launch.
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Time-step candidate of one interior cell from its conserved state: the
+// smallest dx_a / (|v_a| + c_f,a) over the three axes, in FP64 (the
+// start-of-step state of a step that computes its own dt).  A non-finite
+// value, rho <= 0 or P <= 0 sets the sticky status bit and gives +inf.
 template <class T>
-__global__ void __launch_bounds__(BX* BY) k_prim(Geo g, Physics ph, Cons<T> s, Prim<T> w,
-                                                 Counters cnt) {
-  const int i = blockIdx.x * BX + threadIdx.x - NG;
-  const int j = blockIdx.y * BY + threadIdx.y - NG;
-  const int k = blockIdx.z - NG;
-  const bool valid = i <= g.n[0] + NG - 1 && j <= g.n[1] + NG - 1;
+__device__ __forceinline__ double cfl_cell(const Geo& g, const Physics& ph, T rho_, T mx_, T my_,
+                                           T mz_, T E_, T b0x, T b1x, T b0y, T b1y, T b0z, T b1z,
+                                           unsigned* status) {
+  const double rho = rho_, mx = mx_, my = my_, mz = mz_, E = E_;
+  const double bc[3] = {0.5 * ((double)b0x + (double)b1x), 0.5 * ((double)b0y + (double)b1y),
+                        0.5 * ((double)b0z + (double)b1z)};
+  const double ke = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+  const double me = 0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
+  const double P = (ph.gamma - 1.0) * (E - ke - me);
+  const double v[3] = {mx / rho, my / rho, mz / rho};
+  const bool ok = rho > 0.0 && P > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
+                  isfinite(mz) && isfinite(bc[0]) && isfinite(bc[1]) && isfinite(bc[2]);
+  if (!ok) {
+    atomicOr(status, 1u);
+    return INFINITY;
+  }
+  double r = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double cf = fast_speed<double>(rho, P, bc[a], bc[(a + 1) % 3], bc[(a + 2) % 3],
+                                         ph.gamma);
+    const double t = g.d[a] / (fabs(v[a]) + cf);
+    r = t < r ? t : r;
+  }
+  return r;
+}
+
+// Block minimum of r (kSpanThreads threads) into part[blockIdx.x].
+__device__ __forceinline__ void block_min_to(double r, double* part) {
+  __shared__ double red[kSpanThreads / 64];
+  r = wave_min(r);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int q = 1; q < kSpanThreads / 64; ++q) m = fmin(m, red[q]);
+    part[blockIdx.x] = m;
+  }
+}
+
+// CFL = true: the interior cells also give their time-step candidates,
+// folded per block into part[] (the step's own dt, from the same loads).
+template <class T, bool CFL>
+__global__ void __launch_bounds__(kSpanThreads) k_prim(Geo g, Physics ph, Span sp, Cons<T> s,
+                                                       Prim<T> w, Counters cnt, double* part) {
+  const Pt pt = span_point(g, sp);
   bool rec = false;
-  if (valid) {
-    const int p = pidx(g, i, j, k);
+  double r = INFINITY;
+  if (pt.valid) {
+    const int p = pt.p;
     const T gam = (T)ph.gamma;
     const T rho = s.u[0][p], mx = s.u[1][p], my = s.u[2][p], mz = s.u[3][p], E = s.u[4][p];
+    const T b0x = s.b[0][p], b1x = s.b[0][p + 1], b0y = s.b[1][p], b1y = s.b[1][p + g.sy];
+    const T b0z = s.b[2][p], b1z = s.b[2][p + g.sz];
     T bcx, bcy, bcz;
-    const T P = pressure(gam, rho, mx, my, mz, E, s.b[0][p], s.b[0][p + 1], s.b[1][p],
-                         s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz], bcx, bcy, bcz, rec);
+    const T P = pressure(gam, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, bcx, bcy, bcz, rec);
     const T ir = rcp(rho);
     const T vx = mx * ir, vy = my * ir, vz = mz * ir;
     w.w[0][p] = rho;
@@ -195,67 +327,116 @@ __global__ void __launch_bounds__(BX* BY) k_prim(Geo g, Physics ph, Cons<T> s, P
     w.ec[0][p] = vz * bcy - vy * bcz;
     w.ec[1][p] = vx * bcz - vz * bcx;
     w.ec[2][p] = vy * bcx - vx * bcy;
+    if constexpr (CFL) {
+      if (pt.i >= 0 && pt.i < g.n[0] && pt.j >= 0 && pt.j < g.n[1] && pt.k >= 0 && pt.k < g.n[2])
+        r = cfl_cell<T>(g, ph, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, cnt.status);
+    }
   }
   if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);
+  if constexpr (CFL) block_min_to(r, part);
+}
+
+static Span prim_span(const Geo& g) {
+  return make_span(g, -NG, g.n[0] + NG - 1, -NG, g.n[1] + NG - 1, -NG, g.n[2] + NG - 1);
 }
 
 template <class T>
 void launch_prim(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_prim<T>, grid_for(g.n[0] + 2 * NG, g.n[1] + 2 * NG, g.n[2] + 2 * NG),
-                     dim3(BX, BY), 0, st, g, ph, s, w, c);
+  const Span sp = prim_span(g);
+  hipLaunchKernelGGL((k_prim<T, false>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s,
+                     w, c, nullptr);
 }
 
 // ------------------------------------------------------------------------
-// Flux sweep along axis A: faces 0..n_A along A, rows -1..n across (the
-// boundary edges' EMFs need one ghost row of transverse fluxes).
+// Fluxes of all three face families in one sweep.  The point p of cell
+// (i, j, k) carries the faces at the lower x, y and z sides of that cell;
+// the sweep visits i, j, k in -1..n and computes the A-face wherever the
+// A-index is >= 0 (faces 0..n along A, rows -1..n across it: the boundary
+// edges' EMFs need one ghost row of transverse fluxes).  One launch instead
+// of three per-axis sweeps: the A-stencils of neighbouring points overlap,
+// so the primitives are fetched from HBM about once instead of three times.
+// Addressing: buffer loads and stores, a 32-bit byte offset per stencil
+// point shared by all arrays (no 64-bit address arithmetic per access), each
+// array's resource bounded by its size.
 // ------------------------------------------------------------------------
 
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, unsigned bytes) {
+  // word 3 0x00020000: 32-bit data format, the untyped-buffer setting of gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bld(float, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bld(double, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bst(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+// Flux of the A-face at point p: limited reconstruction (Eq. 12-14) of the
+// seven face variables from cells p - 2s .. p + s, HLLD, the sign of the
+// mass flux.  Returns the HLLD branch code (bit 0 HLL, bit 1 degenerate).
 template <class T, int A>
-__global__ void __launch_bounds__(BX* BY) k_flux(Geo g, Physics ph, Prim<T> w,
-                                                 const T* __restrict__ bn, Flux<T> f,
-                                                 Muscl<T> mu, Counters cnt) {
+__device__ __forceinline__ int face_flux(const Physics& ph, int stride, unsigned bytes,
+                                         const Prim<T>& w, const T* __restrict__ bn,
+                                         const Flux<T>& f, const Muscl<T>& mu, int p) {
   constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
-  const int i = blockIdx.x * BX + threadIdx.x + (A == 0 ? 0 : -1);
-  const int j = blockIdx.y * BY + threadIdx.y + (A == 1 ? 0 : -1);
-  const int k = blockIdx.z + (A == 2 ? 0 : -1);
-  const bool valid = i <= g.n[0] && j <= g.n[1];
-  int code = 0;
-  if (valid) {
-    const int p = pidx(g, i, j, k);
-    const int s = stride_of(g, A);
-    const T* __restrict__ src[7] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2],
-                                    w.w[4], w.w[5 + A1], w.w[5 + A2]};
-    T l[7], r[7];
+  const unsigned s = (unsigned)stride * (unsigned)sizeof(T);
+  const unsigned o = (unsigned)p * (unsigned)sizeof(T);
+  const T* src[7] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2], w.w[4], w.w[5 + A1], w.w[5 + A2]};
+  T l[7], r[7];
 #pragma unroll
-    for (int v = 0; v < 7; ++v) {
-      const T* q = src[v];
-      muscl_lr(mu, q[p - 2 * s], q[p - s], q[p], q[p + s], l[v], r[v]);
-    }
-    const Face<T> L{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
-    const Face<T> R{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
-    T F[7];
-    code = hlld(L, R, bn[p], (T)ph.gamma, F);
-#pragma unroll
-    for (int m = 0; m < 7; ++m) f.f[A][m][p] = F[m];
-    f.sg[A][p] = (int8_t)(F[0] > T(0) ? 1 : (F[0] < T(0) ? -1 : 0));
+  for (int v = 0; v < 7; ++v) {
+    const auto q = rsrc(src[v], bytes);
+    muscl_lr(mu, bld(T(), q, o - 2 * s), bld(T(), q, o - s), bld(T(), q, o), bld(T(), q, o + s),
+             l[v], r[v]);
   }
-  wave_count((code & 1) != 0, cnt.hll);
-  wave_count((code & 2) != 0, cnt.deg);
+  const Face<T> L{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
+  const Face<T> R{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+  T F[7];
+  const int code = hlld(L, R, bld(T(), rsrc(bn, bytes), o), (T)ph.gamma, (T)ph.igm1, F);
+#pragma unroll
+  for (int m = 0; m < 7; ++m) bst(F[m], rsrc(f.f[A][m], bytes), o);
+  const int sg = F[0] > T(0) ? 1 : (F[0] < T(0) ? -1 : 0);
+  __builtin_amdgcn_raw_buffer_store_b8((unsigned char)sg, rsrc(f.sg[A], bytes / sizeof(T)),
+                                       (unsigned)p, 0, 0);
+  return code;
 }
 
 template <class T>
-void launch_flux(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
-                 Muscl<T> m, Counters c, hipStream_t st) {
-  int r[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
-  r[axis] = g.n[axis] + 1;
-  const dim3 gr = grid_for(r[0], r[1], r[2]);
-  if (axis == 0)
-    hipLaunchKernelGGL((k_flux<T, 0>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
-  else if (axis == 1)
-    hipLaunchKernelGGL((k_flux<T, 1>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
-  else
-    hipLaunchKernelGGL((k_flux<T, 2>), gr, dim3(BX, BY), 0, st, g, ph, w, bn, f, m, c);
+__global__ void __launch_bounds__(kSpanThreads) k_flux(Geo g, Physics ph, Span sp, Prim<T> w,
+                                                       const T* __restrict__ bx,
+                                                       const T* __restrict__ by,
+                                                       const T* __restrict__ bz, Flux<T> f,
+                                                       Muscl<T> mu, Counters cnt) {
+  const Pt pt = span_point(g, sp);
+  int cx = 0, cy = 0, cz = 0;
+  if (pt.valid) {
+    const unsigned bytes = (unsigned)g.np * (unsigned)sizeof(T);
+    if (pt.i >= 0) cx = face_flux<T, 0>(ph, 1, bytes, w, bx, f, mu, pt.p);
+    if (pt.j >= 0) cy = face_flux<T, 1>(ph, g.sy, bytes, w, by, f, mu, pt.p);
+    if (pt.k >= 0) cz = face_flux<T, 2>(ph, g.sz, bytes, w, bz, f, mu, pt.p);
+  }
+  wave_count((cx & 1) != 0, cnt.hll);
+  wave_count((cy & 1) != 0, cnt.hll);
+  wave_count((cz & 1) != 0, cnt.hll);
+  wave_count((cx & 2) != 0, cnt.deg);
+  wave_count((cy & 2) != 0, cnt.deg);
+  wave_count((cz & 2) != 0, cnt.deg);
+}
+
+template <class T>
+void launch_flux(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f, Muscl<T> m,
+                 Counters c, hipStream_t st) {
+  const Span sp = make_span(g, -1, g.n[0], -1, g.n[1], -1, g.n[2]);
+  hipLaunchKernelGGL(k_flux<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, w, s.b[0],
+                     s.b[1], s.b[2], f, m, c);
 }
 
 // ------------------------------------------------------------------------
@@ -267,35 +448,32 @@ void launch_flux(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Fl
 // (so constrained transport sees the corrected B fluxes).
 // ------------------------------------------------------------------------
 
-constexpr int BY_MLP = 2;
-
 struct MlpWaveLds {
   unsigned short X[64 * kXs];
-  unsigned short H1[64 * kHs];
-  unsigned short H2[64 * kHs];
   float Y[64 * 8];
 };
 
 template <class T, int A>
-__global__ void __launch_bounds__(BX* BY_MLP) k_flux_mlp(Geo g, Physics ph, Prim<T> w,
-                                                         const T* __restrict__ bn, Flux<T> f,
-                                                         Muscl<T> mu, Counters cnt, MlpRef mlp) {
-  __shared__ MlpWaveLds lds[BY_MLP];
-  MlpWaveLds& L = lds[threadIdx.y];
+__global__ void __launch_bounds__(kSpanThreads) k_flux_mlp(Geo g, Physics ph, Span sp,
+                                                           Prim<T> w, const T* __restrict__ bn,
+                                                           Flux<T> f, Muscl<T> mu, Counters cnt,
+                                                           MlpRef mlp) {
+  __shared__ MlpWaveLds lds[kSpanThreads / 64];
+  MlpWaveLds& L = lds[threadIdx.x >> 6];
   constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
-  const int lane = threadIdx.x;
-  const int i = blockIdx.x * BX + threadIdx.x + (A == 0 ? 0 : -1);
-  const int j = blockIdx.y * BY_MLP + threadIdx.y + (A == 1 ? 0 : -1);
-  const int k = blockIdx.z + (A == 2 ? 0 : -1);
-  const bool valid = i <= g.n[0] && j <= g.n[1];
+  const int lane = threadIdx.x & 63;
+  const Pt pt = span_point(g, sp);
+  const bool valid = pt.valid;
   const int s = stride_of(g, A);
-  const int p = valid ? pidx(g, i, j, k) : 0;
+  const int p = valid ? pt.p : 0;
   int code = 0;
   T F[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
   Face<T> Lf{}, Rf{};
-  float w8[32];
+  FaceScale sc{};
+  bool means_ok = false;
   const float gam = (float)ph.gamma;
   if (valid) {
+    float w8[32];
     const T* __restrict__ src[8] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2],
                                     w.w[4], w.w[5 + A], w.w[5 + A1], w.w[5 + A2]};
     T st4[8][4];
@@ -315,9 +493,11 @@ __global__ void __launch_bounds__(BX* BY_MLP) k_flux_mlp(Geo g, Physics ph, Prim
     }
     Lf = Face<T>{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
     Rf = Face<T>{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
-    code = hlld(Lf, Rf, bn[p], (T)ph.gamma, F);
+    code = hlld(Lf, Rf, bn[p], (T)ph.gamma, (T)ph.igm1, F);
     float x[32];
-    face_features(w8, face_scale(w8, gam), x);
+    means_ok = (w8[8] + w8[16] > 0.f) && (w8[12] + w8[20] > 0.f);
+    sc = face_scale(w8, gam);
+    face_features(w8, sc, x);
 #pragma unroll
     for (int c = 0; c < 32; ++c) L.X[lane * kXs + c] = bf16_bits(x[c]);
   } else {
@@ -325,19 +505,19 @@ __global__ void __launch_bounds__(BX* BY_MLP) k_flux_mlp(Geo g, Physics ph, Prim
     for (int c = 0; c < 32; ++c) L.X[lane * kXs + c] = 0;
   }
   __syncthreads();
-  wave_mlp_forward(mlp.params, L.X, L.H1, L.H2, L.Y, nullptr, nullptr);
+  wave_mlp_infer((const u32x2*)mlp.frags, mlp.params, L.X, L.Y);
+  __syncthreads();
   bool corrected = false, gated = false;
   if (valid) {
-    const bool means_ok = (w8[8] + w8[16] > 0.f) && (w8[12] + w8[20] > 0.f);
     if (mlp.shock[p - s] || mlp.shock[p] || !means_ok) {
       gated = true;
     } else {
       float y[8], df[7];
 #pragma unroll
       for (int o = 0; o < 8; ++o) y[o] = L.Y[lane * 8 + o];
-      out_to_flux(face_scale(w8, gam), y, df);
+      out_to_flux(sc, y, df);
       const T b = bn[p];
-      const T igm1 = T(1) / ((T)ph.gamma - T(1));
+      const T igm1 = (T)ph.igm1;
       T ul[7], fl[7], ur[7], fr[7];
       cons_flux(Lf, b, igm1, ul, fl);
       cons_flux(Rf, b, igm1, ur, fr);
@@ -370,29 +550,27 @@ __global__ void __launch_bounds__(BX* BY_MLP) k_flux_mlp(Geo g, Physics ph, Prim
 template <class T>
 void launch_flux_mlp(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
                      Muscl<T> m, Counters c, MlpRef mlp, hipStream_t st) {
-  int r[3] = {g.n[0] + 2, g.n[1] + 2, g.n[2] + 2};
-  r[axis] = g.n[axis] + 1;
-  const dim3 gr((unsigned)((r[0] + BX - 1) / BX), (unsigned)((r[1] + BY_MLP - 1) / BY_MLP),
-                (unsigned)r[2]);
-  const dim3 bl(BX, BY_MLP);
+  // faces 0..n along the axis, rows -1..n across it
+  const Span sp = make_span(g, axis == 0 ? 0 : -1, g.n[0], axis == 1 ? 0 : -1, g.n[1],
+                            axis == 2 ? 0 : -1, g.n[2]);
+  const dim3 gr = span_grid(sp), bl(kSpanThreads);
   if (axis == 0)
-    hipLaunchKernelGGL((k_flux_mlp<T, 0>), gr, bl, 0, st, g, ph, w, bn, f, m, c, mlp);
+    hipLaunchKernelGGL((k_flux_mlp<T, 0>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
   else if (axis == 1)
-    hipLaunchKernelGGL((k_flux_mlp<T, 1>), gr, bl, 0, st, g, ph, w, bn, f, m, c, mlp);
+    hipLaunchKernelGGL((k_flux_mlp<T, 1>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
   else
-    hipLaunchKernelGGL((k_flux_mlp<T, 2>), gr, bl, 0, st, g, ph, w, bn, f, m, c, mlp);
+    hipLaunchKernelGGL((k_flux_mlp<T, 2>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
 }
 
 // Shock cells of the stage state on cells [-1, n]^3: some neighbour's
 // pressure differs by more than `jump` times the cell's and the central
 // divergence of v is negative.
 template <class T>
-__global__ void __launch_bounds__(BX* BY) k_shock(Geo g, Prim<T> w, uint8_t* shock, double jump) {
-  const int i = blockIdx.x * BX + threadIdx.x - 1;
-  const int j = blockIdx.y * BY + threadIdx.y - 1;
-  const int k = blockIdx.z - 1;
-  if (i > g.n[0] || j > g.n[1]) return;
-  const int p = pidx(g, i, j, k);
+__global__ void __launch_bounds__(kSpanThreads) k_shock(Geo g, Span sp, Prim<T> w, uint8_t* shock,
+                                                        double jump) {
+  const Pt pt = span_point(g, sp);
+  if (!pt.valid) return;
+  const int p = pt.p;
   const int st[3] = {1, g.sy, g.sz};
   const T P = w.w[4][p];
   T jmax = T(0), div = T(0);
@@ -408,8 +586,8 @@ __global__ void __launch_bounds__(BX* BY) k_shock(Geo g, Prim<T> w, uint8_t* sho
 
 template <class T>
 void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, hipStream_t st) {
-  hipLaunchKernelGGL(k_shock<T>, grid_for(g.n[0] + 2, g.n[1] + 2, g.n[2] + 2), dim3(BX, BY), 0, st,
-                     g, w, shock, jump);
+  const Span sp = make_span(g, -1, g.n[0], -1, g.n[1], -1, g.n[2]);
+  hipLaunchKernelGGL(k_shock<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, sp, w, shock, jump);
 }
 
 // ------------------------------------------------------------------------
@@ -447,21 +625,20 @@ __device__ __forceinline__ void corner(const Geo& g, const Prim<T>& w, const Flu
 }
 
 template <class T>
-__global__ void __launch_bounds__(BX* BY) k_emf(Geo g, Prim<T> w, Flux<T> f, Edge<T> e) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i > g.n[0] || j > g.n[1]) return;
-  const int p = pidx(g, i, j, k);
-  if (i < g.n[0]) corner<T, 0>(g, w, f, e, p);
-  if (j < g.n[1]) corner<T, 1>(g, w, f, e, p);
-  if (k < g.n[2]) corner<T, 2>(g, w, f, e, p);
+__global__ void __launch_bounds__(kSpanThreads) k_emf(Geo g, Span sp, Prim<T> w, Flux<T> f,
+                                                      Edge<T> e) {
+  const Pt pt = span_point(g, sp);
+  if (!pt.valid) return;
+  const int p = pt.p;
+  if (pt.i < g.n[0]) corner<T, 0>(g, w, f, e, p);
+  if (pt.j < g.n[1]) corner<T, 1>(g, w, f, e, p);
+  if (pt.k < g.n[2]) corner<T, 2>(g, w, f, e, p);
 }
 
 template <class T>
 void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st) {
-  hipLaunchKernelGGL(k_emf<T>, grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1), dim3(BX, BY), 0, st,
-                     g, w, f, e);
+  const Span sp = make_span(g, 0, g.n[0], 0, g.n[1], 0, g.n[2]);
+  hipLaunchKernelGGL(k_emf<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, sp, w, f, e);
 }
 
 // ------------------------------------------------------------------------
@@ -489,15 +666,14 @@ __device__ __forceinline__ void grad_phi(const Physics& ph, double x, double y, 
 }
 
 template <class T>
-__global__ void __launch_bounds__(BX* BY) k_update(Geo g, Physics ph, Cons<T> s0, Cons<T> s1,
-                                                   Prim<T> w, Flux<T> f, Edge<T> e, DtRef dtr) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
-  const bool valid = i <= g.n[0] && j <= g.n[1];
-  if (valid) {
+__global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span sp, Cons<T> s0,
+                                                         Cons<T> s1, Prim<T> w, Flux<T> f,
+                                                         Edge<T> e, DtRef dtr) {
+  const Pt pt = span_point(g, sp);
+  const int i = pt.i, j = pt.j, k = pt.k;
+  if (pt.valid) {
     const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
-    const int p = pidx(g, i, j, k);
+    const int p = pt.p;
     const int cc[3] = {i, j, k};
     const int st[3] = {1, g.sy, g.sz};
 #pragma unroll
@@ -549,13 +725,12 @@ __global__ void __launch_bounds__(BX* BY) k_update(Geo g, Physics ph, Cons<T> s0
 // of the updated faces.  A pass of its own, after every face of the stage
 // has been written.
 template <class T>
-__global__ void __launch_bounds__(BX* BY) k_floors(Geo g, Physics ph, Cons<T> s, Counters cnt) {
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
+__global__ void __launch_bounds__(kSpanThreads) k_floors(Geo g, Physics ph, Span sp, Cons<T> s,
+                                                         Counters cnt) {
+  const Pt pt = span_point(g, sp);
   bool hit = false;
-  if (i < g.n[0] && j < g.n[1]) {
-    const int p = pidx(g, i, j, k);
+  if (pt.valid) {
+    const int p = pt.p;
     T rho = s.u[0][p];
     if (rho < (T)ph.rho_floor) {
       rho = (T)ph.rho_floor;
@@ -580,32 +755,13 @@ __global__ void __launch_bounds__(BX* BY) k_floors(Geo g, Physics ph, Cons<T> s,
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Flux<T> f, Edge<T> e, DtRef dt, Counters c, hipStream_t st) {
-  hipLaunchKernelGGL(k_update<T>, grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1), dim3(BX, BY), 0,
-                     st, g, ph, s0, s1, w, f, e, dt);
-  if (ph.rho_floor > 0.0 || ph.p_floor > 0.0)
-    hipLaunchKernelGGL(k_floors<T>, grid_for(g.n[0], g.n[1], g.n[2]), dim3(BX, BY), 0, st, g, ph,
-                       s1, c);
-}
-
-// ------------------------------------------------------------------------
-// Block reductions (256 threads = 4 waves of 64): wave shuffles, then the
-// four wave results in fixed order.  Deterministic for a fixed launch.
-// ------------------------------------------------------------------------
-
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  const Span sp = make_span(g, 0, g.n[0], 0, g.n[1], 0, g.n[2]);
+  hipLaunchKernelGGL(k_update<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s0, s1, w,
+                     f, e, dt);
+  if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
+    const Span si = make_span(g, 0, g.n[0] - 1, 0, g.n[1] - 1, 0, g.n[2] - 1);
+    hipLaunchKernelGGL(k_floors<T>, span_grid(si), dim3(kSpanThreads), 0, st, g, ph, si, s1, c);
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -614,71 +770,72 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ------------------------------------------------------------------------
 
 template <class T>
-__global__ void __launch_bounds__(BX* BY) k_cfl(Geo g, Physics ph, Cons<T> s, double* part,
-                                                Counters cnt) {
-  __shared__ double red[BY];
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
+__global__ void __launch_bounds__(kSpanThreads) k_cfl(Geo g, Physics ph, Span sp, Cons<T> s,
+                                                      double* part, Counters cnt) {
+  const Pt pt = span_point(g, sp);
   double r = INFINITY;
-  if (i < g.n[0] && j < g.n[1]) {
-    const int p = pidx(g, i, j, k);
-    const double rho = s.u[0][p];
-    const double mx = s.u[1][p], my = s.u[2][p], mz = s.u[3][p], E = s.u[4][p];
-    const double bc[3] = {0.5 * ((double)s.b[0][p] + (double)s.b[0][p + 1]),
-                          0.5 * ((double)s.b[1][p] + (double)s.b[1][p + g.sy]),
-                          0.5 * ((double)s.b[2][p] + (double)s.b[2][p + g.sz])};
-    const double ke = 0.5 * (mx * mx + my * my + mz * mz) / rho;
-    const double me = 0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
-    const double P = (ph.gamma - 1.0) * (E - ke - me);
-    const double v[3] = {mx / rho, my / rho, mz / rho};
-    const bool ok = rho > 0.0 && P > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
-                    isfinite(mz) && isfinite(bc[0]) && isfinite(bc[1]) && isfinite(bc[2]);
-    if (!ok) atomicOr(cnt.status, 1u);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double cf = fast_speed<double>(rho, P, bc[a], bc[(a + 1) % 3], bc[(a + 2) % 3],
-                                           ph.gamma);
-      const double t = g.d[a] / (fabs(v[a]) + cf);
-      r = t < r ? t : r;
-    }
-    if (!ok) r = INFINITY;
+  if (pt.valid) {
+    const int p = pt.p;
+    r = cfl_cell<T>(g, ph, s.u[0][p], s.u[1][p], s.u[2][p], s.u[3][p], s.u[4][p], s.b[0][p],
+                    s.b[0][p + 1], s.b[1][p], s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz],
+                    cnt.status);
   }
-  r = wave_min(r);
-  if (threadIdx.x == 0) red[threadIdx.y] = r;
-  __syncthreads();
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
-    double m = red[0];
-    for (int q = 1; q < BY; ++q) m = fmin(m, red[q]);
-    part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = m;
-  }
+  block_min_to(r, part);
 }
 
-__global__ void k_cfl_final(const double* part, int nb, double cfl, double* dt_out) {
+// Minimum of the per-block partials in two passes: kCflReduce blocks each
+// fold a contiguous share into out[block]; then one block folds those and
+// scales by the Courant number.  (One block walking every partial is
+// latency bound: ~90 us for the 65k partials of a 256^3 box.)
+constexpr int kCflReduce = 64;
+
+__global__ void __launch_bounds__(256) k_cfl_reduce(const double* part, int nb, double* out) {
   __shared__ double red[4];
+  const int share = (nb + kCflReduce - 1) / kCflReduce;
+  const int lo = blockIdx.x * share, hi = min(nb, lo + share);
   double m = INFINITY;
-  for (int q = threadIdx.x; q < nb; q += blockDim.x) m = fmin(m, part[q]);
+  for (int q = lo + (int)threadIdx.x; q < hi; q += 256) m = fmin(m, part[q]);
   m = wave_min(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = red[0];
-    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = fmin(r, red[q]);
-    *dt_out = cfl * r;
-  }
+  if (threadIdx.x == 0) out[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+__global__ void __launch_bounds__(64) k_cfl_final(const double* part, double cfl, double* dt_out) {
+  double m = part[threadIdx.x];
+  m = wave_min(m);
+  if (threadIdx.x == 0) *dt_out = cfl * m;
+}
+
+static Span cfl_span(const Geo& g) {
+  return make_span(g, 0, g.n[0] - 1, 0, g.n[1] - 1, 0, g.n[2] - 1);
 }
 
 int cfl_blocks(const Geo& g) {
-  const dim3 gr = grid_for(g.n[0], g.n[1], g.n[2]);
-  return (int)(gr.x * gr.y * gr.z);
+  const int nb = cfl_span(g).nblk, np = prim_span(g).nblk;
+  return (nb > np ? nb : np) + kCflReduce;
+}
+
+template <class T>
+void launch_prim_cfl(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, double* part,
+                     double* dt_out, Counters c, hipStream_t st) {
+  const Span sp = prim_span(g);
+  hipLaunchKernelGGL((k_prim<T, true>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s, w,
+                     c, part);
+  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, sp.nblk,
+                     part + sp.nblk);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + sp.nblk, ph.cfl, dt_out);
 }
 
 template <class T>
 void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
                 Counters c, hipStream_t st) {
-  hipLaunchKernelGGL(k_cfl<T>, grid_for(g.n[0], g.n[1], g.n[2]), dim3(BX, BY), 0, st, g, ph, s,
-                     part, c);
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, st, part, cfl_blocks(g), ph.cfl, dt_out);
+  static_assert(kCflReduce == 64, "k_cfl_final folds one wave");
+  const Span sp = cfl_span(g);
+  hipLaunchKernelGGL(k_cfl<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s, part, c);
+  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, sp.nblk,
+                     part + sp.nblk);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + sp.nblk, ph.cfl, dt_out);
 }
 
 __global__ void k_advance_time(double* t, long long* step, DtRef dtr) {
@@ -859,8 +1016,8 @@ void launch_gather(const Geo& g, Cons<T> s, T* cell5, T* bx, T* by, T* bz, hipSt
 // ------------------------------------------------------------------------
 
 template <class T>
-__global__ void k_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T gam, T* flux,
-                             int8_t* code) {
+__global__ void k_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T gam, T igm1,
+                             T* flux, int8_t* code) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const T* a = wl + 7 * t;
@@ -868,7 +1025,7 @@ __global__ void k_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T
   const Face<T> L{a[0], a[1], a[2], a[3], a[4], a[5], a[6]};
   const Face<T> R{b[0], b[1], b[2], b[3], b[4], b[5], b[6]};
   T F[7];
-  const int c = hlld(L, R, bn[t], gam, F);
+  const int c = hlld(L, R, bn[t], gam, igm1, F);
 #pragma unroll
   for (int m = 0; m < 7; ++m) flux[7 * t + m] = F[m];
   if (code) code[t] = (int8_t)c;
@@ -878,8 +1035,9 @@ template <class T>
 void launch_hlld_batch(int64_t n, const T* wl, const T* wr, const T* bn, T gam, T* flux,
                        int8_t* code, hipStream_t st) {
   if (n <= 0) return;
+  const T igm1 = (T)(1.0 / ((double)gam - 1.0));
   hipLaunchKernelGGL(k_hlld_batch<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, wl,
-                     wr, bn, gam, flux, code);
+                     wr, bn, gam, igm1, flux, code);
 }
 
 template <class T>
@@ -905,7 +1063,9 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_ghosts<T>(const Geo&, const Physics&, Cons<T>, hipStream_t);              \
   template void launch_prim<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,           \
                                hipStream_t);                                                     \
-  template void launch_flux<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>, Muscl<T>,  \
+  template void launch_prim_cfl<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, double*,        \
+                                   double*, Counters, hipStream_t);                              \
+  template void launch_flux<T>(const Geo&, const Physics&, Prim<T>, Cons<T>, Flux<T>, Muscl<T>,  \
                                Counters, hipStream_t);                                           \
   template void launch_emf<T>(const Geo&, Prim<T>, Flux<T>, Edge<T>, hipStream_t);              \
   template void launch_flux_mlp<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>,        \

@@ -69,7 +69,8 @@ struct Counters {
 
 // Learned correction of the corrector fluxes (null params = off).
 struct MlpRef {
-  const float* params;  // FP32 master weights, 6792
+  const float* params;    // FP32 master weights, 6792 (biases read from here)
+  const unsigned* frags;  // the weights packed as bf16 MFMA fragments (launch_mlp_pack)
   double tau;           // clip factor of the dissipation-scale term
   double jump;          // relative pressure jump of a shock cell
   double tau_flux;      // clip factor of the flux-scale term
@@ -78,6 +79,7 @@ struct MlpRef {
 
 struct Physics {
   double gamma;
+  double igm1;  // 1 / (gamma - 1)
   double cfl;
   int source;
   double src[4];
@@ -98,9 +100,15 @@ void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, hipStream_t st);
 template <class T>
 void launch_prim(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
                  hipStream_t st);
+// Primitives plus the per-block CFL candidates of the interior cells,
+// reduced to dt_out (= cfl x min): the start of a step with its own dt.
 template <class T>
-void launch_flux(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
-                 Muscl<T> m, Counters c, hipStream_t st);
+void launch_prim_cfl(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, double* part,
+                     double* dt_out, Counters c, hipStream_t st);
+// Fluxes of all three face families (normal B from the face arrays of s).
+template <class T>
+void launch_flux(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f, Muscl<T> m,
+                 Counters c, hipStream_t st);
 template <class T>
 void launch_flux_mlp(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
                      Muscl<T> m, Counters c, MlpRef mlp, hipStream_t st);
@@ -111,7 +119,8 @@ void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Flux<T> f, Edge<T> e, DtRef dt, Counters c, hipStream_t st);
-// CFL: per-block minima into part (size cfl_blocks(g)), then dt_out = cfl min.
+// CFL: per-block minima into part (size cfl_blocks(g), which also fits the
+// partials of launch_prim_cfl), then dt_out = cfl min.
 int cfl_blocks(const Geo& g);
 template <class T>
 void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
@@ -137,6 +146,10 @@ void launch_mlp_forward(int64_t n, const float* x, const float* P, float* y, hip
 size_t mlp_grad_workspace(int64_t n);
 void launch_mlp_grad(int64_t n, const float* x, const float* t, const float* P, float* grad,
                      float* loss, float* part, hipStream_t st);
+// Packs the weights of P into the bf16 fragments read by the fused sweep
+// (frags: kMlpFragBytes bytes).
+constexpr int kMlpFragBytes = 28 * 64 * 8;
+void launch_mlp_pack(const float* P, unsigned* frags, hipStream_t st);
 void launch_mlp_adam(float* P, float* m, float* v, const float* g, int64_t step, double lr,
                      double b1, double b2, double eps, hipStream_t st);
 template <class T>

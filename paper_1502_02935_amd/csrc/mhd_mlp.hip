@@ -53,6 +53,30 @@ __global__ void __launch_bounds__(64) k_mlp_forward(int64_t n, const float* __re
     for (int o = 0; o < 8; ++o) y[b * 8 + o] = s.Y[threadIdx.x * 8 + o];
 }
 
+// Weights of P as the bf16 A fragments of wave_mlp_infer: block f packs
+// fragment f, lane l the 4 weights that lane l holds.
+__global__ void __launch_bounds__(64) k_mlp_pack(const float* __restrict__ P, u32x2* W) {
+  const int f = blockIdx.x, lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+  int off, K, M, mb, kb;
+  if (f < kFragW2) {
+    off = kP_W1, K = kMlpIn, M = kMlpHid, mb = f / 2, kb = f % 2;
+  } else if (f < kFragW3) {
+    off = kP_W2, K = kMlpHid, M = kMlpHid, mb = (f - kFragW2) / 4, kb = (f - kFragW2) % 4;
+  } else {
+    off = kP_W3, K = kMlpHid, M = kMlpOut, mb = 0, kb = f - kFragW3;
+  }
+  const int row = 16 * mb + r, col = 16 * kb + 4 * q;
+  unsigned v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = row < M ? bf16_bits(P[off + row * K + col + i]) : 0u;
+  W[f * 64 + lane] = u32x2{v[0] | (v[1] << 16), v[2] | (v[3] << 16)};
+}
+
+void launch_mlp_pack(const float* P, unsigned* frags, hipStream_t st) {
+  static_assert(kMlpFragBytes == kFragBytes, "fragment buffer size");
+  hipLaunchKernelGGL(k_mlp_pack, dim3(kNumFrags), dim3(64), 0, st, P, (u32x2*)frags);
+}
+
 // Sum over the 64 samples (rows) of a [64][64] FP32 LDS matrix, column =
 // lane.
 __device__ __forceinline__ float col_sum(const float* m, int ld) {

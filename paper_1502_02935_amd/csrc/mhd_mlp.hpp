@@ -44,12 +44,38 @@ __device__ __forceinline__ float bf16_float(unsigned short b) {
 }
 __device__ __forceinline__ float bf16_round(float x) { return bf16_float(bf16_bits(x)); }
 
-__device__ __forceinline__ float gelu(float x) {
-  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+// Normal CDF Phi(x) = (1 + erf(x / sqrt 2)) / 2 from the Chebyshev-fitted
+// erfc of Numerical Recipes (2nd ed., section 6.2; fractional error below
+// 1.2e-7 for every argument), taken at |x| so that both tails keep their
+// relative accuracy: Phi = 1 - erfc(|x|/sqrt 2)/2 for x >= 0, else
+// erfc(|x|/sqrt 2)/2.  About 16 vector instructions against some 50 for the
+// library erff; GELU's 128 evaluations per face dominate the MLP's cost.
+__device__ __forceinline__ float norm_cdf(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  const float e = 0.5f * t * __expf(fmaf(-z, z, p));
+  return x >= 0.0f ? 1.0f - e : e;
 }
+
+// GELU(x) = x Phi(x) and its derivative Phi(x) + x phi(x).
+__device__ __forceinline__ float gelu(float x) { return x * norm_cdf(x); }
 __device__ __forceinline__ float gelu_d(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
-         x * __expf(-0.5f * x * x) * 0.39894228040143268f;
+  return norm_cdf(x) + x * __expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// Hardware round-to-nearest-even conversion (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ unsigned short bf16_hw(float x) {
+  return __builtin_bit_cast(unsigned short, (__bf16)x);
 }
 
 __device__ __forceinline__ bf16x4 pack4(unsigned short a, unsigned short b, unsigned short c,
@@ -134,6 +160,75 @@ __device__ __forceinline__ void wave_mlp_forward(const float* __restrict__ P,
   __syncthreads();
 }
 
+// ---- inference with the activations kept in registers ------------------
+// Each layer is computed transposed, H^T = W X^T: the weights are the A
+// operand (M = outputs, K = inputs), the samples the B operand (N).  The D
+// fragment of output block mb then holds, in lane (r, q), features
+// 16 mb + 4q .. 4q+3 of sample r -- exactly the B fragment of the next
+// layer's input block kb = mb, so hidden activations never leave the
+// registers: bias, GELU and the bf16 rounding happen in place.
+//
+// Weights are pre-packed (k_mlp_pack, from the FP32 master vector) as bf16
+// A fragments: fragment f holds, in lane l = r + 16 q, W[16 mb + r]
+// [16 kb + 4q .. 4q+3] (8 bytes), stored [f][64 lanes] so that one wave
+// fetches a fragment with one coalesced 512-byte load.  Rows beyond a
+// layer's outputs (W3 has 8) are zero.
+constexpr int kFragW1 = 0;             // mb 0..3 x kb 0..1
+constexpr int kFragW2 = kFragW1 + 8;   // mb 0..3 x kb 0..3
+constexpr int kFragW3 = kFragW2 + 16;  // mb 0 x kb 0..3
+constexpr int kNumFrags = kFragW3 + 4;
+constexpr int kFragBytes = kNumFrags * 64 * 8;
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ bf16x4 frag_of(const u32x2* __restrict__ W, int f, int lane) {
+  return __builtin_bit_cast(bf16x4, W[f * 64 + lane]);
+}
+
+// bias + GELU of the 4 D values of a lane, rounded to bf16 in place.
+__device__ __forceinline__ bf16x4 act4(f32x4 d, const float* __restrict__ b) {
+  return pack4(bf16_hw(gelu(d[0] + b[0])), bf16_hw(gelu(d[1] + b[1])),
+               bf16_hw(gelu(d[2] + b[2])), bf16_hw(gelu(d[3] + b[3])));
+}
+
+// y = MLP(x) for the 64 samples of a wave.  X: LDS bf16 [64][kXs] (row =
+// sample); Y: LDS float [64][8].  Wave-local: the caller orders the LDS
+// writes of X before, and the reads of Y after, with barriers.
+__device__ __forceinline__ void wave_mlp_infer(const u32x2* __restrict__ W,
+                                               const float* __restrict__ P,
+                                               const unsigned short* X, float* Y) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll 1
+  for (int sb = 0; sb < 4; ++sb) {
+    const unsigned short* xr = X + (sb * 16 + r) * kXs + 4 * q;
+    const bf16x4 x0 = *(const bf16x4*)(xr), x1 = *(const bf16x4*)(xr + 16);
+    bf16x4 h1[4], h2[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma16(frag_of(W, kFragW1 + 2 * mb, lane), x0, acc);
+      acc = mfma16(frag_of(W, kFragW1 + 2 * mb + 1, lane), x1, acc);
+      h1[mb] = act4(acc, P + kP_B1 + 16 * mb + 4 * q);
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) acc = mfma16(frag_of(W, kFragW2 + 4 * mb + kb, lane), h1[kb], acc);
+      h2[mb] = act4(acc, P + kP_B2 + 16 * mb + 4 * q);
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc = mfma16(frag_of(W, kFragW3 + kb, lane), h2[kb], acc);
+    if (q < 2) {
+      float* y = Y + (sb * 16 + r) * 8 + 4 * q;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[i] = acc[i] + P[kP_B3 + 4 * q + i];
+    }
+  }
+}
+
 // ---- face features and the output <-> flux maps ------------------------
 // w8 = rho, vn, vt1, vt2, P, Bn, Bt1, Bt2 of cells i-2 .. i+1 (face i-1/2),
 // cell-centred, face-normal frame.  Face means rho_m, v_m, P_m of cells i-1,
@@ -148,8 +243,8 @@ __device__ __forceinline__ FaceScale face_scale(const float w8[32], float gam) {
   FaceScale s;
   s.rm = 0.5f * (w8[8] + w8[16]);
   for (int d = 0; d < 3; ++d) s.vm[d] = 0.5f * (w8[9 + d] + w8[17 + d]);
-  s.cm = sqrtf(gam * 0.5f * (w8[12] + w8[20]) / s.rm);
-  s.sr = sqrtf(s.rm);
+  s.cm = __builtin_amdgcn_sqrtf(gam * 0.5f * (w8[12] + w8[20]) / s.rm);
+  s.sr = __builtin_amdgcn_sqrtf(s.rm);
   return s;
 }
 

@@ -10,8 +10,8 @@
 // (the Bn flux is identically zero, Eq. 3).
 //
 // Divisions are grouped so that each denominator is inverted once.  In FP32
-// the reciprocal is the hardware v_rcp_f32 (1 ulp); in FP64 it is the
-// correctly rounded 1/x.
+// the reciprocal and the square root are the hardware v_rcp_f32 and
+// v_sqrt_f32 (1 ulp each); in FP64 both are correctly rounded.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +28,17 @@ constexpr double kDegenerate = 1.0e-3;
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float root(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double root(double x) { return sqrt(x); }
+// q = sqrt(x) and iq = 1/sqrt(x): in FP32 from the hardware v_rsq_f32.
+__device__ __forceinline__ void root_pair(float x, float& q, float& iq) {
+  iq = __builtin_amdgcn_rsqf(x);
+  q = x * iq;
+}
+__device__ __forceinline__ void root_pair(double x, double& q, double& iq) {
+  q = sqrt(x);
+  iq = 1.0 / q;
+}
 
 template <class T>
 struct Face {
@@ -76,7 +87,7 @@ __device__ __forceinline__ T fast_speed(T d, T p, T bn, T bt1, T bt2, T gam) {
   const T bt2s = (bt1 * bt1 + bt2 * bt2) * id;
   const T b2 = bt2s + bn * bn * id;
   const T q = a2 - b2;
-  return sqrt(T(0.5) * ((a2 + b2) + sqrt(q * q + T(4) * a2 * bt2s)));
+  return root(T(0.5) * ((a2 + b2) + root(q * q + T(4) * a2 * bt2s)));
 }
 
 // Conserved vector and physical flux (Eq. 3) of a face state; igm1 =
@@ -140,11 +151,11 @@ __device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T
   return r;
 }
 
-// HLLD flux.  Returns bit0 if the HLL flux was used (S_M outside
-// (S_L, S_R)), bit1 if a star state was degenerate.
+// HLLD flux (igm1 = 1/(gamma - 1)).  Returns bit0 if the HLL flux was used
+// (S_M outside (S_L, S_R)), bit1 if a star state was degenerate.
 template <class T>
-__device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T gam, T f[7]) {
-  const T igm1 = rcp(gam - T(1));
+__device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T gam, T igm1,
+                                    T f[7]) {
   T ul[7], fl[7], ur[7], fr[7];
   cons_flux(L, bn, igm1, ul, fl);
   cons_flux(R, bn, igm1, ur, fr);
@@ -179,10 +190,12 @@ __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T 
   int deg = 0;
   const Star<T> sl = star_side(L, ul[4], bn, SL, SM, pts, deg);
   const Star<T> sr = star_side(R, ur[4], bn, SR, SM, pts, deg);
-  const T ql = sqrt(sl.d), qr = sqrt(sr.d);
+  T ql, qr, iql, iqr;
+  root_pair(sl.d, ql, iql);
+  root_pair(sr.d, qr, iqr);
   const T abn = fabs(bn);
-  const T SsL = SM - abn * rcp(ql);
-  const T SsR = SM + abn * rcp(qr);
+  const T SsL = SM - abn * iql;
+  const T SsR = SM + abn * iqr;
   const bool left = SM >= T(0);
   const Star<T> s = left ? sl : sr;
   const T S = left ? SL : SR;

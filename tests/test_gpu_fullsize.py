@@ -1,0 +1,70 @@
+"""Parity at full size: the 256^3 periodic turbulent-ISM box in the
+configuration the benchmark times (FP32 bulk; and the FP64 path), checked on
+sampled outputs.  The GPU advances the whole box; the oracle advances 48^3
+boxes cut out around seeded sample points (outflow sides) with the same time
+steps, and the cells and faces 14 or more cells in from a cut box's sides
+(untouched by its ghost data after 4 steps: the step's stencil reaches 3
+cells) are compared element by element."""
+import numpy as np
+import pytest
+
+from mhd_inputs import problems as P
+from tests import subbox
+from tests.gpu_util import field_errors, gpu_sim, host_state, l1_rel, needs_gpu
+from tests.helpers import oracle_of
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+N = 256
+STEPS = 4
+DT = 1.5e-4  # below the box's CFL step
+M, MARGIN = 48, 14
+
+
+@pytest.fixture(scope="module")
+def turbulent():
+    return P.turbulent_ism(N, seed=1)
+
+
+def _samples(seed=7, k=4):
+    rng = np.random.default_rng(seed)
+    return [tuple(int(v) for v in rng.integers(0, N, 3)) for _ in range(k)]
+
+
+def _run(pb, precision):
+    s = gpu_sim(pb, precision=precision)
+    s.step(STEPS, dt=[DT] * STEPS)
+    d = s.diag()
+    g = host_state(s)
+    s.close()
+    out = []
+    for lo in _samples():
+        o = oracle_of(subbox.cut(pb, lo, M))
+        for _ in range(STEPS):
+            o.step(DT)
+        ref = subbox.core(o.get_state(), lo, M, MARGIN)
+        got = subbox.core(g, lo, M, MARGIN, full=(N, N, N))
+        out.append((lo, got, ref))
+    return d, out
+
+
+def test_fullsize_fp64_sampled(turbulent):
+    d, out = _run(turbulent, 0)
+    assert d["status"] == 0
+    for lo, got, ref in out:
+        err = field_errors(got, ref)
+        assert max(err.values()) <= 1e-11, (lo, err)
+
+
+def test_fullsize_fp32_sampled(turbulent):
+    """FP32 bulk from the FP32-rounded state against the FP64 oracle from the
+    same state: per-field L1 <= 1e-6 relative, max <= 1e-4 of the field
+    scale (4 steps; the 100-step whole-box figure is the benchmark's)."""
+    pb = turbulent.astype("float32")
+    d, out = _run(pb, 1)
+    assert d["status"] == 0
+    for lo, got, ref in out:
+        err = field_errors(got, ref)
+        assert max(err.values()) <= 1e-4, (lo, err)
+        assert l1_rel(got[0][0], ref[0][0]) <= 1e-6, lo
+        assert l1_rel(got[0][4], ref[0][4]) <= 1e-6, lo

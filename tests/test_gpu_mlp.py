@@ -222,3 +222,27 @@ def test_fused_correction_matches_oracle(precision):
     assert dg["n_mlp_faces"] > 0
     assert abs(dg["n_mlp_faces"] - do["n_mlp_faces"]) <= 0.001 * do["n_mlp_faces"]
     assert dg["n_mlp_gated"] == do["n_mlp_gated"]
+
+
+def test_trained_network_beats_plain_coarse():
+    """What the trained network gains: on a held-out turbulent box (seed 205,
+    not used in training), 40 fine 256^3 steps against 20 coarse 128^3 steps
+    from the coarse-grained start, forced to the fine pair-summed steps.  The
+    learned coarse run is closer to the coarse-grained fine run than the
+    plain coarse run (L1 of rho and E at least 5 % lower), stays physical,
+    and runs faster than the fine run in fine-equivalent cell-updates/s."""
+    import os
+
+    import torch
+
+    from paper_1502_02935_amd import learned
+
+    w = os.path.join(os.path.dirname(learned.__file__), "weights", "mlp_turbulent256.npy")
+    params = torch.as_tensor(np.load(w), dtype=torch.float32, device="cuda")
+    r = learned.evaluate(P.turbulent_ism(256, seed=205), params, pairs=20, tau=0.1, jump=0.5)
+    pl, le = r["plain"], r["learned"]
+    assert pl["status"] == 0 and le["status"] == 0
+    assert le["mlp_faces"] > 0
+    for f in ("rho", "E"):
+        assert le["L1"][f] <= 0.95 * pl["L1"][f], (f, le["L1"], pl["L1"])
+    assert le["fine_equivalent_cell_updates_per_s"] > r["fine_cell_updates_per_s"]
