@@ -121,10 +121,12 @@ MUSCL_FLOPS_PER_FACE = 154.0
 # Whole step per cell-update (both stages, every part), same count.
 STEP_FLOPS_PER_CELL_UPDATE = 3162.0
 STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
-# Measured HBM traffic (TCC FETCH_SIZE + WRITE_SIZE, scaled by the
-# calibration factor of a plain copy) of one flux-kernel launch at n = 256,
-# valid only for the kernel sources with this hash.
-PROFILED_FLUX = {"sources_sha256_16": "unprofiled", "n": 256, "bytes_per_launch": None}
+# Measured HBM traffic of one flux-kernel launch at n = 256 (2 x TCC
+# FETCH_SIZE + WRITE_SIZE: a plain 1 GiB copy reads as 512 MiB of
+# FETCH_SIZE and 1 GiB of WRITE_SIZE), valid only for the kernel sources
+# with this hash.
+PROFILED_FLUX = {"sources_sha256_16": "e74632a9a8e14a90", "n": 256,
+                 "bytes_per_launch": 3.454e9}
 KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_kernels.hip",
                   "paper_1502_02935_amd/csrc/mhd_physics.hpp",
                   "paper_1502_02935_amd/csrc/mhd_kernels.hpp")

@@ -197,6 +197,45 @@ def evaluate(problem, params, pairs: int, precision=L.MHD_FP32, tau=0.5, jump=0.
     return out
 
 
+def default_weights() -> str:
+    """The network trained on the 256^3 turbulent boxes (seeds 100-109)."""
+    import os
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                        "mlp_turbulent256.npy")
+
+
+def time_coarse(problem, params, steps: int, tau=0.1, jump=0.5, dt=1e-4, warmup=5,
+                device="cuda"):
+    """Step time of the plain and the learned coarse run (2x coarse-graining
+    of `problem`), same fixed dt, with the per-kernel-class profile."""
+    fcfg = config_from_problem(problem, precision=L.MHD_FP32)
+    fine = Sim(fcfg, problem.cell5, problem.bx, problem.by, problem.bz, device=device)
+    c0 = fine.coarsen()
+    fine.close()
+    ccfg = coarse_config(fcfg)
+    out = {"coarse_cells": ccfg.nx * ccfg.ny * ccfg.nz, "steps": steps, "dt": dt}
+    for name, mlp in (("plain", None), ("learned", params)):
+        c = Sim(ccfg, *[x.clone() for x in c0], device=device)
+        if mlp is not None:
+            c.set_mlp(mlp, tau=tau, jump=jump)
+        c.step(warmup, dt=dt)
+        torch.cuda.synchronize()
+        c.profile(True)
+        t0 = time.perf_counter()
+        c.step(steps, dt=dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = c.profile_get()
+        c.profile(False)
+        d = c.diag(check=False)
+        out[name] = {"ms_per_step": 1e3 * el / steps, "status": d["status"],
+                     "kernel_ms_per_launch": {k: v[0] / v[1] for k, v in prof.items() if v[1]},
+                     "launches_per_step": {k: v[1] / steps for k, v in prof.items() if v[1]}}
+        c.close()
+    out["learned_over_plain"] = out["learned"]["ms_per_step"] / out["plain"]["ms_per_step"]
+    return out
+
+
 def _seeds(s: str):
     if "-" in s:
         a, b = s.split("-")
@@ -228,11 +267,22 @@ def main(argv=None):
                     help="comma list of tau or tau:tau_flux clip settings to evaluate")
     ap.add_argument("--tau-flux", type=float, default=0.0)
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--time-coarse", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS plain and learned coarse steps (weights: --params-in "
+                         "or the shipped ones) on the first evaluation seed")
     a = ap.parse_args(argv)
 
     def log(*m):
         print(*m, file=sys.stderr, flush=True)
 
+    if a.time_coarse:
+        params = torch.as_tensor(np.load(a.params_in or default_weights()), dtype=torch.float32,
+                                 device="cuda")
+        sd = _seeds(a.eval_seeds)[0]
+        r = time_coarse(P.turbulent_ism(a.n, seed=sd).astype("float32"), params, a.time_coarse,
+                        tau=a.tau)
+        print(json.dumps(r))
+        return
     if a.params_in:
         params = torch.as_tensor(np.load(a.params_in), dtype=torch.float32, device="cuda")
         res = {"params_in": a.params_in, "eval": {}}

@@ -5,9 +5,10 @@ counter runs) of this library into a short text table.
     python -m paper_1502_02935_amd.profile_summary trace  <kernel_trace.csv>
     python -m paper_1502_02935_amd.profile_summary counter <counter_collection.csv> [copy_bytes]
 
-The counter mode reports per-kernel average KiB per dispatch (the counters
-are in KiB), and if copy_bytes is given, the ratio of the plain copy kernel's
-reading to its known traffic (the scale factor for the others).
+The counter mode reports the per-kernel average of every counter per
+dispatch (FETCH_SIZE and WRITE_SIZE are in KiB), and, for a single-counter
+run with copy_bytes given, the ratio of the plain copy kernel's reading to
+its known traffic (the scale factor for the others).
 """
 from __future__ import annotations
 
@@ -42,15 +43,16 @@ def trace(path):
 
 def counter(path, copy_bytes=None):
     rows = list(csv.DictReader(open(path)))
-    per = collections.defaultdict(list)
-    cname = None
+    per = collections.OrderedDict()
     for r in rows:
-        cname = r["Counter_Name"]
-        per[r["Kernel_Name"][:40]].append(float(r["Counter_Value"]))
-    print("counter %s (KiB per dispatch)" % cname)
-    print("%-40s %8s %14s" % ("kernel", "calls", "avg_KiB"))
-    for k, v in per.items():
-        print("%-40s %8d %14.1f" % (k, len(v), sum(v) / len(v)))
+        per.setdefault(r["Counter_Name"], collections.OrderedDict()).setdefault(
+            r["Kernel_Name"][:40], []).append(float(r["Counter_Value"]))
+    for cname, ks in per.items():
+        print("counter %s (per dispatch%s)" % (cname, "; KiB" if "SIZE" in cname else ""))
+        print("%-40s %8s %16s" % ("kernel", "calls", "average"))
+        for k, v in ks.items():
+            print("%-40s %8d %16.1f" % (k, len(v), sum(v) / len(v)))
+    per = next(iter(per.values())) if len(per) == 1 else {}
     if copy_bytes:
         for k, v in per.items():
             if "elementwise" in k or "copy" in k.lower():
