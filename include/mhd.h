@@ -228,18 +228,22 @@ typedef struct mhd_gate {
 int mhd_set_mlp(mhd_ctx *ctx, const float *d_params, const mhd_gate *gate);
 
 /* While d_acc is non-NULL, every step adds dt times the mean corrector flux
-   over the 2x2 fine faces tiling each face of the 2x-coarsened grid:
-   d_acc [3][7][nz/2][ny/2][nx/2] (context precision; components in the face
-   frame rho, Mn, Mt1, Mt2, E, Bt1, Bt2).  The caller zeroes it.  Needs even
-   extents and periodic boundaries (else MHD_E_UNSUPPORTED). */
+   over the 2x2 fine faces tiling each face at the lower side of a cell of
+   the 2x-coarsened grid: d_acc [3][7][nz/2][ny/2][nx/2] (context precision;
+   components in the face frame rho, Mn, Mt1, Mt2, E, Bt1, Bt2; the last
+   boundary face of a non-periodic axis is not accumulated).  The caller
+   zeroes it.  Needs even extents and, per axis, both sides periodic or both
+   not (else MHD_E_UNSUPPORTED). */
 int mhd_flux_accumulate(mhd_ctx *ctx, void *d_acc);
 
 /* Writes the 2x-coarsened state (2^3 volume means, 2^2 face means) in the
-   interior layout of this header for the half-size grid.  Even extents and
-   periodic boundaries.  Synchronises. */
+   interior layout of this header for the half-size grid with the same
+   boundary kinds (n/2 + 1 faces along a non-periodic axis, the last one
+   tiled by the fine boundary faces).  Same requirements as
+   mhd_flux_accumulate.  Synchronises. */
 int mhd_coarsen(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_bz);
 
-/* Training samples from the last step of a (coarse, periodic) context:
+/* Training samples from the last step of a (coarse) context:
    for n faces d_faces [n][4] = (axis, i, j, k) with 0 <= i,j,k < n_axis,
    d_x [n][32] = features of the corrector state, d_t [n][8] = the MLP
    output that would turn its corrector flux into d_acc/dt_coarse (d_acc

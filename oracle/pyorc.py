@@ -384,13 +384,17 @@ def mlp_flux_to_out(w8, gamma, df):
 
 
 def coarsen(cell5, bx, by, bz):
-    """2x coarse-graining of a periodic state: volume means of the cell
-    fields over 2^3 fine cells, area means of each face field over the 2^2
-    fine faces that tile a coarse face (plain definition, numpy)."""
+    """2x coarse-graining of a state: volume means of the cell fields over
+    2^3 fine cells, area means of each face field over the 2^2 fine faces
+    that tile a coarse face (plain definition, numpy).  A face array with n+1
+    faces along its normal (non-periodic axis) keeps its boundary face."""
     c5 = np.asarray(cell5, dtype=np.float64)
     nz, ny, nx = c5.shape[1:]
     cc = c5.reshape(5, nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(2, 4, 6))
-    bx = np.asarray(bx, dtype=np.float64)[:, :, 0::2].reshape(nz // 2, 2, ny // 2, 2, nx // 2)
-    by = np.asarray(by, dtype=np.float64)[:, 0::2, :].reshape(nz // 2, 2, ny // 2, nx // 2, 2)
-    bz = np.asarray(bz, dtype=np.float64)[0::2, :, :].reshape(nz // 2, ny // 2, 2, nx // 2, 2)
+    bx = np.asarray(bx, dtype=np.float64)[:, :, 0::2]
+    by = np.asarray(by, dtype=np.float64)[:, 0::2, :]
+    bz = np.asarray(bz, dtype=np.float64)[0::2, :, :]
+    bx = bx.reshape(nz // 2, 2, ny // 2, 2, bx.shape[2])
+    by = by.reshape(nz // 2, 2, by.shape[1], nx // 2, 2)
+    bz = bz.reshape(bz.shape[0], ny // 2, 2, nx // 2, 2)
     return cc, bx.mean(axis=(1, 3)), by.mean(axis=(1, 4)), bz.mean(axis=(2, 4))

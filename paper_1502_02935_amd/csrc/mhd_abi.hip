@@ -559,9 +559,14 @@ int mhd_destroy(mhd_ctx* c) {
   return MHD_OK;
 }
 
-static bool even_periodic(const mhd_ctx* c) {
-  for (int a = 0; a < 3; ++a)
-    if (c->g.n[a] % 2 != 0 || c->g.bc[2 * a] != MHD_BC_PERIODIC) return false;
+// 2x coarse-graining needs even extents and, per axis, both sides periodic
+// or both not.
+static bool coarsenable(const mhd_ctx* c) {
+  for (int a = 0; a < 3; ++a) {
+    if (c->g.n[a] % 2 != 0) return false;
+    if ((c->g.bc[2 * a] == MHD_BC_PERIODIC) != (c->g.bc[2 * a + 1] == MHD_BC_PERIODIC))
+      return false;
+  }
   return true;
 }
 
@@ -582,14 +587,14 @@ int mhd_set_mlp(mhd_ctx* c, const float* d_params, const mhd_gate* gate) {
 
 int mhd_flux_accumulate(mhd_ctx* c, void* d_acc) {
   if (!c) return MHD_E_ARG;
-  if (d_acc && !even_periodic(c)) return MHD_E_UNSUPPORTED;
+  if (d_acc && !coarsenable(c)) return MHD_E_UNSUPPORTED;
   c->flux_acc = d_acc;
   return MHD_OK;
 }
 
 int mhd_coarsen(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz) {
   if (!c || !d_cell5 || !d_bx || !d_by || !d_bz) return MHD_E_ARG;
-  if (!even_periodic(c)) return MHD_E_UNSUPPORTED;
+  if (!coarsenable(c)) return MHD_E_UNSUPPORTED;
   if (c->cfg.precision == MHD_FP64)
     launch_coarsen<double>(c->g, c->cons<double>(0), (double*)d_cell5, (double*)d_bx,
                            (double*)d_by, (double*)d_bz, c->st);
@@ -604,10 +609,7 @@ int mhd_mlp_samples(mhd_ctx* c, const void* d_acc, double dt_coarse, int64_t n,
                     const int32_t* d_faces, float* d_x, float* d_t, uint8_t* d_mask) {
   if (!c || n < 0 || !(dt_coarse > 0.0)) return MHD_E_ARG;
   if (n > 0 && (!d_acc || !d_faces || !d_x || !d_t || !d_mask)) return MHD_E_ARG;
-  if (!even_periodic(c)) {
-    for (int a = 0; a < 3; ++a)
-      if (c->g.bc[2 * a] != MHD_BC_PERIODIC) return MHD_E_UNSUPPORTED;
-  }
+
   if (n == 0) return MHD_OK;
   if (c->cfg.precision == MHD_FP64) {
     launch_shock<double>(c->g, c->prim<double>(), c->shock(), c->mlp_jump, c->st);

@@ -306,7 +306,9 @@ __device__ __forceinline__ int pidx2(const Geo& g, int i, int j, int k) {
 }
 
 // acc[a][m][K][J][I] += dt * mean of the 2x2 fine a-faces tiling coarse
-// a-face (I, J, K), frame components m = 0..6 of the fine corrector flux.
+// a-face (I, J, K), frame components m = 0..6 of the fine corrector flux:
+// the faces at the lower sides of the coarse cells (on a non-periodic axis
+// the last boundary face is not accumulated).
 template <class T>
 __global__ void k_fluxacc(Geo g, Flux<T> f, T* acc, DtRef dtr) {
   const int I = blockIdx.x * 64 + threadIdx.x;
@@ -339,29 +341,44 @@ void launch_fluxacc(const Geo& g, Flux<T> f, T* acc, DtRef dt, hipStream_t st) {
                      dim3(64), 0, st, g, f, acc, dt);
 }
 
-// 2x coarse-graining of the interior state into interior-layout arrays.
+// 2x coarse-graining of the interior state into interior-layout arrays:
+// cells are the means of their 2^3 fine cells, faces the means of the 2^2
+// fine faces tiling them.  A non-periodic axis has n/2 + 1 coarse faces
+// along it (the last one tiled by the fine boundary faces), so the launch
+// covers I, J, K in 0..n/2.
 template <class T>
 __global__ void k_coarsen(Geo g, Cons<T> s, T* cell5, T* bx, T* by, T* bz) {
   const int I = blockIdx.x * 64 + threadIdx.x;
   const int J = blockIdx.y, K = blockIdx.z;
   const int nc[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
-  if (I >= nc[0]) return;
-  const size_t ncell = (size_t)nc[0] * nc[1] * nc[2];
-  const size_t q = ((size_t)K * nc[1] + J) * nc[0] + I;
+  int nfc[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) nfc[a] = g.nf[a] > g.n[a] ? nc[a] + 1 : nc[a];
+  if (I > nc[0]) return;
+  const int C[3] = {I, J, K};
   const int p0 = pidx2(g, 2 * I, 2 * J, 2 * K);
   const int st[3] = {1, g.sy, g.sz};
+  if (I < nc[0] && J < nc[1] && K < nc[2]) {
+    const size_t ncell = (size_t)nc[0] * nc[1] * nc[2];
+    const size_t q = ((size_t)K * nc[1] + J) * nc[0] + I;
 #pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    T a = T(0);
-    for (int dz = 0; dz < 2; ++dz)
-      for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx) a += s.u[m][p0 + dx + dy * g.sy + dz * g.sz];
-    cell5[m * ncell + q] = T(0.125) * a;
+    for (int m = 0; m < 5; ++m) {
+      T a = T(0);
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) a += s.u[m][p0 + dx + dy * g.sy + dz * g.sz];
+      cell5[m * ncell + q] = T(0.125) * a;
+    }
   }
   T* out[3] = {bx, by, bz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+    if (C[a] >= nfc[a] || C[t1] >= nc[t1] || C[t2] >= nc[t2]) continue;
+    // face array a: extents nfc[a] along a, nc across, x fastest
+    int ext[3] = {nc[0], nc[1], nc[2]};
+    ext[a] = nfc[a];
+    const size_t q = ((size_t)K * ext[1] + J) * ext[0] + I;
     const T* B = s.b[a];
     out[a][q] = T(0.25) * (B[p0] + B[p0 + st[t1]] + B[p0 + st[t2]] + B[p0 + st[t1] + st[t2]]);
   }
@@ -369,8 +386,8 @@ __global__ void k_coarsen(Geo g, Cons<T> s, T* cell5, T* bx, T* by, T* bz) {
 
 template <class T>
 void launch_coarsen(const Geo& g, Cons<T> s, T* c5, T* bx, T* by, T* bz, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarsen<T>, dim3((unsigned)((g.n[0] / 2 + 63) / 64), (unsigned)(g.n[1] / 2),
-                                        (unsigned)(g.n[2] / 2)),
+  hipLaunchKernelGGL(k_coarsen<T>, dim3((unsigned)((g.n[0] / 2 + 1 + 63) / 64),
+                                        (unsigned)(g.n[1] / 2 + 1), (unsigned)(g.n[2] / 2 + 1)),
                      dim3(64), 0, st, g, s, c5, bx, by, bz);
 }
 
@@ -384,7 +401,7 @@ __global__ void k_mlp_samples(Geo g, Prim<T> w, Flux<T> f, const uint8_t* shock,
   if (b >= n) return;
   const int a = faces[4 * b], i = faces[4 * b + 1], j = faces[4 * b + 2], k = faces[4 * b + 3];
   if (a < 0 || a > 2 || i < 0 || i >= g.n[0] || j < 0 || j >= g.n[1] || k < 0 || k >= g.n[2]) {
-    // not an interior face of a periodic grid: no access, flagged
+    // not the lower face of an interior cell: no access, flagged
     for (int c = 0; c < 32; ++c) x[b * 32 + c] = 0.f;
     for (int o = 0; o < 8; ++o) t[b * 8 + o] = 0.f;
     mask[b] = 2;

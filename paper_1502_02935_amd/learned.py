@@ -49,7 +49,7 @@ def random_faces(cfg: MHDConfig, n: int, gen: torch.Generator, device) -> torch.
 def generate(problem, pairs: int, faces_per_pair: int, seed: int = 0, precision=L.MHD_FP32,
              device="cuda", log=None):
     """Samples (x [m][32], t [m][8]) from `pairs` fine step pairs of
-    `problem` (a periodic generator output with even extents)."""
+    `problem` (even extents; per axis periodic on both sides or on neither)."""
     fcfg = config_from_problem(problem, precision=precision)
     ccfg = coarse_config(fcfg)
     fine = Sim(fcfg, problem.cell5, problem.bx, problem.by, problem.bz, device=device)
@@ -236,6 +236,20 @@ def time_coarse(problem, params, steps: int, tau=0.1, jump=0.5, dt=1e-4, warmup=
     return out
 
 
+def make_problem(kind: str, n: int, seed: int):
+    """A fine-grid workload, rounded to FP32: the periodic turbulent-ISM box
+    n^3, or the disc slab n x n x n/4 (24 x 24 x 6 kpc at n = 512, the box
+    growing with n so the cell size stays 46.875 pc)."""
+    from mhd_inputs import problems as P
+    if kind == "turbulent":
+        return P.turbulent_ism(n, seed=seed).astype("float32")
+    if kind == "disc":
+        sc = n / 512.0
+        return P.disc(n, n, n // 4, lx=24.0 * sc, ly=24.0 * sc, lz=6.0 * sc,
+                      seed=seed).astype("float32")
+    raise ValueError(kind)
+
+
 def _seeds(s: str):
     if "-" in s:
         a, b = s.split("-")
@@ -249,10 +263,12 @@ def main(argv=None):
     import os
     import sys
 
-    from mhd_inputs import problems as P
 
     ap = argparse.ArgumentParser(description="train and evaluate the learned flux correction")
-    ap.add_argument("--n", type=int, default=256, help="fine cells per axis")
+    ap.add_argument("--problem", choices=("turbulent", "disc"), default="turbulent")
+    ap.add_argument("--n", type=int, default=256, help="fine cells per axis (disc: along x, y)")
+    ap.add_argument("--eval-n", type=int, default=None,
+                    help="fine cells per axis of the evaluation runs (default --n)")
     ap.add_argument("--train-seeds", default="100-109")
     ap.add_argument("--eval-seeds", default="200-204")
     ap.add_argument("--pairs", type=int, default=100, help="fine step pairs per seed (= coarse steps)")
@@ -279,7 +295,7 @@ def main(argv=None):
         params = torch.as_tensor(np.load(a.params_in or default_weights()), dtype=torch.float32,
                                  device="cuda")
         sd = _seeds(a.eval_seeds)[0]
-        r = time_coarse(P.turbulent_ism(a.n, seed=sd).astype("float32"), params, a.time_coarse,
+        r = time_coarse(make_problem(a.problem, a.eval_n or a.n, sd), params, a.time_coarse,
                         tau=a.tau)
         print(json.dumps(r))
         return
@@ -289,7 +305,7 @@ def main(argv=None):
         for spec in (a.taus or "%g:%g" % (a.tau, a.tau_flux)).split(","):
             tau, tauf = (float(v) for v in (spec.split(":") + ["0"])[:2])
             for sd in _seeds(a.eval_seeds):
-                r = evaluate(P.turbulent_ism(a.n, seed=sd).astype("float32"), params, a.pairs,
+                r = evaluate(make_problem(a.problem, a.eval_n or a.n, sd), params, a.pairs,
                              tau=tau, tau_flux=tauf)
                 res["eval"]["%g:%g/%d" % (tau, tauf, sd)] = r
                 log("tau %g seed %d: L1 rho plain %.4e learned %.4e; E %.4e %.4e; status %d "
@@ -305,8 +321,7 @@ def main(argv=None):
     t0 = time.perf_counter()
     for sd in _seeds(a.train_seeds):
         log("training data, seed %d" % sd)
-        x, t = generate(P.turbulent_ism(a.n, seed=sd).astype("float32"), a.pairs, a.faces,
-                        seed=sd, log=log)
+        x, t = generate(make_problem(a.problem, a.n, sd), a.pairs, a.faces, seed=sd, log=log)
         xs.append(x)
         ts.append(t)
     x = torch.cat(xs)
@@ -325,7 +340,7 @@ def main(argv=None):
     del x, t, xs, ts
     for sd in _seeds(a.eval_seeds):
         log("evaluation, seed %d" % sd)
-        r = evaluate(P.turbulent_ism(a.n, seed=sd).astype("float32"), params, a.pairs, tau=a.tau,
+        r = evaluate(make_problem(a.problem, a.eval_n or a.n, sd), params, a.pairs, tau=a.tau,
                      tau_flux=a.tau_flux)
         res["eval"][str(sd)] = r
         log("  L1 rho plain %.4e learned %.4e" % (r["plain"]["L1"]["rho"], r["learned"]["L1"]["rho"]))

@@ -193,7 +193,9 @@ class Sim:
         dt = cfg.dtype
         nx, ny, nz = cfg.nx // 2, cfg.ny // 2, cfg.nz // 2
         c5 = torch.empty((5, nz, ny, nx), dtype=dt, device=self.device)
-        b = [torch.empty((nz, ny, nx), dtype=dt, device=self.device) for _ in range(3)]
+        ox, oy, oz = (0 if cfg.bc[2 * a] == L.BC_PERIODIC else 1 for a in range(3))
+        shapes = ((nz, ny, nx + ox), (nz, ny + oy, nx), (nz + oz, ny, nx))
+        b = [torch.empty(sh, dtype=dt, device=self.device) for sh in shapes]
         L.check(self.L.mhd_coarsen(self.ctx, _ptr(c5), _ptr(b[0]), _ptr(b[1]), _ptr(b[2])),
                 "mhd_coarsen")
         return c5, b[0], b[1], b[2]

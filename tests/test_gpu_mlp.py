@@ -107,8 +107,10 @@ def test_training_reduces_loss():
     assert last < 0.2 * first, (first, last)
 
 
-def test_coarsen_matches_definition():
-    pb = P.turbulent_ism(32, seed=9)
+@pytest.mark.parametrize("outflow", [False, True])
+def test_coarsen_matches_definition(outflow):
+    pb = P.random_smooth((16, 12, 10), seed=9, bc=(P.OUTFLOW,) * 6) if outflow else \
+        P.turbulent_ism(32, seed=9)
     s = gpu_sim(pb)
     s.step(2)
     fine = host_state(s)
@@ -118,10 +120,12 @@ def test_coarsen_matches_definition():
         np.testing.assert_allclose(g, w, rtol=1e-14, atol=1e-15)
 
 
-def test_flux_accumulator_matches_oracle_fluxes():
+@pytest.mark.parametrize("bc", [(P.PERIODIC,) * 6, (P.OUTFLOW,) * 6])
+def test_flux_accumulator_matches_oracle_fluxes(bc):
     """Sum over steps of dt times the mean fine corrector flux on each
-    coarse face, against the oracle's corrector fluxes."""
-    pb = P.random_smooth((16, 12, 8), seed=10)
+    coarse face (at the lower side of a coarse cell), against the oracle's
+    corrector fluxes."""
+    pb = P.random_smooth((16, 12, 8), seed=10, bc=bc)
     o = oracle_of(pb)
     s = gpu_sim(pb)
     acc = s.flux_accumulator(True)
@@ -155,8 +159,9 @@ def test_flux_accumulator_matches_oracle_fluxes():
             assert np.abs(got[a, m] - want[a, m]).max() <= 1e-11 * sc, (a, m)
 
 
-def test_samples_match_oracle_features_and_targets():
-    pb = P.random_smooth((16, 12, 10), seed=11)
+@pytest.mark.parametrize("bc", [(P.PERIODIC,) * 6, (P.OUTFLOW,) * 6])
+def test_samples_match_oracle_features_and_targets(bc):
+    pb = P.random_smooth((16, 12, 10), seed=11, bc=bc)
     o = oracle_of(pb)
     s = gpu_sim(pb)
     dt = o.dt()

@@ -138,3 +138,28 @@ def test_shock_cells_gate_the_correction(make, gated):
     d = o.diag()
     assert d["n_mlp_faces"] > 0
     assert (d["n_mlp_gated"] > 0) == gated
+
+
+@pytest.mark.parametrize("bc", [(P.PERIODIC,) * 6, (P.OUTFLOW,) * 6])
+def test_coarsening_keeps_mass_and_div_b(bc):
+    """The 2x coarse-graining (plain definition) keeps the total of every
+    cell field (volume means of 2^3 cells) and, for a discretely
+    divergence-free face field, a coarse field that is divergence-free on the
+    coarse grid (the face means telescope); on a non-periodic axis the
+    boundary faces carry over."""
+    pb = P.random_smooth((12, 8, 6), seed=5, bc=bc)
+    c5, bx, by, bz = O.coarsen(pb.cell5, pb.bx, pb.by, pb.bz)
+    for m in range(5):
+        assert abs(c5[m].sum() * 8 - pb.cell5[m].sum()) <= 1e-12 * np.abs(pb.cell5[m]).sum()
+    dx, dy, dz = 2 * pb.dx, 2 * pb.dy, 2 * pb.dz
+    nz, ny, nx = c5.shape[1:]
+    if bc[0] == P.PERIODIC:
+        div = ((np.roll(bx, -1, 2) - bx) / dx + (np.roll(by, -1, 1) - by) / dy +
+               (np.roll(bz, -1, 0) - bz) / dz)
+    else:
+        assert bx.shape == (nz, ny, nx + 1) and by.shape == (nz, ny + 1, nx)
+        assert bz.shape == (nz + 1, ny, nx)
+        div = (np.diff(bx, axis=2) / dx + np.diff(by, axis=1) / dy + np.diff(bz, axis=0) / dz)
+        np.testing.assert_allclose(bx[:, :, -1], pb.bx[:, :, -1].reshape(nz, 2, ny, 2).mean(axis=(1, 3)))
+    bs = max(np.abs(bx).max(), np.abs(by).max(), np.abs(bz).max())
+    assert np.abs(div).max() * min(dx, dy, dz) <= 1e-13 * bs
