@@ -272,6 +272,8 @@ def main(argv=None):
     ap.add_argument("--train-seeds", default="100-109")
     ap.add_argument("--eval-seeds", default="200-204")
     ap.add_argument("--pairs", type=int, default=100, help="fine step pairs per seed (= coarse steps)")
+    ap.add_argument("--eval-pairs", type=int, default=None,
+                    help="fine step pairs of the evaluation runs (default --pairs)")
     ap.add_argument("--faces", type=int, default=16384, help="sampled coarse faces per pair")
     ap.add_argument("--steps", type=int, default=4000, help="Adam steps")
     ap.add_argument("--batch", type=int, default=16384)
@@ -305,8 +307,8 @@ def main(argv=None):
         for spec in (a.taus or "%g:%g" % (a.tau, a.tau_flux)).split(","):
             tau, tauf = (float(v) for v in (spec.split(":") + ["0"])[:2])
             for sd in _seeds(a.eval_seeds):
-                r = evaluate(make_problem(a.problem, a.eval_n or a.n, sd), params, a.pairs,
-                             tau=tau, tau_flux=tauf)
+                r = evaluate(make_problem(a.problem, a.eval_n or a.n, sd), params,
+                             a.eval_pairs or a.pairs, tau=tau, tau_flux=tauf)
                 res["eval"]["%g:%g/%d" % (tau, tauf, sd)] = r
                 log("tau %g seed %d: L1 rho plain %.4e learned %.4e; E %.4e %.4e; status %d "
                     "faces %d gated %d" % (tau, sd, r["plain"]["L1"]["rho"],
@@ -340,8 +342,8 @@ def main(argv=None):
     del x, t, xs, ts
     for sd in _seeds(a.eval_seeds):
         log("evaluation, seed %d" % sd)
-        r = evaluate(make_problem(a.problem, a.eval_n or a.n, sd), params, a.pairs, tau=a.tau,
-                     tau_flux=a.tau_flux)
+        r = evaluate(make_problem(a.problem, a.eval_n or a.n, sd), params,
+                     a.eval_pairs or a.pairs, tau=a.tau, tau_flux=a.tau_flux)
         res["eval"][str(sd)] = r
         log("  L1 rho plain %.4e learned %.4e" % (r["plain"]["L1"]["rho"], r["learned"]["L1"]["rho"]))
     fields = ("rho", "Mx", "My", "Mz", "E", "Bx", "By", "Bz")
