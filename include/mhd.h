@@ -72,7 +72,9 @@ enum {
 enum { MHD_ST_BAD_STATE = 1u };
 
 typedef struct mhd_config {
-  int32_t nx, ny, nz;     /* interior cells, each >= 1 */
+  int32_t nx, ny, nz;     /* interior cells, each >= 1; a padded array,
+                             (nx+5)(ny+5)(nz+5) elements, must stay below
+                             2^31 elements and 4 GiB */
   int32_t precision;      /* MHD_FP64 or MHD_FP32 (FP32 bulk, FP64 where cancellation bites) */
   int32_t bc[6];          /* -x, +x, -y, +y, -z, +z; periodic must be set on both sides */
   double x0, y0, z0;      /* lower corner of the domain */

@@ -81,7 +81,10 @@ bool config_ok(const mhd_config* c) {
   for (int q = 0; q < 4; ++q)
     if (c->reserved[q] != 0) return false;
   Geo g;
-  return geo_of(c, &g);
+  if (!geo_of(c, &g)) return false;
+  // the flux kernel addresses every padded array with 32-bit byte offsets
+  const unsigned long long es = c->precision == MHD_FP64 ? 8ull : 4ull;
+  return (unsigned long long)g.np * es <= 0xFFFFFFFFull;
 }
 
 Layout layout_of(const mhd_config* c) {

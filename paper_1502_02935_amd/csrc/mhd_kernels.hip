@@ -69,12 +69,12 @@ static Span make_span(const Geo& g, int ilo, int ihi, int jlo, int jhi, int klo,
 
 static dim3 span_grid(const Span& s) { return dim3((unsigned)s.nblk); }
 
-// q = floor(a / d) for 0 <= a < 2^23 from a float estimate, corrected to
-// exact in integer arithmetic.
+// q = floor(a / d) for 0 <= a < 2^31, d > 0: a float estimate (off by at
+// most one step below 2^23, a few above), corrected to exact in integers.
 __device__ __forceinline__ int div_small(int a, int d, float inv_d) {
   int q = (int)(((float)a + 0.5f) * inv_d);
-  if (q * d > a) --q;
-  else if ((q + 1) * d <= a) ++q;
+  while (q * d > a) --q;
+  while ((q + 1) * d <= a) ++q;
   return q;
 }
 

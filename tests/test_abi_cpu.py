@@ -66,3 +66,12 @@ def test_null_arguments_rejected():
     # zero-length batches are valid no-ops
     assert lib.mhd_hlld_batch(0, 0, None, None, None, 1.4, None, None, None) == L.MHD_OK
     assert lib.mhd_recon_batch(1, 0, None, 0, 0.3, None, None, None) == L.MHD_OK
+
+
+def test_workspace_rejects_arrays_beyond_32bit_offsets():
+    """An FP64 padded array above 4 GiB cannot be addressed by the flux
+    kernel's 32-bit byte offsets: rejected; the same grid in FP32 fits."""
+    big = dict(nx=1000, ny=1000, nz=600, dx=1.0, dy=1.0, dz=1.0)
+    assert workspace_bytes(MHDConfig(precision=L.MHD_FP32, **big)) > 0
+    with pytest.raises(Exception):
+        workspace_bytes(MHDConfig(precision=L.MHD_FP64, **big))
