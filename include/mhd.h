@@ -71,6 +71,14 @@ enum {
 /* Status bits (mhd_diag_t.status). */
 enum { MHD_ST_BAD_STATE = 1u };
 
+/* Riemann solver of both stages (section 2.1: HLLD for magneto-gas
+   dynamics; HLL and HLLC for pure gas dynamics).  HLL uses the outer wave
+   speeds of HLLD and is valid with a field; HLLC is the gas-dynamic
+   three-wave solver and takes the field to be zero (the magnetic flux
+   components are zero): use it only for B = 0.  The learned correction
+   (mhd_set_mlp) requires HLLD. */
+enum { MHD_RIEMANN_HLLD = 0, MHD_RIEMANN_HLL = 1, MHD_RIEMANN_HLLC = 2 };
+
 typedef struct mhd_config {
   int32_t nx, ny, nz;     /* interior cells, each >= 1; a padded array,
                              (nx+5)(ny+5)(nz+5) elements, must stay below
@@ -89,7 +97,8 @@ typedef struct mhd_config {
   double p_floor;         /* 0 = off; else E is raised so that P >= p_floor */
   double inflow[8];       /* ghost primitive state of MHD_BC_INFLOW sides:
                              rho, vx, vy, vz, P, Bx, By, Bz */
-  int32_t reserved[4];    /* must be 0 */
+  int32_t riemann;        /* MHD_RIEMANN_*: HLLD (0, default), or the gas-dynamic HLL or HLLC */
+  int32_t reserved[3];    /* must be 0 */
 } mhd_config;
 
 typedef struct mhd_diag_t {

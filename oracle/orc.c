@@ -251,6 +251,78 @@ int orc_hlld(const double wl[7], const double wr[7], double bn, double gam,
   return deg ? 2 : 0;
 }
 
+/* HLL (Harten, Lax & van Leer): one intermediate state between the outer
+   waves, with the outer speeds of orc_hlld. */
+int orc_hll(const double wl[7], const double wr[7], double bn, double gam,
+            double flux[7]) {
+  double ul[7], ur[7], fl[7], fr[7];
+  int m;
+  orc_prim_to_cons(wl, bn, gam, ul);
+  orc_prim_to_cons(wr, bn, gam, ur);
+  orc_phys_flux(wl, bn, gam, fl);
+  orc_phys_flux(wr, bn, gam, fr);
+  double cfl = orc_fast_speed(wl, bn, gam);
+  double cfr = orc_fast_speed(wr, bn, gam);
+  double cmax = cfl > cfr ? cfl : cfr;
+  double SL = (wl[1] < wr[1] ? wl[1] : wr[1]) - cmax;
+  double SR = (wl[1] > wr[1] ? wl[1] : wr[1]) + cmax;
+  if (SL > 0.0) {
+    for (m = 0; m < 7; ++m) flux[m] = fl[m];
+  } else if (SR < 0.0) {
+    for (m = 0; m < 7; ++m) flux[m] = fr[m];
+  } else {
+    for (m = 0; m < 7; ++m)
+      flux[m] = (SR * fl[m] - SL * fr[m] + SL * SR * (ur[m] - ul[m])) / (SR - SL);
+  }
+  return 0;
+}
+
+/* HLLC (Toro, Spruce & Speares) for gas dynamics: the HLL fan split at the
+   contact S* into two star states of equal pressure and normal velocity. */
+int orc_hllc(const double wl[7], const double wr[7], double bn, double gam,
+             double flux[7]) {
+  double gl[7], gr[7], ul[7], ur[7], fl[7], fr[7];
+  int m;
+  (void)bn;
+  for (m = 0; m < 7; ++m) {
+    gl[m] = m < 5 ? wl[m] : 0.0;
+    gr[m] = m < 5 ? wr[m] : 0.0;
+  }
+  orc_prim_to_cons(gl, 0.0, gam, ul);
+  orc_prim_to_cons(gr, 0.0, gam, ur);
+  orc_phys_flux(gl, 0.0, gam, fl);
+  orc_phys_flux(gr, 0.0, gam, fr);
+  double cl = sqrt(gam * gl[4] / gl[0]), cr = sqrt(gam * gr[4] / gr[0]);
+  double cmax = cl > cr ? cl : cr;
+  double SL = (gl[1] < gr[1] ? gl[1] : gr[1]) - cmax;
+  double SR = (gl[1] > gr[1] ? gl[1] : gr[1]) + cmax;
+  if (SL > 0.0) {
+    for (m = 0; m < 7; ++m) flux[m] = fl[m];
+    return 0;
+  }
+  if (SR < 0.0) {
+    for (m = 0; m < 7; ++m) flux[m] = fr[m];
+    return 0;
+  }
+  double ml = gl[0] * (SL - gl[1]), mr = gr[0] * (SR - gr[1]);
+  double Ss = (gr[4] - gl[4] + ml * gl[1] - mr * gr[1]) / (ml - mr);
+  const double *w = Ss >= 0.0 ? gl : gr;
+  const double *u = Ss >= 0.0 ? ul : ur;
+  const double *f = Ss >= 0.0 ? fl : fr;
+  double S = Ss >= 0.0 ? SL : SR;
+  double fac = w[0] * (S - w[1]) / (S - Ss);
+  double us[7];
+  us[0] = fac;
+  us[1] = fac * Ss;
+  us[2] = fac * w[2];
+  us[3] = fac * w[3];
+  us[4] = fac * (u[4] / w[0] + (Ss - w[1]) * (Ss + w[4] / (w[0] * (S - w[1]))));
+  us[5] = 0.0;
+  us[6] = 0.0;
+  for (m = 0; m < 7; ++m) flux[m] = f[m] + S * (us[m] - u[m]);
+  return 0;
+}
+
 /* minmod limiter: the argument of smaller magnitude when both have the same
    strict sign, else 0.  The sign test is by comparison, never by a*b. */
 double orc_minmod(double a, double b) {
@@ -485,6 +557,7 @@ orc_grid *orc_create(const orc_config *cfg) {
   int a, m;
   if (!g) return NULL;
   g->c = *cfg;
+  if (cfg->riemann < ORC_RIEMANN_HLLD || cfg->riemann > ORC_RIEMANN_HLLC) { free(g); return NULL; }
   g->n[0] = cfg->nx; g->n[1] = cfg->ny; g->n[2] = cfg->nz;
   g->d[0] = cfg->dx; g->d[1] = cfg->dy; g->d[2] = cfg->dz;
   for (a = 0; a < 3; ++a) {
@@ -739,7 +812,11 @@ static void sweep(orc_grid *g, int a, double *const bf[3], int recon) {
           double st4[4] = {src[v][p - 2 * s], src[v][p - s], src[v][p], src[v][p + s]};
           orc_recon(st4, recon, g->c.kappa, &wl[v], &wr[v]);
         }
-        int code = orc_hlld(wl, wr, bf[a][p], g->c.gamma, f);
+        int code = g->c.riemann == ORC_RIEMANN_HLL
+                       ? orc_hll(wl, wr, bf[a][p], g->c.gamma, f)
+                       : g->c.riemann == ORC_RIEMANN_HLLC
+                             ? orc_hllc(wl, wr, bf[a][p], g->c.gamma, f)
+                             : orc_hlld(wl, wr, bf[a][p], g->c.gamma, f);
         if (code & 1) nhll++;
         if (code & 2) ndeg++;
         if (learned) {

@@ -16,6 +16,8 @@
  *   - constrained-transport induction update                      (Eq. 8-9)
  *   - contact-upwinded corner EMF                                 (Eq. 10-11)
  *   - HLLD approximate Riemann solver (Miyoshi & Kusano 2005)     (sec. 2.1)
+ *     and the two gas-dynamic solvers the code also offers: HLL, and HLLC
+ *     for pure gas dynamics (B = 0)                                (sec. 2.1)
  *   - kappa-MUSCL reconstruction with minmod                      (Eq. 12-14)
  * Readings where the paper is silent or misprinted (time integrator, CFL,
  * sign of the Eq. 10 correction, ...) are listed in the project design notes
@@ -41,6 +43,9 @@ extern "C" {
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_INFLOW = 2 };
 enum { ORC_RECON_PAPER = 0, ORC_RECON_KAPPA = 1, ORC_RECON_FIRST = 2 };
+/* Riemann solver of both stages.  HLLC is the pure gas-dynamics solver: it
+   takes the field to be zero (the magnetic flux components are zero). */
+enum { ORC_RIEMANN_HLLD = 0, ORC_RIEMANN_HLL = 1, ORC_RIEMANN_HLLC = 2 };
 enum {
   ORC_SRC_NONE = 0,
   ORC_SRC_LOGPOT = 1,  /* Phi = v0^2/2 ln(Rc^2 + x^2 + y^2 + z^2/q^2): par = v0, Rc, q */
@@ -62,6 +67,7 @@ typedef struct orc_config {
   double rho_floor, p_floor; /* 0 = off */
   double inflow[8];       /* primitive ghost state for ORC_BC_INFLOW sides:
                              rho, vx, vy, vz, P, Bx, By, Bz */
+  int32_t riemann;        /* ORC_RIEMANN_* */
 } orc_config;
 
 typedef struct orc_diag {
@@ -114,6 +120,14 @@ double orc_fast_speed(const double w[7], double bn, double gamma);
    flux = rho, Mn, Mt1, Mt2, E, Bt1, Bt2.  Returns a code:
    bit0 = HLL fallback used, bit1 = a degenerate star state met. */
 int orc_hlld(const double wl[7], const double wr[7], double bn, double gamma,
+             double flux[7]);
+/* HLL flux with the same outer wave speeds as orc_hlld (returns 0). */
+int orc_hll(const double wl[7], const double wr[7], double bn, double gamma,
+            double flux[7]);
+/* HLLC flux of pure gas dynamics (Toro's three-wave solver): the field is
+   taken to be zero, flux[5] = flux[6] = 0, bn and wl/wr[5..6] are ignored
+   (returns 0). */
+int orc_hllc(const double wl[7], const double wr[7], double bn, double gamma,
              double flux[7]);
 /* Physical flux of Eq. 3 in the face-normal frame. */
 void orc_phys_flux(const double w[7], double bn, double gamma, double flux[7]);

@@ -18,6 +18,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_PAPER, RECON_KAPPA, RECON_FIRST = 0, 1, 2
+RIEMANN_HLLD, RIEMANN_HLL, RIEMANN_HLLC = 0, 1, 2
 MLP_NPARAM = 6792
 SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X = 0, 1, 2, 3
 
@@ -33,6 +34,7 @@ class _Cfg(C.Structure):
         ("source", C.c_int32), ("src", C.c_double * 4),
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("inflow", C.c_double * 8),
+        ("riemann", C.c_int32),
     ]
 
 
@@ -69,6 +71,7 @@ class OrcConfig:
     rho_floor: float = 0.0
     p_floor: float = 0.0
     inflow: tuple = field(default_factory=lambda: (0.0,) * 8)
+    riemann: int = RIEMANN_HLLD
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -85,6 +88,7 @@ class OrcConfig:
         c.rho_floor, c.p_floor = self.rho_floor, self.p_floor
         for i in range(8):
             c.inflow[i] = float(self.inflow[i])
+        c.riemann = int(self.riemann)
         return c
 
 
@@ -158,8 +162,9 @@ def load_oracle():
     L.orc_padded_size.argtypes = [C.c_void_p]
     L.orc_fast_speed.restype = C.c_double
     L.orc_fast_speed.argtypes = [dp, C.c_double, C.c_double]
-    L.orc_hlld.restype = C.c_int
-    L.orc_hlld.argtypes = [dp, dp, C.c_double, C.c_double, dp]
+    for nm in ("orc_hlld", "orc_hll", "orc_hllc"):
+        getattr(L, nm).restype = C.c_int
+        getattr(L, nm).argtypes = [dp, dp, C.c_double, C.c_double, dp]
     L.orc_phys_flux.argtypes = [dp, C.c_double, C.c_double, dp]
     L.orc_prim_to_cons.argtypes = [dp, C.c_double, C.c_double, dp]
     L.orc_minmod.restype = C.c_double
@@ -280,6 +285,22 @@ def hlld(wl, wr, bn: float, gamma: float):
     f = np.empty(7)
     code = L.orc_hlld(_ptr(wl), _ptr(wr), bn, gamma, _ptr(f))
     return f, code
+
+
+def hll(wl, wr, bn: float, gamma: float):
+    L = load_oracle()
+    wl, wr = _f64(wl), _f64(wr)
+    f = np.empty(7)
+    L.orc_hll(_ptr(wl), _ptr(wr), bn, gamma, _ptr(f))
+    return f
+
+
+def hllc(wl, wr, bn: float, gamma: float):
+    L = load_oracle()
+    wl, wr = _f64(wl), _f64(wr)
+    f = np.empty(7)
+    L.orc_hllc(_ptr(wl), _ptr(wr), bn, gamma, _ptr(f))
+    return f
 
 
 def phys_flux(w, bn: float, gamma: float):

@@ -18,6 +18,7 @@ MHD_OK, MHD_E_ARG, MHD_E_HIP, MHD_E_STATE, MHD_E_UNSUPPORTED, MHD_E_WS = 0, -1, 
 MHD_FP64, MHD_FP32 = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_PAPER, RECON_KAPPA, RECON_FIRST = 0, 1, 2
+RIEMANN_HLLD, RIEMANN_HLL, RIEMANN_HLLC = 0, 1, 2
 SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X = 0, 1, 2, 3
 
 
@@ -34,7 +35,8 @@ class mhd_config(C.Structure):
         ("src", C.c_double * 4),
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("inflow", C.c_double * 8),
-        ("reserved", C.c_int32 * 4),
+        ("riemann", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 

@@ -78,7 +78,8 @@ bool config_ok(const mhd_config* c) {
   if (!(c->kappa >= -1.0) || !(c->kappa < 1.0)) return false;
   if (c->source < MHD_SRC_NONE || c->source > MHD_SRC_GAUSS_X) return false;
   if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0)) return false;
-  for (int q = 0; q < 4; ++q)
+  if (c->riemann < MHD_RIEMANN_HLLD || c->riemann > MHD_RIEMANN_HLLC) return false;
+  for (int q = 0; q < 3; ++q)
     if (c->reserved[q] != 0) return false;
   Geo g;
   if (!geo_of(c, &g)) return false;
@@ -250,6 +251,7 @@ Physics physics_of(const mhd_config* c) {
   Physics ph;
   ph.gamma = c->gamma;
   ph.igm1 = 1.0 / (c->gamma - 1.0);
+  ph.riemann = c->riemann;
   ph.cfl = c->cfl;
   ph.source = c->source;
   for (int q = 0; q < 4; ++q) ph.src[q] = c->src[q];
@@ -579,6 +581,7 @@ int mhd_set_mlp(mhd_ctx* c, const float* d_params, const mhd_gate* gate) {
     c->mlp_params = nullptr;
     return MHD_OK;
   }
+  if (c->cfg.riemann != MHD_RIEMANN_HLLD) return MHD_E_UNSUPPORTED;
   if (!gate || !(gate->tau >= 0.0) || !(gate->jump > 0.0) || !(gate->tau_flux >= 0.0))
     return MHD_E_ARG;
   c->mlp_params = d_params;

@@ -379,10 +379,21 @@ __device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, unsigned
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
+// Flux of the face states with Riemann solver RS (a template parameter: a
+// run-time switch would size every kernel's registers for the largest).
+template <class T, int RS>
+__device__ __forceinline__ int riemann_flux(const Physics& ph, const Face<T>& L, const Face<T>& R,
+                                            T bn, T F[7]) {
+  if constexpr (RS == kRiemannHLL) return hll(L, R, bn, (T)ph.gamma, (T)ph.igm1, F);
+  if constexpr (RS == kRiemannHLLC) return hllc(L, R, (T)ph.gamma, (T)ph.igm1, F);
+  return hlld(L, R, bn, (T)ph.gamma, (T)ph.igm1, F);
+}
+
 // Flux of the A-face at point p: limited reconstruction (Eq. 12-14) of the
 // seven face variables from cells p - 2s .. p + s, HLLD, the sign of the
-// mass flux.  Returns the HLLD branch code (bit 0 HLL, bit 1 degenerate).
-template <class T, int A>
+// mass flux.  Returns the HLLD branch code (bit 0 HLL fallback, bit 1
+// degenerate; 0 for the other solvers).
+template <class T, int A, int RS>
 __device__ __forceinline__ int face_flux(const Physics& ph, int stride, unsigned bytes,
                                          const Prim<T>& w, const T* __restrict__ bn,
                                          const Flux<T>& f, const Muscl<T>& mu, int p) {
@@ -400,7 +411,7 @@ __device__ __forceinline__ int face_flux(const Physics& ph, int stride, unsigned
   const Face<T> L{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
   const Face<T> R{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
   T F[7];
-  const int code = hlld(L, R, bld(T(), rsrc(bn, bytes), o), (T)ph.gamma, (T)ph.igm1, F);
+  const int code = riemann_flux<T, RS>(ph, L, R, bld(T(), rsrc(bn, bytes), o), F);
 #pragma unroll
   for (int m = 0; m < 7; ++m) bst(F[m], rsrc(f.f[A][m], bytes), o);
   const int sg = F[0] > T(0) ? 1 : (F[0] < T(0) ? -1 : 0);
@@ -409,7 +420,7 @@ __device__ __forceinline__ int face_flux(const Physics& ph, int stride, unsigned
   return code;
 }
 
-template <class T>
+template <class T, int RS>
 __global__ void __launch_bounds__(kSpanThreads) k_flux(Geo g, Physics ph, Span sp, Prim<T> w,
                                                        const T* __restrict__ bx,
                                                        const T* __restrict__ by,
@@ -419,9 +430,9 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux(Geo g, Physics ph, Span s
   int cx = 0, cy = 0, cz = 0;
   if (pt.valid) {
     const unsigned bytes = (unsigned)g.np * (unsigned)sizeof(T);
-    if (pt.i >= 0) cx = face_flux<T, 0>(ph, 1, bytes, w, bx, f, mu, pt.p);
-    if (pt.j >= 0) cy = face_flux<T, 1>(ph, g.sy, bytes, w, by, f, mu, pt.p);
-    if (pt.k >= 0) cz = face_flux<T, 2>(ph, g.sz, bytes, w, bz, f, mu, pt.p);
+    if (pt.i >= 0) cx = face_flux<T, 0, RS>(ph, 1, bytes, w, bx, f, mu, pt.p);
+    if (pt.j >= 0) cy = face_flux<T, 1, RS>(ph, g.sy, bytes, w, by, f, mu, pt.p);
+    if (pt.k >= 0) cz = face_flux<T, 2, RS>(ph, g.sz, bytes, w, bz, f, mu, pt.p);
   }
   wave_count((cx & 1) != 0, cnt.hll);
   wave_count((cy & 1) != 0, cnt.hll);
@@ -435,8 +446,16 @@ template <class T>
 void launch_flux(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f, Muscl<T> m,
                  Counters c, hipStream_t st) {
   const Span sp = make_span(g, -1, g.n[0], -1, g.n[1], -1, g.n[2]);
-  hipLaunchKernelGGL(k_flux<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, w, s.b[0],
-                     s.b[1], s.b[2], f, m, c);
+  const dim3 gr = span_grid(sp), bl(kSpanThreads);
+  if (ph.riemann == kRiemannHLL)
+    hipLaunchKernelGGL((k_flux<T, kRiemannHLL>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
+                       s.b[2], f, m, c);
+  else if (ph.riemann == kRiemannHLLC)
+    hipLaunchKernelGGL((k_flux<T, kRiemannHLLC>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
+                       s.b[2], f, m, c);
+  else
+    hipLaunchKernelGGL((k_flux<T, kRiemannHLLD>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
+                       s.b[2], f, m, c);
 }
 
 // ------------------------------------------------------------------------

@@ -77,9 +77,14 @@ struct MlpRef {
   uint8_t* shock;       // per padded cell
 };
 
+// Riemann solver of the flux sweeps: HLLD, or the paper's two gas-dynamic
+// solvers HLL and HLLC (HLLC: pure gas dynamics, the field taken as zero).
+enum { kRiemannHLLD = 0, kRiemannHLL = 1, kRiemannHLLC = 2 };
+
 struct Physics {
   double gamma;
   double igm1;  // 1 / (gamma - 1)
+  int riemann;  // kRiemann*
   double cfl;
   int source;
   double src[4];

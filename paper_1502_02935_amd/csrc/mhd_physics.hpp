@@ -151,6 +151,75 @@ __device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T
   return r;
 }
 
+// HLL flux (Harten, Lax & van Leer): one intermediate state between the
+// outer waves, with the outer speeds of the HLLD solver.
+template <class T>
+__device__ __forceinline__ int hll(const Face<T>& L, const Face<T>& R, T bn, T gam, T igm1,
+                                   T f[7]) {
+  T ul[7], fl[7], ur[7], fr[7];
+  cons_flux(L, bn, igm1, ul, fl);
+  cons_flux(R, bn, igm1, ur, fr);
+  const T cfl = fast_speed(L.d, L.p, bn, L.bt1, L.bt2, gam);
+  const T cfr = fast_speed(R.d, R.p, bn, R.bt1, R.bt2, gam);
+  const T cmax = cfl > cfr ? cfl : cfr;
+  const T SL = (L.vn < R.vn ? L.vn : R.vn) - cmax;
+  const T SR = (L.vn > R.vn ? L.vn : R.vn) + cmax;
+  if (SL > T(0)) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = fl[m];
+  } else if (SR < T(0)) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = fr[m];
+  } else {
+    const T inv = rcp(SR - SL);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = (SR * fl[m] - SL * fr[m] + SL * SR * (ur[m] - ul[m])) * inv;
+  }
+  return 0;
+}
+
+// HLLC flux of pure gas dynamics (Toro, Spruce & Speares): the field is
+// taken to be zero, so the B components of the flux are zero; outer speeds
+// from the sound speeds, the contact speed S* from the two outer jump
+// conditions, star states of equal pressure and normal velocity.
+template <class T>
+__device__ __forceinline__ int hllc(const Face<T>& L0, const Face<T>& R0, T gam, T igm1, T f[7]) {
+  const Face<T> L{L0.d, L0.vn, L0.vt1, L0.vt2, L0.p, T(0), T(0)};
+  const Face<T> R{R0.d, R0.vn, R0.vt1, R0.vt2, R0.p, T(0), T(0)};
+  T ul[7], fl[7], ur[7], fr[7];
+  cons_flux(L, T(0), igm1, ul, fl);
+  cons_flux(R, T(0), igm1, ur, fr);
+  const T cl = root(gam * L.p * rcp(L.d)), cr = root(gam * R.p * rcp(R.d));
+  const T cmax = cl > cr ? cl : cr;
+  const T SL = (L.vn < R.vn ? L.vn : R.vn) - cmax;
+  const T SR = (L.vn > R.vn ? L.vn : R.vn) + cmax;
+  if (SL > T(0)) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = fl[m];
+    return 0;
+  }
+  if (SR < T(0)) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = fr[m];
+    return 0;
+  }
+  const T ml = L.d * (SL - L.vn), mr = R.d * (SR - R.vn);
+  const T Ss = (R.p - L.p + ml * L.vn - mr * R.vn) * rcp(ml - mr);
+  const bool left = Ss >= T(0);
+  const Face<T>& w = left ? L : R;
+  const T S = left ? SL : SR;
+  const T e = left ? ul[4] : ur[4];
+  const T sv = S - w.vn;
+  const T fac = w.d * sv * rcp(S - Ss);
+  const T us[5] = {fac, fac * Ss, fac * w.vt1, fac * w.vt2,
+                   fac * (e * rcp(w.d) + (Ss - w.vn) * (Ss + w.p * rcp(w.d * sv)))};
+#pragma unroll
+  for (int m = 0; m < 5; ++m) f[m] = (left ? fl[m] : fr[m]) + S * (us[m] - (left ? ul[m] : ur[m]));
+  f[5] = T(0);
+  f[6] = T(0);
+  return 0;
+}
+
 // HLLD flux (igm1 = 1/(gamma - 1)).  Returns bit0 if the HLL flux was used
 // (S_M outside (S_L, S_R)), bit1 if a star state was degenerate.
 template <class T>

@@ -35,7 +35,8 @@ def coarse_config(fine: MHDConfig) -> MHDConfig:
                      dy=2 * fine.dy, dz=2 * fine.dz, x0=fine.x0, y0=fine.y0, z0=fine.z0,
                      precision=fine.precision, gamma=fine.gamma, cfl=fine.cfl, bc=fine.bc,
                      recon=fine.recon, kappa=fine.kappa, source=fine.source, src=fine.src,
-                     rho_floor=fine.rho_floor, p_floor=fine.p_floor, inflow=fine.inflow)
+                     rho_floor=fine.rho_floor, p_floor=fine.p_floor, inflow=fine.inflow,
+                     riemann=fine.riemann)
 
 
 def random_faces(cfg: MHDConfig, n: int, gen: torch.Generator, device) -> torch.Tensor:

@@ -34,6 +34,7 @@ class MHDConfig:
     rho_floor: float = 0.0
     p_floor: float = 0.0
     inflow: tuple = field(default_factory=lambda: (0.0,) * 8)
+    riemann: int = L.RIEMANN_HLLD
 
     def to_c(self) -> L.mhd_config:
         c = L.mhd_config()
@@ -50,6 +51,7 @@ class MHDConfig:
         c.rho_floor, c.p_floor = self.rho_floor, self.p_floor
         for i in range(8):
             c.inflow[i] = float(self.inflow[i])
+        c.riemann = int(self.riemann)
         return c
 
     @property
@@ -65,12 +67,12 @@ class MHDConfig:
 
 
 def config_from_problem(pb, precision=L.MHD_FP64, recon=L.RECON_PAPER, kappa=1.0 / 3.0,
-                        cfl=None) -> MHDConfig:
+                        cfl=None, riemann=L.RIEMANN_HLLD) -> MHDConfig:
     return MHDConfig(nx=pb.nx, ny=pb.ny, nz=pb.nz, dx=pb.dx, dy=pb.dy, dz=pb.dz, x0=pb.x0,
                      y0=pb.y0, z0=pb.z0, precision=precision, gamma=pb.gamma,
                      cfl=pb.cfl if cfl is None else cfl, bc=tuple(pb.bc), recon=recon,
                      kappa=kappa, source=pb.source, src=tuple(pb.src), rho_floor=pb.rho_floor,
-                     p_floor=pb.p_floor, inflow=tuple(pb.inflow))
+                     p_floor=pb.p_floor, inflow=tuple(pb.inflow), riemann=riemann)
 
 
 def workspace_bytes(cfg: MHDConfig) -> int:

@@ -14,9 +14,9 @@ except Exception:  # pragma: no cover
 needs_gpu = pytest.mark.skipif(not HAVE_GPU, reason="no GPU visible")
 
 
-def gpu_sim(pb, precision=0, recon=0, kappa=1.0 / 3.0, state=None):
+def gpu_sim(pb, precision=0, recon=0, kappa=1.0 / 3.0, state=None, riemann=0):
     from paper_1502_02935_amd import Sim, config_from_problem
-    cfg = config_from_problem(pb, precision=precision, recon=recon, kappa=kappa)
+    cfg = config_from_problem(pb, precision=precision, recon=recon, kappa=kappa, riemann=riemann)
     c5, bx, by, bz = state if state is not None else (pb.cell5, pb.bx, pb.by, pb.bz)
     return Sim(cfg, c5, bx, by, bz)
 

@@ -6,12 +6,12 @@ import numpy as np
 from oracle.pyorc import Oracle, OrcConfig
 
 
-def orc_config(pb, recon=0, kappa=1.0 / 3.0, cfl=None) -> OrcConfig:
+def orc_config(pb, recon=0, kappa=1.0 / 3.0, cfl=None, riemann=0) -> OrcConfig:
     return OrcConfig(nx=pb.nx, ny=pb.ny, nz=pb.nz, dx=pb.dx, dy=pb.dy, dz=pb.dz,
                      x0=pb.x0, y0=pb.y0, z0=pb.z0, gamma=pb.gamma,
                      cfl=pb.cfl if cfl is None else cfl, bc=pb.bc, recon=recon, kappa=kappa,
                      source=pb.source, src=pb.src, rho_floor=pb.rho_floor, p_floor=pb.p_floor,
-                     inflow=pb.inflow)
+                     inflow=pb.inflow, riemann=riemann)
 
 
 def oracle_of(pb, **kw) -> Oracle:

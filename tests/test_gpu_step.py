@@ -14,9 +14,10 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 TOL = 1e-11
 
 
-def _parity(pb, nsteps, recon=O.RECON_PAPER, tol=TOL, check_dt=True):
-    o = oracle_of(pb, recon=recon)
-    s = gpu_sim(pb, precision=0, recon=recon)
+def _parity(pb, nsteps, recon=O.RECON_PAPER, tol=TOL, check_dt=True, kappa=1.0 / 3.0,
+            riemann=O.RIEMANN_HLLD):
+    o = oracle_of(pb, recon=recon, kappa=kappa, riemann=riemann)
+    s = gpu_sim(pb, precision=0, recon=recon, kappa=kappa, riemann=riemann)
     if check_dt:
         dto, dtg = o.dt(), s.dt()
         assert abs(dtg - dto) <= 1e-13 * dto, (dtg, dto)
@@ -72,6 +73,40 @@ def test_random_box_ragged(bc):
 def test_recon_variants(recon):
     pb = P.random_smooth((40, 18, 12), seed=32)
     _parity(pb, 3, recon=recon)
+
+
+@pytest.mark.parametrize("kappa", [-1.0, 0.0])
+@pytest.mark.parametrize("recon", [O.RECON_PAPER, O.RECON_KAPPA])
+def test_other_kappas(recon, kappa):
+    """Eq. 12-14 with kappa = -1 (fully upwind) and 0 (upwind biased)."""
+    pb = P.random_smooth((40, 18, 12), seed=33)
+    _parity(pb, 3, recon=recon, kappa=kappa)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("riemann", [O.RIEMANN_HLL, O.RIEMANN_HLLC])
+def test_gas_solvers_sod_each_axis(riemann, axis):
+    """The paper's gas-dynamic solvers on the Sod tube laid along each axis."""
+    _parity(P.sod(100, axis=axis), 30, riemann=riemann)
+
+
+def test_hll_with_field():
+    """HLL keeps the HLLD wave speeds and is valid with a field: Ryu-Jones
+    and a random magnetised box under mixed boundaries."""
+    _parity(P.ryu_jones(100), 30, riemann=O.RIEMANN_HLL)
+    pb = P.random_smooth((34, 20, 14), seed=35,
+                         bc=(P.OUTFLOW, P.OUTFLOW, P.PERIODIC, P.PERIODIC, P.OUTFLOW, P.OUTFLOW))
+    _parity(pb, 4, riemann=O.RIEMANN_HLL)
+
+
+def test_hllc_gas_box():
+    """HLLC on a 3-D gas-dynamic box: a random smooth state with the field
+    removed (its energy stays, as extra gas pressure)."""
+    pb = P.random_smooth((36, 22, 10), seed=36, b0=(0.0, 0.0, 0.0))
+    pb.bx[:] = 0.0
+    pb.by[:] = 0.0
+    pb.bz[:] = 0.0
+    _parity(pb, 4, riemann=O.RIEMANN_HLLC)
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
