@@ -301,19 +301,23 @@ def _cyc(v, axis):
 
 
 def riemann_1d(left, right, n: int, *, xlo=-0.5, xhi=0.5, gamma=5.0 / 3.0, axis=0,
-               name="riemann", t_end=0.0, cfl=0.4, bc_lohi=(OUTFLOW, OUTFLOW)) -> Problem:
-    """Two constant states (rho, vx, vy, vz, P, Bx, By, Bz) split at x = 0 on
-    [xlo, xhi] with n cells, outflow along the problem axis and periodic
-    (one cell) across it.  `axis` lays the problem along x, y or z with the
-    vector components permuted cyclically."""
+               name="riemann", t_end=0.0, cfl=0.4, bc_lohi=(OUTFLOW, OUTFLOW), x_split=0.0,
+               right_rho=None) -> Problem:
+    """Two constant states (rho, vx, vy, vz, P, Bx, By, Bz) split at x_split
+    on [xlo, xhi] with n cells, outflow along the problem axis and periodic
+    (one cell) across it; right_rho(x), if given, replaces the right state's
+    density at the cell centres.  `axis` lays the problem along x, y or z
+    with the vector components permuted cyclically."""
     L = np.asarray(left, dtype=np.float64)
     R = np.asarray(right, dtype=np.float64)
     if L[5] != R[5]:
         raise ValueError("normal B must be continuous")
     h = (xhi - xlo) / n
     xc = xlo + (np.arange(n) + 0.5) * h
-    sel = xc < 0.0
+    sel = xc < x_split
     q = np.where(sel[:, None], L[None, :], R[None, :])   # [n][8]
+    if right_rho is not None:
+        q[:, 0] = np.where(sel, L[0], right_rho(xc))
     # 1-D arrays along the problem axis
     rho, vx, vy, vz, P = (q[:, m] for m in range(5))
     b_n = np.full(n + 1, L[5])
@@ -353,6 +357,16 @@ def sod(n=200, axis=0) -> Problem:
     [-1, 1], t = 0.5."""
     return riemann_1d((1, 0, 0, 0, 1, 0, 0, 0), (0.125, 0, 0, 0, 0.1, 0, 0, 0), n, xlo=-1.0,
                       xhi=1.0, gamma=1.4, axis=axis, name="sod", t_end=0.5)
+
+
+def shu_osher(n=200, axis=0) -> Problem:
+    """Shu-Osher (section 3): a Mach-3 shock, {rho, u, P} = {3.857143,
+    2.629369, 10.33333} for x < 0.125, running into rho = 1 + 0.2 sin(16 pi x),
+    u = 0, P = 1; gamma 1.4 on [0, 1] (reading: the paper gives the split
+    point and t = 0.18, not the domain), outflow ends, t = 0.18."""
+    return riemann_1d((3.857143, 2.629369, 0, 0, 10.33333, 0, 0, 0), (1, 0, 0, 0, 1, 0, 0, 0), n,
+                      xlo=0.0, xhi=1.0, gamma=1.4, axis=axis, name="shu_osher", t_end=0.18,
+                      x_split=0.125, right_rho=lambda x: 1.0 + 0.2 * np.sin(16.0 * np.pi * x))
 
 
 def brio_wu(n=200, axis=0) -> Problem:

@@ -90,6 +90,12 @@ def test_gas_solvers_sod_each_axis(riemann, axis):
     _parity(P.sod(100, axis=axis), 30, riemann=riemann)
 
 
+@pytest.mark.parametrize("riemann", [O.RIEMANN_HLLD, O.RIEMANN_HLLC])
+def test_shu_osher(riemann):
+    """Shu-Osher (Mach-3 shock into a density sine), 200 cells, 100 steps."""
+    _parity(P.shu_osher(200), 100, riemann=riemann)
+
+
 def test_hll_with_field():
     """HLL keeps the HLLD wave speeds and is valid with a field: Ryu-Jones
     and a random magnetised box under mixed boundaries."""

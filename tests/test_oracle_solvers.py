@@ -145,3 +145,38 @@ def test_other_kappas_are_second_order(kappa):
         errs.append(float(np.mean(np.abs(c5[1] - vx) + np.abs(c5[2] - vy) + np.abs(c5[3] - vz))))
     order = math.log(errs[0] / errs[1], 2)
     assert order >= 1.6, (errs, order)
+
+
+# ---------------------------------------------------------- Shu-Osher -----
+
+def test_shu_osher_left_state_is_a_mach3_shock():
+    """The printed post-shock state is the Rankine-Hugoniot state behind a
+    Mach-3 shock running into rho = 1, u = 0, P = 1 (gamma 1.4), to the
+    printed digits."""
+    g, M = 1.4, 3.0
+    rho2 = (g + 1) * M * M / ((g - 1) * M * M + 2)
+    p2 = (2 * g * M * M - (g - 1)) / (g + 1)
+    u2 = M * math.sqrt(g) * (1 - 1 / rho2)
+    pb = P.shu_osher(50)
+    L = pb.extra["left"]
+    assert abs(L[0] - rho2) < 5e-7 and abs(L[4] - p2) < 5e-6 and abs(L[1] - u2) < 5e-6
+
+
+def _shu_osher_rho(n, riemann=O.RIEMANN_HLLD):
+    pb = P.shu_osher(n)
+    o = oracle_of(pb, riemann=riemann)
+    run_to(o, pb.t_end)
+    return o.get_state()[0][0].reshape(-1)
+
+
+def test_shu_osher_self_convergence():
+    """No closed form (the paper shows figures only): averaged onto 100
+    cells, the 100-, 200- and 400-cell solutions approach the 800-cell one,
+    each doubling closing at least a fifth of the distance (shock and
+    under-resolved wave train: slow at these resolutions), with HLLD and
+    HLLC."""
+    for rs in (O.RIEMANN_HLLD, O.RIEMANN_HLLC):
+        ref = _shu_osher_rho(800, rs).reshape(100, 8).mean(axis=1)
+        d = [np.abs(_shu_osher_rho(n, rs).reshape(100, n // 100).mean(axis=1) - ref).mean()
+             for n in (100, 200, 400)]
+        assert d[1] < 0.8 * d[0] and d[2] < 0.8 * d[1], (rs, d)
