@@ -25,7 +25,7 @@ from dataclasses import dataclass, field, replace
 import numpy as np
 
 PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
-SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X = 0, 1, 2, 3
+SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X, SRC_SELF_GRAVITY = 0, 1, 2, 3, 4
 
 
 @dataclass
@@ -320,7 +320,8 @@ def riemann_1d(left, right, n: int, *, xlo=-0.5, xhi=0.5, gamma=5.0 / 3.0, axis=
         q[:, 0] = np.where(sel, L[0], right_rho(xc))
     # 1-D arrays along the problem axis
     rho, vx, vy, vz, P = (q[:, m] for m in range(5))
-    b_n = np.full(n + 1, L[5])
+    nfn = n if bc_lohi[0] == PERIODIC else n + 1  # faces along the problem axis
+    b_n = np.full(nfn, L[5])
     b_t1 = q[:, 6]
     b_t2 = q[:, 7]
     shape = [1, 1, 1]
@@ -328,14 +329,14 @@ def riemann_1d(left, right, n: int, *, xlo=-0.5, xhi=0.5, gamma=5.0 / 3.0, axis=
     shp = tuple(shape)  # (nz, ny, nx)
     vel = _cyc((vx, vy, vz), axis)
     comps = [rho.reshape(shp), *(c.reshape(shp) for c in vel), P.reshape(shp)]
-    # face arrays: the normal one has n+1 faces along the axis, transverse ones
-    # are one per cell (periodic single-cell axes)
+    # face arrays: the normal one has n+1 faces along the axis (n if it is
+    # periodic), transverse ones are one per cell (periodic single-cell axes)
     bfield = _cyc((b_n, b_t1, b_t2), axis)
     faces = []
     for d in range(3):
         fs = list(shp)
         if d == axis:
-            fs[2 - d] = n + 1
+            fs[2 - d] = nfn
         faces.append(np.ascontiguousarray(bfield[d].reshape(fs)))
     bc = [PERIODIC] * 6
     bc[2 * axis], bc[2 * axis + 1] = bc_lohi
@@ -357,6 +358,29 @@ def sod(n=200, axis=0) -> Problem:
     [-1, 1], t = 0.5."""
     return riemann_1d((1, 0, 0, 0, 1, 0, 0, 0), (0.125, 0, 0, 0, 0.1, 0, 0, 0), n, xlo=-1.0,
                       xhi=1.0, gamma=1.4, axis=axis, name="sod", t_end=0.5)
+
+
+def jeans(n=64, axis=0, k_over_kj=0.5, amp=1e-4, cs=1.0, gamma=5.0 / 3.0) -> Problem:
+    """Jeans problem on a periodic unit box laid along `axis` (one cell
+    across): rho = 1 + amp cos(2 pi x), adiabatic P = P0 (rho/rho0)^gamma with
+    sound speed cs, at rest, B = 0; self-gravity with G such that the mode
+    k = 2 pi sits at k/k_J = k_over_kj (k_J^2 = 4 pi G rho0 / cs^2).  extra:
+    the linear rate, growth (k < k_J) or angular frequency (k > k_J)."""
+    rho0, k = 1.0, 2.0 * math.pi
+    G = cs * cs * k * k / (4.0 * math.pi * rho0 * k_over_kj ** 2)
+    p0 = rho0 * cs * cs / gamma
+    pb = riemann_1d((rho0, 0, 0, 0, p0, 0, 0, 0), (rho0, 0, 0, 0, p0, 0, 0, 0), n, xlo=0.0, xhi=1.0,
+                    gamma=gamma, axis=axis, name="jeans", bc_lohi=(PERIODIC, PERIODIC),
+                    x_split=-1.0, right_rho=lambda x: rho0 + amp * np.cos(k * x))
+    # adiabatic pressure of the perturbed density
+    shp = pb.cell5.shape[1:]
+    rho = pb.cell5[0]
+    P = p0 * (rho / rho0) ** gamma
+    pb.cell5[4] = P / (gamma - 1.0)  # at rest, B = 0
+    pb.source, pb.src = SRC_SELF_GRAVITY, (G, 0.0, 0.0, 0.0)
+    w2 = 4.0 * math.pi * G * rho0 - cs * cs * k * k
+    pb.extra.update(G=G, rate=math.sqrt(abs(w2)), growing=w2 > 0, amp=amp, k=k)
+    return pb
 
 
 def shu_osher(n=200, axis=0) -> Problem:

@@ -49,6 +49,8 @@
 #define DEG_EPS 1.0e-3
 #endif
 
+#define M_PI_ORC 3.14159265358979323846
+
 struct orc_grid {
   orc_config c;
   int n[3];
@@ -72,6 +74,8 @@ struct orc_grid {
   double mlp_tau, mlp_jump, mlp_tau_flux;
   unsigned char *shock;   /* per cell: 1 = shock cell (no correction on its faces) */
   int64_t n_mlp, n_gated;
+  /* self-gravity: potential and its central gradient at the cells (padded) */
+  double *psi, *gpsi[3];
 };
 
 static long at(const orc_grid *g, int i, int j, int k) {
@@ -552,6 +556,8 @@ void orc_recon_batch(long n, const double *w4, int recon, double kappa, double *
 
 static double *alloc_arr(long n) { return (double *)calloc((size_t)n, sizeof(double)); }
 
+void orc_destroy(orc_grid *g);
+
 orc_grid *orc_create(const orc_config *cfg) {
   orc_grid *g = (orc_grid *)calloc(1, sizeof(orc_grid));
   int a, m;
@@ -582,6 +588,13 @@ orc_grid *orc_create(const orc_config *cfg) {
   }
   for (m = 0; m < 8; ++m) g->w[m] = alloc_arr(g->np);
   g->shock = (unsigned char *)calloc((size_t)g->np, 1);
+  if (cfg->source == ORC_SRC_SELF_GRAVITY) {
+    /* the potential of a periodic box only */
+    for (a = 0; a < 3; ++a)
+      if (!g->per[a]) { orc_destroy(g); return NULL; }
+    g->psi = alloc_arr(g->np);
+    for (a = 0; a < 3; ++a) g->gpsi[a] = alloc_arr(g->np);
+  }
   return g;
 }
 
@@ -608,6 +621,8 @@ void orc_destroy(orc_grid *g) {
   for (m = 0; m < 8; ++m) free(g->w[m]);
   free(g->shock);
   free(g->mlp);
+  free(g->psi);
+  for (a = 0; a < 3; ++a) free(g->gpsi[a]);
   free(g);
 }
 
@@ -938,6 +953,111 @@ static void grad_phi(const orc_grid *g, double x, double y, double z, double gp[
 }
 
 /* ------------------------------------------------------------------------ */
+/* Self-gravity (the paper's Poisson equation), periodic box.               */
+/* ------------------------------------------------------------------------ */
+
+/* One-dimensional DFT along a line of n values (stride st) of re/im, from
+   the definition: X_k = sum_j x_j exp(sign 2 pi i j k / n). */
+static void dft_line(double *re, double *im, int n, long st, int sign, double *tr, double *ti) {
+  int j, k;
+  for (k = 0; k < n; ++k) {
+    double sr = 0.0, si = 0.0;
+    for (j = 0; j < n; ++j) {
+      double a = sign * 2.0 * M_PI_ORC * (double)(((long)j * k) % n) / (double)n;
+      double c = cos(a), s = sin(a);
+      sr += re[j * st] * c - im[j * st] * s;
+      si += re[j * st] * s + im[j * st] * c;
+    }
+    tr[k] = sr;
+    ti[k] = si;
+  }
+  for (k = 0; k < n; ++k) {
+    re[k * st] = tr[k];
+    im[k * st] = ti[k];
+  }
+}
+
+static void dft3(double *re, double *im, int nx, int ny, int nz, int sign) {
+  int n[3] = {nx, ny, nz};
+  long st[3] = {1, nx, (long)nx * ny};
+  int a;
+  for (a = 0; a < 3; ++a) {
+    if (n[a] == 1) continue;
+    int b = (a + 1) % 3, c = (a + 2) % 3;
+    int ib;
+#pragma omp parallel for schedule(static)
+    for (ib = 0; ib < n[b]; ++ib) {
+      double *tr = (double *)malloc(sizeof(double) * (size_t)n[a]);
+      double *ti = (double *)malloc(sizeof(double) * (size_t)n[a]);
+      int ic;
+      for (ic = 0; ic < n[c]; ++ic) {
+        long o = ib * st[b] + ic * st[c];
+        dft_line(re + o, im + o, n[a], st[a], sign, tr, ti);
+      }
+      free(tr);
+      free(ti);
+    }
+  }
+}
+
+void orc_poisson_periodic(int nx, int ny, int nz, double dx, double dy, double dz, double G,
+                          const double *rho, double *psi) {
+  long N = (long)nx * ny * nz, q;
+  double *re = (double *)malloc(sizeof(double) * (size_t)N);
+  double *im = (double *)calloc((size_t)N, sizeof(double));
+  for (q = 0; q < N; ++q) re[q] = rho[q];
+  dft3(re, im, nx, ny, nz, -1);
+  int i, j, k;
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < nx; ++i) {
+        /* eigenvalue of the 7-point Laplacian for mode (i, j, k) */
+        double lam = (2.0 * cos(2.0 * M_PI_ORC * i / nx) - 2.0) / (dx * dx) +
+                     (2.0 * cos(2.0 * M_PI_ORC * j / ny) - 2.0) / (dy * dy) +
+                     (2.0 * cos(2.0 * M_PI_ORC * k / nz) - 2.0) / (dz * dz);
+        long p = ((long)k * ny + j) * nx + i;
+        if (i == 0 && j == 0 && k == 0) {
+          re[p] = 0.0;
+          im[p] = 0.0;
+        } else {
+          re[p] *= 4.0 * M_PI_ORC * G / lam;
+          im[p] *= 4.0 * M_PI_ORC * G / lam;
+        }
+      }
+  dft3(re, im, nx, ny, nz, +1);
+  for (q = 0; q < N; ++q) psi[q] = re[q] / (double)N;
+  free(re);
+  free(im);
+}
+
+/* Psi of the stage density (primitives w[0]) and its central gradient at
+   every interior cell, with periodic wrap. */
+static void self_gravity(orc_grid *g) {
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+  long N = (long)nx * ny * nz;
+  double *rho = (double *)calloc((size_t)N, sizeof(double));
+  double *psi = (double *)calloc((size_t)N, sizeof(double));
+  int i, j, k;
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < nx; ++i) rho[((long)k * ny + j) * nx + i] = g->w[0][at(g, i, j, k)];
+  orc_poisson_periodic(nx, ny, nz, g->d[0], g->d[1], g->d[2], g->c.src[0], rho, psi);
+  for (k = 0; k < nz; ++k)
+    for (j = 0; j < ny; ++j)
+      for (i = 0; i < nx; ++i) {
+        long p = at(g, i, j, k);
+#define PSI(ii, jj, kk) psi[((long)(((kk) + nz) % nz) * ny + (((jj) + ny) % ny)) * nx + (((ii) + nx) % nx)]
+        g->psi[p] = PSI(i, j, k);
+        g->gpsi[0][p] = (PSI(i + 1, j, k) - PSI(i - 1, j, k)) / (2.0 * g->d[0]);
+        g->gpsi[1][p] = (PSI(i, j + 1, k) - PSI(i, j - 1, k)) / (2.0 * g->d[1]);
+        g->gpsi[2][p] = (PSI(i, j, k + 1) - PSI(i, j, k - 1)) / (2.0 * g->d[2]);
+#undef PSI
+      }
+  free(rho);
+  free(psi);
+}
+
+/* ------------------------------------------------------------------------ */
 /* O7 / O11: conservative update (Eq. 7) and CT induction update (Eq. 8).  */
 /* ------------------------------------------------------------------------ */
 
@@ -979,7 +1099,13 @@ static void update(orc_grid *g, double dt, double *const u0[5], double *const b0
           double x = g->c.x0 + (i + 0.5) * g->d[0];
           double y = g->c.y0 + (j + 0.5) * g->d[1];
           double z = g->c.z0 + (k + 0.5) * g->d[2];
-          grad_phi(g, x, y, z, gp);
+          if (g->c.source == ORC_SRC_SELF_GRAVITY) {
+            gp[0] = g->gpsi[0][p];
+            gp[1] = g->gpsi[1][p];
+            gp[2] = g->gpsi[2][p];
+          } else {
+            grad_phi(g, x, y, z, gp);
+          }
           double rho = g->w[0][p];
           s[1] = -rho * gp[0];
           s[2] = -rho * gp[1];
@@ -1049,12 +1175,14 @@ double orc_step(orc_grid *g, double dt) {
   if (!(dt > 0.0)) dt = orc_dt(g);
   /* predictor: first-order fluxes of U^n, half step */
   primitives(g, g->u, g->b);
+  if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g);
   for (a = 0; a < 3; ++a) sweep(g, a, g->b, ORC_RECON_FIRST);
   for (a = 0; a < 3; ++a) corner_emf(g, a);
   update(g, 0.5 * dt, g->u, g->b, g->us, g->bs);
   fill_ghosts(g, g->us, g->bs);
   /* corrector: MUSCL fluxes of U*, full step from U^n */
   primitives(g, g->us, g->bs);
+  if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g);
   if (g->mlp) shock_cells(g);
   for (a = 0; a < 3; ++a) sweep(g, a, g->bs, g->c.recon);
   for (a = 0; a < 3; ++a) corner_emf(g, a);
@@ -1206,6 +1334,7 @@ long orc_debug_array(const orc_grid *g, int what, double *out) {
   else if (what >= 24 && what < 27) src = g->e[what - 24];
   else if (what >= 27 && what < 30) src = g->ec[what - 27];
   else if (what >= 33 && what < 41) src = g->w[what - 33];
+  else if (what >= 41 && what < 45 && g->psi) src = what == 41 ? g->psi : g->gpsi[what - 42];
   else if (what >= 30 && what < 33) {
     for (p = 0; p < g->np; ++p) out[p] = (double)g->sg[what - 30][p];
     return g->np;

@@ -50,7 +50,8 @@ enum {
   ORC_SRC_NONE = 0,
   ORC_SRC_LOGPOT = 1,  /* Phi = v0^2/2 ln(Rc^2 + x^2 + y^2 + z^2/q^2): par = v0, Rc, q */
   ORC_SRC_UNIFORM = 2, /* grad Phi = (gx, gy, gz) constant:              par = gx, gy, gz */
-  ORC_SRC_GAUSS_X = 3  /* Phi = -A exp(-(x/w)^2):                         par = A, w     */
+  ORC_SRC_GAUSS_X = 3, /* Phi = -A exp(-(x/w)^2):                         par = A, w     */
+  ORC_SRC_SELF_GRAVITY = 4 /* Lap Psi = 4 pi G (rho - <rho>), periodic box: par = G */
 };
 
 typedef struct orc_config {
@@ -129,6 +130,13 @@ int orc_hll(const double wl[7], const double wr[7], double bn, double gamma,
    (returns 0). */
 int orc_hllc(const double wl[7], const double wr[7], double bn, double gamma,
              double flux[7]);
+/* Self-gravity potential (the paper's Poisson equation, Lap Psi = 4 pi G rho,
+   on a periodic box, where only rho - <rho> can source it): Psi over the
+   interior cells [nz][ny][nx] from rho of the same layout, with the
+   discrete 7-point Laplacian, solved mode by mode through the discrete
+   Fourier transform written out from its definition (mean mode zero). */
+void orc_poisson_periodic(int nx, int ny, int nz, double dx, double dy, double dz, double G,
+                          const double *rho, double *psi);
 /* Physical flux of Eq. 3 in the face-normal frame. */
 void orc_phys_flux(const double w[7], double bn, double gamma, double flux[7]);
 /* Conserved vector in the face-normal frame: rho, Mn, Mt1, Mt2, E, Bt1, Bt2. */

@@ -20,7 +20,7 @@ BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_PAPER, RECON_KAPPA, RECON_FIRST = 0, 1, 2
 RIEMANN_HLLD, RIEMANN_HLL, RIEMANN_HLLC = 0, 1, 2
 MLP_NPARAM = 6792
-SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X = 0, 1, 2, 3
+SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X, SRC_SELF_GRAVITY = 0, 1, 2, 3, 4
 
 
 class _Cfg(C.Structure):
@@ -162,6 +162,9 @@ def load_oracle():
     L.orc_padded_size.argtypes = [C.c_void_p]
     L.orc_fast_speed.restype = C.c_double
     L.orc_fast_speed.argtypes = [dp, C.c_double, C.c_double]
+    L.orc_poisson_periodic.restype = None
+    L.orc_poisson_periodic.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, dp, dp]
     for nm in ("orc_hlld", "orc_hll", "orc_hllc"):
         getattr(L, nm).restype = C.c_int
         getattr(L, nm).argtypes = [dp, dp, C.c_double, C.c_double, dp]
@@ -301,6 +304,18 @@ def hllc(wl, wr, bn: float, gamma: float):
     f = np.empty(7)
     L.orc_hllc(_ptr(wl), _ptr(wr), bn, gamma, _ptr(f))
     return f
+
+
+def poisson_periodic(rho, d, G: float):
+    """Psi of Lap Psi = 4 pi G (rho - <rho>) on the periodic box rho [nz][ny][nx]
+    with the 7-point Laplacian (oracle)."""
+    L = load_oracle()
+    rho = _f64(rho)
+    nz, ny, nx = rho.shape
+    psi = np.empty_like(rho)
+    L.orc_poisson_periodic(nx, ny, nz, float(d[0]), float(d[1]), float(d[2]), float(G), _ptr(rho),
+                           _ptr(psi))
+    return psi
 
 
 def phys_flux(w, bn: float, gamma: float):
