@@ -65,7 +65,12 @@ enum {
   MHD_SRC_NONE = 0,
   MHD_SRC_LOGPOT = 1,   /* Phi = v0^2/2 ln(Rc^2 + x^2 + y^2 + z^2/q^2); src = v0, Rc, q */
   MHD_SRC_UNIFORM = 2,  /* grad Phi = (gx, gy, gz);                      src = gx, gy, gz */
-  MHD_SRC_GAUSS_X = 3   /* Phi = -A exp(-(x/w)^2);                        src = A, w */
+  MHD_SRC_GAUSS_X = 3,  /* Phi = -A exp(-(x/w)^2);                        src = A, w */
+  MHD_SRC_SELF_GRAVITY = 4 /* self-gravity, Lap Psi = 4 pi G (rho - <rho>) on a
+                              periodic box (section 2.1, FFT solver): src = G.
+                              Needs periodic boundaries and power-of-two
+                              extents up to 1024; Psi comes from each stage's
+                              density, S from its central gradient */
 };
 
 /* Status bits (mhd_diag_t.status). */
@@ -172,7 +177,8 @@ int mhd_get_state(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_b
    what 0..6 x-face flux (rho, Mn, Mt1, Mt2, E, Bt1, Bt2 in the face frame
    (x,y,z)), 7..13 y-face flux (frame (y,z,x)), 14..20 z-face flux (frame
    (z,x,y)), 21..23 edge EMF Ex, Ey, Ez, 24..26 cell EMF, 27..34 primitives
-   rho, vx, vy, vz, P, Bcx, Bcy, Bcz.  *n_out gets the element count.
+   rho, vx, vy, vz, P, Bcx, Bcy, Bcz, and with self-gravity 35 Psi and
+   36..38 its gradient at the cells.  *n_out gets the element count.
    Synchronises. */
 int mhd_debug_array(mhd_ctx *ctx, int what, void *d_out, size_t *n_out);
 

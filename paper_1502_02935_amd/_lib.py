@@ -19,7 +19,7 @@ MHD_FP64, MHD_FP32 = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_PAPER, RECON_KAPPA, RECON_FIRST = 0, 1, 2
 RIEMANN_HLLD, RIEMANN_HLL, RIEMANN_HLLC = 0, 1, 2
-SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X = 0, 1, 2, 3
+SRC_NONE, SRC_LOGPOT, SRC_UNIFORM, SRC_GAUSS_X, SRC_SELF_GRAVITY = 0, 1, 2, 3, 4
 
 
 class mhd_config(C.Structure):

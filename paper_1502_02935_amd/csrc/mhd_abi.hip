@@ -35,6 +35,8 @@ struct Layout {
   size_t off_cfl;   // cfl partials
   size_t off_diag;  // diag partials
   size_t off_frag;  // learned correction: weights packed as bf16 MFMA fragments
+  size_t off_grav;  // self-gravity: 4 padded T arrays (Psi, grad Psi), the complex
+                    // [nz][ny][nx] array, twiddle and eigenvalue tables (0 bytes if off)
   size_t total;
 };
 
@@ -76,7 +78,16 @@ bool config_ok(const mhd_config* c) {
   if (!(c->cfl > 0.0) || !(c->cfl <= 1.0)) return false;
   if (c->recon < MHD_RECON_PAPER || c->recon > MHD_RECON_FIRST) return false;
   if (!(c->kappa >= -1.0) || !(c->kappa < 1.0)) return false;
-  if (c->source < MHD_SRC_NONE || c->source > MHD_SRC_GAUSS_X) return false;
+  if (c->source < MHD_SRC_NONE || c->source > MHD_SRC_SELF_GRAVITY) return false;
+  if (c->source == MHD_SRC_SELF_GRAVITY) {
+    // periodic box, extents powers of two up to 1024 (radix-2 FFT lines in LDS)
+    const int n[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a) {
+      if (c->bc[2 * a] != MHD_BC_PERIODIC || c->bc[2 * a + 1] != MHD_BC_PERIODIC) return false;
+      if (n[a] < 1 || n[a] > 1024 || (n[a] & (n[a] - 1)) != 0) return false;
+    }
+    if (!(c->src[0] >= 0.0) || !isfinite(c->src[0])) return false;
+  }
   if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0)) return false;
   if (c->riemann < MHD_RIEMANN_HLLD || c->riemann > MHD_RIEMANN_HLLC) return false;
   for (int q = 0; q < 3; ++q)
@@ -103,7 +114,14 @@ Layout layout_of(const mhd_config* c) {
                                    sizeof(unsigned long long));
   L.off_diag = L.off_cfl + align_up((size_t)cfl_blocks(g) * sizeof(double));
   L.off_frag = L.off_diag + align_up((size_t)diag_blocks(g) * 16 * sizeof(double));
-  L.total = L.off_frag + align_up((size_t)kMlpFragBytes);
+  L.off_grav = L.off_frag + align_up((size_t)kMlpFragBytes);
+  size_t grav = 0;
+  if (c->source == MHD_SRC_SELF_GRAVITY) {
+    const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
+    grav = 4 * L.arr + align_up(ncell * 2 * es);
+    for (int a = 0; a < 3; ++a) grav += align_up((size_t)g.n[a] * 2 * es);  // twiddles, eigenvalues
+  }
+  L.total = L.off_grav + grav;
   return L;
 }
 
@@ -223,6 +241,30 @@ struct mhd_ctx {
     for (int a = 0; a < 3; ++a) e.e[a] = (T*)arr(48 + a);
     return e;
   }
+  bool gravity() const { return cfg.source == MHD_SRC_SELF_GRAVITY; }
+  template <class T>
+  Grav<T> grav() const {
+    Grav<T> r{};
+    if (!gravity()) return r;
+    char* b = ws + L.off_grav;
+    r.psi = (T*)b;
+    for (int a = 0; a < 3; ++a) r.g[a] = (T*)(b + (1 + a) * L.arr);
+    return r;
+  }
+  // tables: per axis n/2 twiddle pairs then n eigenvalues, each block aligned
+  template <class T>
+  GravFFT<T> grav_fft() const {
+    GravFFT<T> f{};
+    char* b = ws + L.off_grav + 4 * L.arr;
+    f.c = (T*)b;
+    b += align_up((size_t)g.n[0] * g.n[1] * g.n[2] * 2 * sizeof(T));
+    for (int a = 0; a < 3; ++a) {
+      f.tw[a] = (const T*)b;
+      f.lam[a] = (const T*)(b + (size_t)g.n[a] * sizeof(T));  // after n/2 pairs
+      b += align_up((size_t)g.n[a] * 2 * sizeof(T));
+    }
+    return f;
+  }
 };
 
 namespace {
@@ -290,6 +332,10 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     launch_prim_cfl<T>(g, c->ph, U, W, c->cfl_part(), c->misc() + M_DT, cnt, c->st);
   else
     launch_prim<T>(g, c->ph, U, W, cnt, c->st);
+  if (c->gravity()) {
+    c->mark(MHD_K_OTHER);
+    launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), c->st);
+  }
   c->mark(MHD_K_FLUX);
   launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
   c->mark(MHD_K_EMF);
@@ -297,12 +343,16 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   DtRef half = dt;
   half.factor = 0.5;
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, Us, W, F, E, half, cnt, c->st);
+  launch_update<T>(g, c->ph, U, Us, W, F, E, c->grav<T>(), half, cnt, c->st);
   c->mark(MHD_K_GHOSTS);
   launch_ghosts<T>(g, c->ph, Us, c->st);
   // corrector: MUSCL fluxes of U*, full step from U^n
   c->mark(MHD_K_PRIM);
   launch_prim<T>(g, c->ph, Us, W, cnt, c->st);
+  if (c->gravity()) {
+    c->mark(MHD_K_OTHER);
+    launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), c->st);
+  }
   if (c->mlp_params) {
     c->mark(MHD_K_SHOCK);
     launch_shock<T>(g, W, c->shock(), c->mlp_jump, c->st);
@@ -323,7 +373,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, W, F, E, c->st);
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, U, W, F, E, dt, cnt, c->st);
+  launch_update<T>(g, c->ph, U, U, W, F, E, c->grav<T>(), dt, cnt, c->st);
   c->mark(MHD_K_GHOSTS);
   launch_ghosts<T>(g, c->ph, U, c->st);
   c->mark(MHD_K_OTHER);
@@ -337,6 +387,31 @@ void enqueue_cfl(mhd_ctx* c) {
   launch_cfl<T>(c->g, c->ph, c->cons<T>(0), c->cfl_part(), c->misc() + M_DT, c->counters(),
                 c->st);
   c->mark(-1);
+}
+
+// Twiddles exp(-2 pi i q / n) (q < n/2) and the 3-point Laplacian's
+// eigenvalues (2 cos(2 pi m / n) - 2) / d^2 of each axis, computed in FP64
+// and stored in the context precision, in the layout grav_fft() reads.
+template <class T>
+int upload_gravity_tables(mhd_ctx* c) {
+  const GravFFT<T> f = c->grav_fft<T>();
+  for (int a = 0; a < 3; ++a) {
+    const int n = c->g.n[a];
+    std::vector<T> h((size_t)n * 2, T(0));
+    for (int q = 0; q < n / 2; ++q) {
+      const double ang = 2.0 * 3.14159265358979323846 * q / n;
+      h[2 * q] = (T)cos(ang);
+      h[2 * q + 1] = (T)(-sin(ang));
+    }
+    for (int m = 0; m < n; ++m)
+      h[(size_t)n + m] =
+          (T)((2.0 * cos(2.0 * 3.14159265358979323846 * m / n) - 2.0) / (c->g.d[a] * c->g.d[a]));
+    if (hipMemcpyAsync((void*)f.tw[a], h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice,
+                       c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+      return MHD_E_HIP;
+  }
+  return MHD_OK;
 }
 
 int sync_status(mhd_ctx* c) {
@@ -393,6 +468,14 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
       hipMemsetAsync(c->counter_slots(), 0, L.off_cfl - L.off_cnt, c->st) != hipSuccess) {
     delete c;
     return MHD_E_HIP;
+  }
+  if (c->gravity()) {
+    const int rc = cfg->precision == MHD_FP64 ? upload_gravity_tables<double>(c)
+                                              : upload_gravity_tables<float>(c);
+    if (rc != MHD_OK) {
+      delete c;
+      return rc;
+    }
   }
   if (cfg->precision == MHD_FP64) {
     launch_scatter<double>(c->g, (const double*)d_cell5, (const double*)d_bx,
@@ -514,7 +597,18 @@ int mhd_get_state(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz)
 }
 
 int mhd_debug_array(mhd_ctx* c, int what, void* d_out, size_t* n_out) {
-  if (!c || !d_out || what < 0 || what > 34) return MHD_E_ARG;
+  if (!c || !d_out || what < 0 || what > 38) return MHD_E_ARG;
+  const size_t es = c->cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
+  if (what >= 35) {
+    if (!c->gravity()) return MHD_E_ARG;
+    const char* src = c->ws + c->L.off_grav + (size_t)(what - 35) * c->L.arr;
+    if (hipMemcpyAsync(d_out, src, (size_t)c->g.np * es, hipMemcpyDeviceToDevice, c->st) !=
+        hipSuccess)
+      return MHD_E_HIP;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+    if (n_out) *n_out = (size_t)c->g.np;
+    return MHD_OK;
+  }
   int q;
   if (what < 21)
     q = 27 + what;  // fluxes
@@ -524,7 +618,6 @@ int mhd_debug_array(mhd_ctx* c, int what, void* d_out, size_t* n_out) {
     q = 24 + (what - 24);  // cell EMF
   else
     q = 16 + (what - 27);  // primitives
-  const size_t es = c->cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
   if (hipMemcpyAsync(d_out, c->arr(q), (size_t)c->g.np * es, hipMemcpyDeviceToDevice, c->st) !=
       hipSuccess)
     return MHD_E_HIP;

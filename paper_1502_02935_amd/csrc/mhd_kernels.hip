@@ -687,7 +687,7 @@ __device__ __forceinline__ void grad_phi(const Physics& ph, double x, double y, 
 template <class T>
 __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span sp, Cons<T> s0,
                                                          Cons<T> s1, Prim<T> w, Flux<T> f,
-                                                         Edge<T> e, DtRef dtr) {
+                                                         Edge<T> e, Grav<T> gr, DtRef dtr) {
   const Pt pt = span_point(g, sp);
   const int i = pt.i, j = pt.j, k = pt.k;
   if (pt.valid) {
@@ -709,8 +709,14 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
       T S[5] = {T(0), T(0), T(0), T(0), T(0)};
       if (ph.source != 0) {
         double gp[3];
-        grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
-                 g.x0[2] + (k + 0.5) * g.d[2], gp);
+        if (ph.source == 4) {
+          gp[0] = gr.g[0][p];
+          gp[1] = gr.g[1][p];
+          gp[2] = gr.g[2][p];
+        } else {
+          grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
+                   g.x0[2] + (k + 0.5) * g.d[2], gp);
+        }
         const T rho = w.w[0][p];
         const T gx = (T)gp[0], gy = (T)gp[1], gz = (T)gp[2];
         S[1] = -rho * gx;
@@ -773,10 +779,10 @@ __global__ void __launch_bounds__(kSpanThreads) k_floors(Geo g, Physics ph, Span
 
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
-                   Flux<T> f, Edge<T> e, DtRef dt, Counters c, hipStream_t st) {
+                   Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c, hipStream_t st) {
   const Span sp = make_span(g, 0, g.n[0], 0, g.n[1], 0, g.n[2]);
   hipLaunchKernelGGL(k_update<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s0, s1, w,
-                     f, e, dt);
+                     f, e, gr, dt);
   if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
     const Span si = make_span(g, 0, g.n[0] - 1, 0, g.n[1] - 1, 0, g.n[2] - 1);
     hipLaunchKernelGGL(k_floors<T>, span_grid(si), dim3(kSpanThreads), 0, st, g, ph, si, s1, c);
@@ -1091,7 +1097,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
                                    Muscl<T>, Counters, MlpRef, hipStream_t);                     \
   template void launch_shock<T>(const Geo&, Prim<T>, uint8_t*, double, hipStream_t);           \
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Flux<T>, \
-                                 Edge<T>, DtRef, Counters, hipStream_t);                         \
+                                 Edge<T>, Grav<T>, DtRef, Counters, hipStream_t);                \
   template void launch_cfl<T>(const Geo&, const Physics&, Cons<T>, double*, double*, Counters,   \
                               hipStream_t);                                                      \
   template void launch_diag<T>(const Geo&, const Physics&, Cons<T>, double*, double*,           \

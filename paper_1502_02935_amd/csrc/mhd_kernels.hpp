@@ -93,6 +93,24 @@ struct Physics {
   double inflow_b[3];
 };
 
+// Self-gravity: potential and its central gradient at the cells (padded
+// arrays; null when the source is off).
+template <class T>
+struct Grav {
+  T* psi;
+  T* g[3];
+};
+
+// Workspace of the periodic Poisson solve: complex [nz][ny][nx] array (T
+// pairs), per axis n/2 twiddles exp(-2 pi i q / n) (T pairs) and n
+// eigenvalues of the 3-point Laplacian.
+template <class T>
+struct GravFFT {
+  T* c;
+  const T* tw[3];
+  const T* lam[3];
+};
+
 // Time-step source: a value, or (if ptr != nullptr) a device scalar.
 struct DtRef {
   double value;
@@ -123,7 +141,12 @@ template <class T>
 void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
-                   Flux<T> f, Edge<T> e, DtRef dt, Counters c, hipStream_t st);
+                   Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c, hipStream_t st);
+// Psi of the stage density rho (padded primitive array) and its gradient
+// into gr (mhd_gravity.hip).
+template <class T>
+void launch_self_gravity(const Geo& g, const Physics& ph, const T* rho, GravFFT<T> f, Grav<T> gr,
+                         hipStream_t st);
 // CFL: per-block minima into part (size cfl_blocks(g), which also fits the
 // partials of launch_prim_cfl), then dt_out = cfl min.
 int cfl_blocks(const Geo& g);

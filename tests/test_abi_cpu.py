@@ -75,3 +75,15 @@ def test_workspace_rejects_arrays_beyond_32bit_offsets():
     assert workspace_bytes(MHDConfig(precision=L.MHD_FP32, **big)) > 0
     with pytest.raises(Exception):
         workspace_bytes(MHDConfig(precision=L.MHD_FP64, **big))
+
+
+def test_self_gravity_needs_periodic_power_of_two_box():
+    base = dict(dx=0.1, dy=0.1, dz=0.1, source=L.SRC_SELF_GRAVITY, src=(1.0, 0.0, 0.0, 0.0))
+    assert workspace_bytes(MHDConfig(nx=32, ny=16, nz=8, **base)) > 0
+    with pytest.raises(Exception):
+        workspace_bytes(MHDConfig(nx=24, ny=16, nz=8, **base))
+    with pytest.raises(Exception):
+        workspace_bytes(MHDConfig(nx=32, ny=16, nz=8, bc=(L.BC_OUTFLOW,) * 6, **base))
+    # the gravity buffers come on top of the plain step's
+    plain = workspace_bytes(MHDConfig(nx=32, ny=16, nz=8, dx=0.1, dy=0.1, dz=0.1))
+    assert workspace_bytes(MHDConfig(nx=32, ny=16, nz=8, **base)) > plain
