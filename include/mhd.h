@@ -196,7 +196,8 @@ enum {
   MHD_K_UPDATE = 6,
   MHD_K_CFL = 7,
   MHD_K_OTHER = 8,
-  MHD_K_COUNT = 9
+  MHD_K_GRAVITY = 9,  /* self-gravity Poisson solve (FFTs, k-space division, gradient) */
+  MHD_K_COUNT = 10
 };
 
 typedef struct mhd_profile_t {

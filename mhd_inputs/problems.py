@@ -383,6 +383,31 @@ def jeans(n=64, axis=0, k_over_kj=0.5, amp=1e-4, cs=1.0, gamma=5.0 / 3.0) -> Pro
     return pb
 
 
+def collapse(n=128, *, G=1.0, mass=1.0, radius=1.0, u=0.05, rho_bg=1e-3, gamma=5.0 / 3.0,
+             cfl=0.4) -> Problem:
+    """Self-gravitating gas sphere on the periodic box [-1, 1]^3 (section 3,
+    spherical collapse): rho = M / (2 pi R^2 r) inside R (the 1/r profile of
+    the paper, normalised as in the adiabatic-collapse test of Evrard 1988),
+    rho_bg outside, at rest, specific internal energy u everywhere, B = 0,
+    self-gravity with constant G (readings: the paper names the profile, the
+    box and 100^3 cells; the FFT solver takes 2^k cells per axis)."""
+    h = 2.0 / n
+    c = -1.0 + (np.arange(n) + 0.5) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    rho = np.where(r <= radius, mass / (2.0 * math.pi * radius * radius * np.maximum(r, 1e-300)),
+                   rho_bg)
+    P = (gamma - 1.0) * rho * u
+    zero = np.zeros_like(rho)
+    bc = (PERIODIC,) * 6
+    bx, by, bz = zero.copy(), zero.copy(), zero.copy()
+    cell5 = _pack(rho, zero, zero, zero, P, bx, by, bz, gamma, bc)
+    pb = Problem("collapse", n, n, n, h, h, h, -1.0, -1.0, -1.0, gamma, bc, cell5, bx, by, bz,
+                 cfl=cfl, t_end=1.0)
+    pb.source, pb.src = SRC_SELF_GRAVITY, (G, 0.0, 0.0, 0.0)
+    return pb
+
+
 def shu_osher(n=200, axis=0) -> Problem:
     """Shu-Osher (section 3): a Mach-3 shock, {rho, u, P} = {3.857143,
     2.629369, 10.33333} for x < 0.125, running into rho = 1 + 0.2 sin(16 pi x),

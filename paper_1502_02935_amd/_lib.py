@@ -65,7 +65,8 @@ class mhd_profile_t(C.Structure):
                 ("n_kinds", C.c_int32), ("pad", C.c_int32)]
 
 
-KERNEL_KINDS = ("ghosts", "prim", "flux", "flux_mlp", "shock", "emf", "update", "cfl", "other")
+KERNEL_KINDS = ("ghosts", "prim", "flux", "flux_mlp", "shock", "emf", "update", "cfl", "other",
+                "gravity")
 
 
 class MHDError(RuntimeError):

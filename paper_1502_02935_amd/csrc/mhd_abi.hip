@@ -333,7 +333,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   else
     launch_prim<T>(g, c->ph, U, W, cnt, c->st);
   if (c->gravity()) {
-    c->mark(MHD_K_OTHER);
+    c->mark(MHD_K_GRAVITY);
     launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), c->st);
   }
   c->mark(MHD_K_FLUX);
@@ -350,7 +350,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->mark(MHD_K_PRIM);
   launch_prim<T>(g, c->ph, Us, W, cnt, c->st);
   if (c->gravity()) {
-    c->mark(MHD_K_OTHER);
+    c->mark(MHD_K_GRAVITY);
     launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), c->st);
   }
   if (c->mlp_params) {
