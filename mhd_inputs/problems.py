@@ -525,3 +525,59 @@ def random_face_states(m: int, seed: int = 0, *, gamma=5.0 / 3.0, shock_frac=0.3
     bn = rng.normal(0.0, 0.8, m)
     bn[rng.uniform(size=m) < 0.05] = 0.0
     return np.ascontiguousarray(wl), np.ascontiguousarray(wr), bn
+
+
+# ---------------------------------------------------------------------------
+# Passive scalars (mass fractions carried by the flow)
+# ---------------------------------------------------------------------------
+
+def cell_centres(pb: Problem):
+    """Cell-centre coordinate arrays X, Y, Z of shape (nz, ny, nx)."""
+    xc = pb.x0 + (np.arange(pb.nx) + 0.5) * pb.dx
+    yc = pb.y0 + (np.arange(pb.ny) + 0.5) * pb.dy
+    zc = pb.z0 + (np.arange(pb.nz) + 0.5) * pb.dz
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    return X, Y, Z
+
+
+def mass_fractions(pb: Problem, ns: int, kind: str = "random", *, seed: int = 0, axis: int = 0,
+                   x_split: float = 0.0, amp: float = 0.3, const: float = 0.25) -> np.ndarray:
+    """Conserved passive scalars rho X_s, float64 [ns][nz][ny][nx], for the
+    state of `pb` (rho from its cell5).
+
+    kind: "const"  X_s = const (s + 1) / ns;
+          "step"   X_s = 1 left of x_split along `axis`, 0 right of it (scalar
+                   s > 0: the complement 1 - X_0 for even s);
+          "sine"   X_s = 0.5 + amp sin(2 pi (s + 1) x / L) along `axis` (L the
+                   box length);
+          "random" X_s in (0, 1): logistic of a few random Fourier modes of the
+                   box (periodic), seeded."""
+    rho = pb.cell5[0]
+    X, Y, Z = cell_centres(pb)
+    coord = (X, Y, Z)[axis]
+    lo = (pb.x0, pb.y0, pb.z0)[axis]
+    L = (pb.nx * pb.dx, pb.ny * pb.dy, pb.nz * pb.dz)
+    out = np.empty((ns,) + rho.shape)
+    rng = np.random.default_rng(seed)
+    for s in range(ns):
+        if kind == "const":
+            x = np.full(rho.shape, const * (s + 1) / ns)
+        elif kind == "step":
+            x = np.where(coord < x_split, 1.0, 0.0)
+            if s % 2 == 1:
+                x = 1.0 - x
+        elif kind == "sine":
+            x = 0.5 + amp * np.sin(2.0 * math.pi * (s + 1) * (coord - lo) / L[axis])
+        elif kind == "random":
+            f = np.zeros(rho.shape)
+            for _ in range(4):
+                k = rng.integers(-3, 4, size=3)
+                ph = rng.uniform(0.0, 2.0 * math.pi)
+                f += rng.standard_normal() * np.cos(
+                    2.0 * math.pi * (k[0] * (X - pb.x0) / L[0] + k[1] * (Y - pb.y0) / L[1]
+                                     + k[2] * (Z - pb.z0) / L[2]) + ph)
+            x = 1.0 / (1.0 + np.exp(-2.0 * f))
+        else:
+            raise ValueError(kind)
+        out[s] = rho * x
+    return out

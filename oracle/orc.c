@@ -76,6 +76,9 @@ struct orc_grid {
   int64_t n_mlp, n_gated;
   /* self-gravity: potential and its central gradient at the cells (padded) */
   double *psi, *gpsi[3];
+  /* passive scalars: rho X at t^n and t^{n+1/2}, X of the stage, fluxes */
+  double *xs[ORC_MAX_SCALAR], *xss[ORC_MAX_SCALAR], *xw[ORC_MAX_SCALAR];
+  double *xf[3][ORC_MAX_SCALAR];
 };
 
 static long at(const orc_grid *g, int i, int j, int k) {
@@ -588,6 +591,13 @@ orc_grid *orc_create(const orc_config *cfg) {
   }
   for (m = 0; m < 8; ++m) g->w[m] = alloc_arr(g->np);
   g->shock = (unsigned char *)calloc((size_t)g->np, 1);
+  if (cfg->nscalar < 0 || cfg->nscalar > ORC_MAX_SCALAR) { orc_destroy(g); return NULL; }
+  for (m = 0; m < cfg->nscalar; ++m) {
+    g->xs[m] = alloc_arr(g->np);
+    g->xss[m] = alloc_arr(g->np);
+    g->xw[m] = alloc_arr(g->np);
+    for (a = 0; a < 3; ++a) g->xf[a][m] = alloc_arr(g->np);
+  }
   if (cfg->source == ORC_SRC_SELF_GRAVITY) {
     /* the potential of a periodic box only */
     for (a = 0; a < 3; ++a)
@@ -623,6 +633,10 @@ void orc_destroy(orc_grid *g) {
   free(g->mlp);
   free(g->psi);
   for (a = 0; a < 3; ++a) free(g->gpsi[a]);
+  for (m = 0; m < ORC_MAX_SCALAR; ++m) {
+    free(g->xs[m]); free(g->xss[m]); free(g->xw[m]);
+    for (a = 0; a < 3; ++a) free(g->xf[a][m]);
+  }
   free(g);
 }
 
@@ -662,7 +676,7 @@ static double inflow_value(const orc_grid *g, int m) {
     case 4:
       return q[4] / (gam - 1.0) + 0.5 * q[0] * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) +
              0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
-    default: return q[m];
+    default: return m < 8 ? q[m] : 0.0;  /* passive scalars: none flows in */
   }
 }
 
@@ -696,6 +710,19 @@ static void fill_ghosts(orc_grid *g, double *const u[5], double *const b[3]) {
   int m;
   for (m = 0; m < 5; ++m) fill_ghosts_one(g, u[m], -1, m);
   for (m = 0; m < 3; ++m) fill_ghosts_one(g, b[m], m, 5 + m);
+}
+
+static void fill_ghosts_scalars(orc_grid *g, double *const x[ORC_MAX_SCALAR]) {
+  int m;
+  for (m = 0; m < g->c.nscalar; ++m) fill_ghosts_one(g, x[m], -1, 100);
+}
+
+/* X_s = (rho X_s) / rho of the stage, on every padded cell the sweeps read. */
+static void scalar_prims(orc_grid *g, double *const x[ORC_MAX_SCALAR]) {
+  int m;
+  long p;
+  for (m = 0; m < g->c.nscalar; ++m)
+    for (p = 0; p < g->np; ++p) g->xw[m][p] = g->w[0][p] != 0.0 ? x[m][p] / g->w[0][p] : 0.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -866,6 +893,13 @@ static void sweep(orc_grid *g, int a, double *const bf[3], int recon) {
         g->fl[a][5 + t1][p] = f[5];
         g->fl[a][5 + t2][p] = f[6];
         g->sg[a][p] = f[0] > 0.0 ? 1 : (f[0] < 0.0 ? -1 : 0);
+        /* passive scalars ride on the (final) mass flux, upwinded */
+        for (c = 0; c < g->c.nscalar; ++c) {
+          double xl, xr;
+          double st4[4] = {g->xw[c][p - 2 * s], g->xw[c][p - s], g->xw[c][p], g->xw[c][p + s]};
+          orc_recon(st4, recon, g->c.kappa, &xl, &xr);
+          g->xf[a][c][p] = f[0] > 0.0 ? f[0] * xl : (f[0] < 0.0 ? f[0] * xr : 0.0);
+        }
       }
   }
   g->n_hll += nhll;
@@ -1062,8 +1096,29 @@ static void self_gravity(orc_grid *g) {
 /* ------------------------------------------------------------------------ */
 
 static void update(orc_grid *g, double dt, double *const u0[5], double *const b0[3],
-                   double *const u1[5], double *const b1[3]) {
+                   double *const u1[5], double *const b1[3], double *const x0[ORC_MAX_SCALAR],
+                   double *const x1[ORC_MAX_SCALAR]) {
   int a, k;
+  /* passive scalars: conservative update, no source */
+  {
+    double rx = dt / g->d[0], ry = dt / g->d[1], rz = dt / g->d[2];
+    int m;
+    for (m = 0; m < g->c.nscalar; ++m) {
+#pragma omp parallel for schedule(static)
+      for (k = 0; k < g->n[2]; ++k) {
+        int i, j;
+        for (j = 0; j < g->n[1]; ++j)
+          for (i = 0; i < g->n[0]; ++i) {
+            long p = at(g, i, j, k);
+            double v = x0[m][p];
+            v -= rx * (g->xf[0][m][p + g->st[0]] - g->xf[0][m][p]);
+            v -= ry * (g->xf[1][m][p + g->st[1]] - g->xf[1][m][p]);
+            v -= rz * (g->xf[2][m][p + g->st[2]] - g->xf[2][m][p]);
+            x1[m][p] = v;
+          }
+      }
+    }
+  }
   /* faces first (the floors below need the new cell-centred B) */
   for (a = 0; a < 3; ++a) {
     int b = (a + 1) % 3, c = (a + 2) % 3;
@@ -1175,19 +1230,23 @@ double orc_step(orc_grid *g, double dt) {
   if (!(dt > 0.0)) dt = orc_dt(g);
   /* predictor: first-order fluxes of U^n, half step */
   primitives(g, g->u, g->b);
+  scalar_prims(g, g->xs);
   if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g);
   for (a = 0; a < 3; ++a) sweep(g, a, g->b, ORC_RECON_FIRST);
   for (a = 0; a < 3; ++a) corner_emf(g, a);
-  update(g, 0.5 * dt, g->u, g->b, g->us, g->bs);
+  update(g, 0.5 * dt, g->u, g->b, g->us, g->bs, g->xs, g->xss);
   fill_ghosts(g, g->us, g->bs);
+  fill_ghosts_scalars(g, g->xss);
   /* corrector: MUSCL fluxes of U*, full step from U^n */
   primitives(g, g->us, g->bs);
+  scalar_prims(g, g->xss);
   if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g);
   if (g->mlp) shock_cells(g);
   for (a = 0; a < 3; ++a) sweep(g, a, g->bs, g->c.recon);
   for (a = 0; a < 3; ++a) corner_emf(g, a);
-  update(g, dt, g->u, g->b, g->u, g->b);
+  update(g, dt, g->u, g->b, g->u, g->b, g->xs, g->xs);
   fill_ghosts(g, g->u, g->b);
+  fill_ghosts_scalars(g, g->xs);
   g->t += dt;
   g->step += 1;
   return dt;
@@ -1196,6 +1255,27 @@ double orc_step(orc_grid *g, double dt) {
 /* ------------------------------------------------------------------------ */
 /* State in / out                                                           */
 /* ------------------------------------------------------------------------ */
+
+void orc_set_scalars(orc_grid *g, const double *rho_x) {
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2], i, j, k, m;
+  long ncell = (long)nx * ny * nz;
+  for (m = 0; m < g->c.nscalar; ++m)
+    for (k = 0; k < nz; ++k)
+      for (j = 0; j < ny; ++j)
+        for (i = 0; i < nx; ++i)
+          g->xs[m][at(g, i, j, k)] = rho_x[m * ncell + ((long)k * ny + j) * nx + i];
+  fill_ghosts_scalars(g, g->xs);
+}
+
+void orc_get_scalars(const orc_grid *g, double *rho_x) {
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2], i, j, k, m;
+  long ncell = (long)nx * ny * nz;
+  for (m = 0; m < g->c.nscalar; ++m)
+    for (k = 0; k < nz; ++k)
+      for (j = 0; j < ny; ++j)
+        for (i = 0; i < nx; ++i)
+          rho_x[m * ncell + ((long)k * ny + j) * nx + i] = g->xs[m][at(g, i, j, k)];
+}
 
 int orc_set_state(orc_grid *g, const double *cell5, const double *bx,
                   const double *by, const double *bz) {

@@ -69,7 +69,15 @@ typedef struct orc_config {
   double inflow[8];       /* primitive ghost state for ORC_BC_INFLOW sides:
                              rho, vx, vy, vz, P, Bx, By, Bz */
   int32_t riemann;        /* ORC_RIEMANN_* */
+  int32_t nscalar;        /* passive scalars (mass fractions X_s, conserved as rho X_s),
+                             0..ORC_MAX_SCALAR */
 } orc_config;
+
+/* Passive scalars (the code's multi-species advection): each X_s is carried
+   by the mass flux, F_{rho X} = F_rho X_up with X_up the reconstructed face
+   value on the side the mass comes from (the mean if F_rho = 0); no source,
+   untouched by the floors, zero in inflow ghosts. */
+#define ORC_MAX_SCALAR 8
 
 typedef struct orc_diag {
   double t;
@@ -92,6 +100,10 @@ int orc_set_state(orc_grid *g, const double *cell5, const double *bx,
 void orc_get_state(const orc_grid *g, double *cell5, double *bx, double *by,
                    double *bz);
 void orc_set_time(orc_grid *g, double t, int64_t step);
+/* Passive scalars rho X_s, interior cells [nscalar][nz][ny][nx] (all zero
+   after orc_create). */
+void orc_set_scalars(orc_grid *g, const double *rho_x);
+void orc_get_scalars(const orc_grid *g, double *rho_x);
 /* CFL time step of the current state. */
 double orc_dt(orc_grid *g);
 /* One full step of size dt (dt <= 0: use orc_dt()).  Returns the dt used. */

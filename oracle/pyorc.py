@@ -35,6 +35,7 @@ class _Cfg(C.Structure):
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("inflow", C.c_double * 8),
         ("riemann", C.c_int32),
+        ("nscalar", C.c_int32),
     ]
 
 
@@ -72,6 +73,7 @@ class OrcConfig:
     p_floor: float = 0.0
     inflow: tuple = field(default_factory=lambda: (0.0,) * 8)
     riemann: int = RIEMANN_HLLD
+    nscalar: int = 0
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -89,6 +91,7 @@ class OrcConfig:
         for i in range(8):
             c.inflow[i] = float(self.inflow[i])
         c.riemann = int(self.riemann)
+        c.nscalar = int(self.nscalar)
         return c
 
 
@@ -150,6 +153,8 @@ def load_oracle():
     L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
     L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
     L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+    L.orc_set_scalars.argtypes = [C.c_void_p, dp]
+    L.orc_get_scalars.argtypes = [C.c_void_p, dp]
     L.orc_dt.restype = C.c_double
     L.orc_dt.argtypes = [C.c_void_p]
     L.orc_step.restype = C.c_double
@@ -237,6 +242,17 @@ class Oracle:
         bx, by, bz = (np.empty(s) for s in fs)
         self.L.orc_get_state(self.h, _ptr(c5), _ptr(bx), _ptr(by), _ptr(bz))
         return c5, bx, by, bz
+
+    def set_scalars(self, rho_x):
+        """Passive scalars rho X_s, shape (nscalar, nz, ny, nx)."""
+        a = _f64(rho_x)
+        assert a.shape == (self.cfg.nscalar, self.cfg.nz, self.cfg.ny, self.cfg.nx), a.shape
+        self.L.orc_set_scalars(self.h, _ptr(a))
+
+    def get_scalars(self):
+        a = np.empty((self.cfg.nscalar, self.cfg.nz, self.cfg.ny, self.cfg.nx))
+        self.L.orc_get_scalars(self.h, _ptr(a))
+        return a
 
     def set_time(self, t: float, step: int = 0):
         self.L.orc_set_time(self.h, t, step)
