@@ -103,8 +103,12 @@ typedef struct mhd_config {
   double inflow[8];       /* ghost primitive state of MHD_BC_INFLOW sides:
                              rho, vx, vy, vz, P, Bx, By, Bz */
   int32_t riemann;        /* MHD_RIEMANN_*: HLLD (0, default), or the gas-dynamic HLL or HLLC */
-  int32_t reserved[3];    /* must be 0 */
+  int32_t nscalar;        /* passive scalars, 0..MHD_MAX_SCALARS (see mhd_set_scalars) */
+  int32_t reserved[2];    /* must be 0 */
 } mhd_config;
+
+/* Most passive scalars per context. */
+#define MHD_MAX_SCALARS 8
 
 typedef struct mhd_diag_t {
   double t;               /* simulated time */
@@ -135,7 +139,8 @@ int mhd_abi_version(void);
 const char *mhd_strerror(int code);
 
 /* Device workspace bytes needed for cfg (padded state, half-step state,
-   primitives, fluxes, edge EMFs, reduction scratch).  Returns MHD_E_ARG for
+   primitives, fluxes, edge EMFs, reduction scratch, passive scalars at the
+   two time levels).  Returns MHD_E_ARG for
    an invalid configuration. */
 int mhd_workspace_bytes(const mhd_config *cfg, size_t *out);
 
@@ -171,6 +176,24 @@ int mhd_diag(mhd_ctx *ctx, mhd_diag_t *out);
    (a checkpoint: mhd_init on it resumes bit-for-bit).  Synchronises. */
 int mhd_get_state(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_bz);
 
+/* Passive scalars (the multi-species advection of section 2.1): nscalar
+   mass fractions X_s, each carried by the flow as the conserved density
+   rho X_s with no source.  On every face the scalar flux is the mass flux
+   F_rho of that face (the final one, after any learned correction) times X_s
+   reconstructed like the other variables of the stage (first order in the
+   predictor, the configured MUSCL in the corrector) on the side the mass
+   comes from: F_rho X_L if F_rho > 0, F_rho X_R if F_rho < 0, 0 otherwise,
+   with X = (rho X) / rho of the stage's primitives.  The floors leave rho X
+   unchanged; inflow ghosts hold X = 0.  Sums of rho X over a periodic box
+   are conserved to rounding, and a uniform X stays uniform.
+   d_rho_x: device array [nscalar][nz][ny][nx] of the context precision
+   (interior cells, x fastest).  mhd_init sets every scalar to zero;
+   mhd_set_scalars replaces them (ghost zones refilled), mhd_get_scalars
+   copies them out.  Both synchronise; MHD_E_ARG if the context has no
+   scalars or the pointer is NULL. */
+int mhd_set_scalars(mhd_ctx *ctx, const void *d_rho_x);
+int mhd_get_scalars(mhd_ctx *ctx, void *d_rho_x);
+
 /* Copies one internal padded array of the last corrector stage to d_out
    (element type of the context precision, [nz+5][ny+5][nx+5], x fastest,
    interior cell (i,j,k) at ((k+2)(ny+5) + j+2)(nx+5) + i+2):
@@ -197,7 +220,8 @@ enum {
   MHD_K_CFL = 7,
   MHD_K_OTHER = 8,
   MHD_K_GRAVITY = 9,  /* self-gravity Poisson solve (FFTs, k-space division, gradient) */
-  MHD_K_COUNT = 10
+  MHD_K_SCALARS = 10, /* passive-scalar face fluxes and update, and their ghost fill */
+  MHD_K_COUNT = 11
 };
 
 typedef struct mhd_profile_t {

@@ -451,10 +451,11 @@ def uniform(n=(8, 8, 8), *, rho=1.0, v=(0.3, -0.2, 0.1), p=0.7, b=(0.5, -0.4, 0.
 
 
 def random_smooth(n=(16, 12, 10), seed=0, *, amp=0.3, gamma=5.0 / 3.0, bc=(PERIODIC,) * 6,
-                  b0=(0.6, 0.3, -0.2), d=None) -> Problem:
+                  b0=(0.6, 0.3, -0.2), d=None, b_amp=0.05) -> Problem:
     """Random periodic-ish smooth state for parity tests: a few random Fourier
     modes in rho, P, v and a divergence-free B from a random vector potential
-    (discrete curl of edge values, so div_h B is zero to rounding).  Works for
+    of amplitude b_amp (discrete curl of edge values, so div_h B is zero to
+    rounding) on the uniform field b0 (b_amp = 0 and b0 = 0: no field).  Works for
     any boundary conditions (the potential is sampled, not assumed periodic)."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = n
@@ -483,9 +484,9 @@ def random_smooth(n=(16, 12, 10), seed=0, *, amp=0.3, gamma=5.0 / 3.0, bc=(PERIO
     ye = np.arange(ny + 2) * d[1]
     ze = np.arange(nz + 2) * d[2]
     Ze, Ye, Xe = np.meshgrid(ze, ye, xe, indexing="ij")
-    Ax = 0.05 * field_at(Xe + 0.5 * d[0], Ye, Ze) * d[0]
-    Ay = 0.05 * field_at(Xe, Ye + 0.5 * d[1], Ze) * d[1]
-    Az = 0.05 * field_at(Xe, Ye, Ze + 0.5 * d[2]) * d[2]
+    Ax = b_amp * field_at(Xe + 0.5 * d[0], Ye, Ze) * d[0]
+    Ay = b_amp * field_at(Xe, Ye + 0.5 * d[1], Ze) * d[1]
+    Az = b_amp * field_at(Xe, Ye, Ze + 0.5 * d[2]) * d[2]
     if bc[0] == PERIODIC:  # wrap so the curl is periodic
         Ax[:, :, nx:] = Ax[:, :, :2]; Ay[:, :, nx:] = Ay[:, :, :2]; Az[:, :, nx:] = Az[:, :, :2]
     if bc[2] == PERIODIC:

@@ -36,7 +36,8 @@ class mhd_config(C.Structure):
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("inflow", C.c_double * 8),
         ("riemann", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("nscalar", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -66,7 +67,8 @@ class mhd_profile_t(C.Structure):
 
 
 KERNEL_KINDS = ("ghosts", "prim", "flux", "flux_mlp", "shock", "emf", "update", "cfl", "other",
-                "gravity")
+                "gravity", "scalars")
+MAX_SCALARS = 8
 
 
 class MHDError(RuntimeError):
@@ -104,6 +106,10 @@ def load() -> C.CDLL:
     L.mhd_diag.argtypes = [vp, C.POINTER(mhd_diag_t)]
     L.mhd_get_state.restype = C.c_int
     L.mhd_get_state.argtypes = [vp, vp, vp, vp, vp]
+    L.mhd_set_scalars.restype = C.c_int
+    L.mhd_set_scalars.argtypes = [vp, vp]
+    L.mhd_get_scalars.restype = C.c_int
+    L.mhd_get_scalars.argtypes = [vp, vp]
     L.mhd_debug_array.restype = C.c_int
     L.mhd_debug_array.argtypes = [vp, C.c_int, vp, C.POINTER(sz)]
     L.mhd_profile.restype = C.c_int

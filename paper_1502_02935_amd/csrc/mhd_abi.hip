@@ -37,6 +37,8 @@ struct Layout {
   size_t off_frag;  // learned correction: weights packed as bf16 MFMA fragments
   size_t off_grav;  // self-gravity: 4 padded T arrays (Psi, grad Psi), the complex
                     // [nz][ny][nx] array, twiddle and eigenvalue tables (0 bytes if off)
+  size_t off_scal;  // passive scalars: nscalar padded T arrays at t^n, then nscalar at
+                    // t^{n+1/2}
   size_t total;
 };
 
@@ -90,7 +92,8 @@ bool config_ok(const mhd_config* c) {
   }
   if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0)) return false;
   if (c->riemann < MHD_RIEMANN_HLLD || c->riemann > MHD_RIEMANN_HLLC) return false;
-  for (int q = 0; q < 3; ++q)
+  if (c->nscalar < 0 || c->nscalar > MHD_MAX_SCALARS) return false;
+  for (int q = 0; q < 2; ++q)
     if (c->reserved[q] != 0) return false;
   Geo g;
   if (!geo_of(c, &g)) return false;
@@ -121,7 +124,8 @@ Layout layout_of(const mhd_config* c) {
     grav = 4 * L.arr + align_up(ncell * 2 * es);
     for (int a = 0; a < 3; ++a) grav += align_up((size_t)g.n[a] * 2 * es);  // twiddles, eigenvalues
   }
-  L.total = L.off_grav + grav;
+  L.off_scal = L.off_grav + grav;
+  L.total = L.off_scal + 2 * (size_t)c->nscalar * L.arr;
   return L;
 }
 
@@ -241,6 +245,14 @@ struct mhd_ctx {
     for (int a = 0; a < 3; ++a) e.e[a] = (T*)arr(48 + a);
     return e;
   }
+  int nscalar() const { return cfg.nscalar; }
+  template <class T>
+  Scal<T> scal(int set) const {  // set 0: rho X at t^n, 1: at t^{n+1/2}
+    Scal<T> s{};
+    for (int m = 0; m < cfg.nscalar; ++m)
+      s.x[m] = (T*)(ws + L.off_scal + ((size_t)set * cfg.nscalar + m) * L.arr);
+    return s;
+  }
   bool gravity() const { return cfg.source == MHD_SRC_SELF_GRAVITY; }
   template <class T>
   Grav<T> grav() const {
@@ -325,6 +337,8 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   const Edge<T> E = c->edge<T>();
   const Muscl<T> first = muscl_of<T>(MHD_RECON_FIRST, c->cfg.kappa);
   const Muscl<T> second = muscl_of<T>(c->cfg.recon, c->cfg.kappa);
+  const int ns = c->nscalar();
+  const Scal<T> Xn = c->scal<T>(0), Xh = c->scal<T>(1);
   // predictor: first-order fluxes of U^n, half step into U*; a step that
   // takes its dt from the device gets it from the same primitives pass
   c->mark(MHD_K_PRIM);
@@ -344,6 +358,11 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   half.factor = 0.5;
   c->mark(MHD_K_UPDATE);
   launch_update<T>(g, c->ph, U, Us, W, F, E, c->grav<T>(), half, cnt, c->st);
+  if (ns) {
+    c->mark(MHD_K_SCALARS);
+    launch_scalar_update<T>(g, W.w[0], F, Xn, Xn, Xh, ns, first, half, c->st);
+    launch_scalar_ghosts<T>(g, Xh, ns, c->st);
+  }
   c->mark(MHD_K_GHOSTS);
   launch_ghosts<T>(g, c->ph, Us, c->st);
   // corrector: MUSCL fluxes of U*, full step from U^n
@@ -374,6 +393,11 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   launch_emf<T>(g, W, F, E, c->st);
   c->mark(MHD_K_UPDATE);
   launch_update<T>(g, c->ph, U, U, W, F, E, c->grav<T>(), dt, cnt, c->st);
+  if (ns) {
+    c->mark(MHD_K_SCALARS);
+    launch_scalar_update<T>(g, W.w[0], F, Xn, Xh, Xn, ns, second, dt, c->st);
+    launch_scalar_ghosts<T>(g, Xn, ns, c->st);
+  }
   c->mark(MHD_K_GHOSTS);
   launch_ghosts<T>(g, c->ph, U, c->st);
   c->mark(MHD_K_OTHER);
@@ -465,7 +489,9 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
   c->L = L;
   c->sticky = false;
   if (hipMemsetAsync(c->misc(), 0, 64 * sizeof(double), c->st) != hipSuccess ||
-      hipMemsetAsync(c->counter_slots(), 0, L.off_cfl - L.off_cnt, c->st) != hipSuccess) {
+      hipMemsetAsync(c->counter_slots(), 0, L.off_cfl - L.off_cnt, c->st) != hipSuccess ||
+      (cfg->nscalar > 0 &&
+       hipMemsetAsync(c->ws + L.off_scal, 0, L.total - L.off_scal, c->st) != hipSuccess)) {
     delete c;
     return MHD_E_HIP;
   }
@@ -595,6 +621,26 @@ int mhd_get_state(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz)
   if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
   return MHD_OK;
 }
+
+static int scalar_copy(mhd_ctx* c, void* d, bool in) {
+  if (!c || !d || c->nscalar() == 0) return MHD_E_ARG;
+  if (c->cfg.precision == MHD_FP64) {
+    launch_scalar_copy<double>(c->g, c->scal<double>(0), c->nscalar(), (double*)d, in, c->st);
+    if (in) launch_scalar_ghosts<double>(c->g, c->scal<double>(0), c->nscalar(), c->st);
+  } else {
+    launch_scalar_copy<float>(c->g, c->scal<float>(0), c->nscalar(), (float*)d, in, c->st);
+    if (in) launch_scalar_ghosts<float>(c->g, c->scal<float>(0), c->nscalar(), c->st);
+  }
+  if (hip_status() != MHD_OK) return MHD_E_HIP;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
+  return MHD_OK;
+}
+
+int mhd_set_scalars(mhd_ctx* c, const void* d_rho_x) {
+  return scalar_copy(c, const_cast<void*>(d_rho_x), true);
+}
+
+int mhd_get_scalars(mhd_ctx* c, void* d_rho_x) { return scalar_copy(c, d_rho_x, false); }
 
 int mhd_debug_array(mhd_ctx* c, int what, void* d_out, size_t* n_out) {
   if (!c || !d_out || what < 0 || what > 38) return MHD_E_ARG;

@@ -129,12 +129,11 @@ __device__ __forceinline__ int map_axis(int c, int m, int n, int bclo, int bchi,
   return c;
 }
 
-template <class T>
-__global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// Thread t -> ghost point c (the 5 ghost layers of x, then of y, then of z,
+// over the full extent of the other two axes); false past the last one.
+__device__ __forceinline__ bool ghost_point(const Geo& g, long long t, int c[3]) {
   const long long E0 = g.ext[0], E1 = g.ext[1], E2 = g.ext[2];
   const long long nx5 = 5 * E1 * E2, ny5 = 5 * E0 * E2, nz5 = 5 * E0 * E1;
-  int c[3];
   long long r;
   if (t < nx5) {
     const int l = (int)(t % 5);
@@ -157,8 +156,21 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
     c[0] = (int)(r % E0) - NG;
     c[1] = (int)(r / E0) - NG;
   } else {
-    return;
+    return false;
   }
+  return true;
+}
+
+static unsigned ghost_blocks(const Geo& g, int bs) {
+  const long long tot = 5ll * ((long long)g.ext[1] * g.ext[2] + (long long)g.ext[0] * g.ext[2] +
+                               (long long)g.ext[0] * g.ext[1]);
+  return (unsigned)((tot + bs - 1) / bs);
+}
+
+template <class T>
+__global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
+  int c[3];
+  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, c)) return;
   const int p = pidx(g, c[0], c[1], c[2]);
   // cell arrays
   {
@@ -194,11 +206,7 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
 
 template <class T>
 void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, hipStream_t st) {
-  const long long tot = 5ll * ((long long)g.ext[1] * g.ext[2] + (long long)g.ext[0] * g.ext[2] +
-                               (long long)g.ext[0] * g.ext[1]);
-  const int bs = 256;
-  hipLaunchKernelGGL(k_ghosts<T>, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, st, g, ph,
-                     s);
+  hipLaunchKernelGGL(k_ghosts<T>, dim3(ghost_blocks(g, 256)), dim3(256), 0, st, g, ph, s);
 }
 
 // ------------------------------------------------------------------------
@@ -1037,6 +1045,122 @@ void launch_gather(const Geo& g, Cons<T> s, T* cell5, T* bx, T* by, T* bz, hipSt
 }
 
 // ------------------------------------------------------------------------
+// Passive scalars (mass fractions X_s, conserved as rho X_s).  The face flux
+// is the face's mass flux times X reconstructed on the side the mass comes
+// from.  One kernel per stage: each interior cell rebuilds the two faces of
+// each axis it needs from X = (rho X) / rho on its 13-point stencil and
+// applies the update, so no scalar flux array is written or read back (each
+// face is computed by its two cells; the arithmetic is cheap next to the
+// traffic an extra array pair per scalar and axis would cost).
+// ------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ T scalar_flux(T F, T xl, T xr) {
+  return F > T(0) ? F * xl : (F < T(0) ? F * xr : T(0));
+}
+
+template <class T>
+__global__ void __launch_bounds__(kSpanThreads) k_scalar_update(Geo g, Span sp,
+                                                                const T* __restrict__ rho,
+                                                                Flux<T> f, Scal<T> x0, Scal<T> xs,
+                                                                Scal<T> x1, int ns, Muscl<T> mu,
+                                                                DtRef dtr) {
+  const Pt pt = span_point(g, sp);
+  if (!pt.valid) return;
+  const int p = pt.p;
+  const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
+  const int st[3] = {1, g.sy, g.sz};
+  // 1 / rho on the stencil p + (o - 2) s_a; mass fluxes of the low and high face
+  T ir[3][5], flo[3], fhi[3], r[3];
+  const T ic = rcp(rho[p]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int o = 0; o < 5; ++o) ir[a][o] = o == 2 ? ic : rcp(rho[p + (o - 2) * st[a]]);
+    flo[a] = f.f[a][0][p];
+    fhi[a] = f.f[a][0][p + st[a]];
+    r[a] = (T)(dt / g.d[a]);
+  }
+  for (int m = 0; m < ns; ++m) {
+    const T* q = xs.x[m];
+    T v = x0.x[m][p];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T X[5];
+#pragma unroll
+      for (int o = 0; o < 5; ++o) X[o] = q[p + (o - 2) * st[a]] * ir[a][o];
+      T l0, r0, l1, r1;
+      muscl_lr(mu, X[0], X[1], X[2], X[3], l0, r0);
+      muscl_lr(mu, X[1], X[2], X[3], X[4], l1, r1);
+      v -= r[a] * (scalar_flux(fhi[a], l1, r1) - scalar_flux(flo[a], l0, r0));
+    }
+    x1.x[m][p] = v;
+  }
+}
+
+template <class T>
+void launch_scalar_update(const Geo& g, const T* rho, Flux<T> f, Scal<T> x0, Scal<T> xs,
+                          Scal<T> x1, int ns, Muscl<T> m, DtRef dt, hipStream_t st) {
+  if (ns <= 0) return;
+  const Span sp = make_span(g, 0, g.n[0] - 1, 0, g.n[1] - 1, 0, g.n[2] - 1);
+  hipLaunchKernelGGL(k_scalar_update<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, sp, rho, f,
+                     x0, xs, x1, ns, m, dt);
+}
+
+// Ghost points of the scalar arrays: periodic wrap / outflow copy as for the
+// cell fields; inflow ghosts hold no scalar.
+template <class T>
+__global__ void k_scalar_ghosts(Geo g, Scal<T> x, int ns) {
+  int c[3];
+  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, c)) return;
+  const int p = pidx(g, c[0], c[1], c[2]);
+  bool inflow = false;
+  int m[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    m[a] = map_axis(c[a], g.n[a], g.n[a], g.bc[2 * a], g.bc[2 * a + 1], inflow);
+  if (inflow) {
+    for (int q = 0; q < ns; ++q) x.x[q][p] = T(0);
+  } else if (m[0] != c[0] || m[1] != c[1] || m[2] != c[2]) {
+    const int q0 = pidx(g, m[0], m[1], m[2]);
+    for (int q = 0; q < ns; ++q) x.x[q][p] = x.x[q][q0];
+  }
+}
+
+template <class T>
+void launch_scalar_ghosts(const Geo& g, Scal<T> x, int ns, hipStream_t st) {
+  if (ns <= 0) return;
+  hipLaunchKernelGGL(k_scalar_ghosts<T>, dim3(ghost_blocks(g, 256)), dim3(256), 0, st, g, x, ns);
+}
+
+template <class T, bool IN>
+__global__ void __launch_bounds__(BX* BY) k_scalar_copy(Geo g, Scal<T> x, int ns, T* interior) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.n[0] || j >= g.n[1]) return;
+  const int p = pidx(g, i, j, k);
+  const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
+  const size_t q = ((size_t)k * g.n[1] + j) * g.n[0] + i;
+  for (int m = 0; m < ns; ++m) {
+    if (IN)
+      x.x[m][p] = interior[m * ncell + q];
+    else
+      interior[m * ncell + q] = x.x[m][p];
+  }
+}
+
+template <class T>
+void launch_scalar_copy(const Geo& g, Scal<T> x, int ns, T* interior, bool in, hipStream_t st) {
+  if (ns <= 0) return;
+  const dim3 gr = grid_for(g.n[0], g.n[1], g.n[2]);
+  if (in)
+    hipLaunchKernelGGL((k_scalar_copy<T, true>), gr, dim3(BX, BY), 0, st, g, x, ns, interior);
+  else
+    hipLaunchKernelGGL((k_scalar_copy<T, false>), gr, dim3(BX, BY), 0, st, g, x, ns, interior);
+}
+
+// ------------------------------------------------------------------------
 // Batch entry points for kernel-level parity tests.
 // ------------------------------------------------------------------------
 
@@ -1107,7 +1231,11 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_gather<T>(const Geo&, Cons<T>, T*, T*, T*, T*, hipStream_t);             \
   template void launch_hlld_batch<T>(int64_t, const T*, const T*, const T*, T, T*, int8_t*,     \
                                      hipStream_t);                                               \
-  template void launch_recon_batch<T>(int64_t, const T*, Muscl<T>, T*, T*, hipStream_t);
+  template void launch_recon_batch<T>(int64_t, const T*, Muscl<T>, T*, T*, hipStream_t);       \
+  template void launch_scalar_update<T>(const Geo&, const T*, Flux<T>, Scal<T>, Scal<T>,        \
+                                        Scal<T>, int, Muscl<T>, DtRef, hipStream_t);            \
+  template void launch_scalar_ghosts<T>(const Geo&, Scal<T>, int, hipStream_t);                 \
+  template void launch_scalar_copy<T>(const Geo&, Scal<T>, int, T*, bool, hipStream_t);
 
 MHD_INST(double)
 MHD_INST(float)

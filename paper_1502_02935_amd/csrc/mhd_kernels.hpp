@@ -111,6 +111,13 @@ struct GravFFT {
   const T* lam[3];
 };
 
+// Passive scalars rho X_s (padded arrays, the first ns entries used).
+constexpr int kMaxScalars = 8;
+template <class T>
+struct Scal {
+  T* x[kMaxScalars];
+};
+
 // Time-step source: a value, or (if ptr != nullptr) a device scalar.
 struct DtRef {
   double value;
@@ -142,6 +149,17 @@ void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c, hipStream_t st);
+// Passive scalars of one stage: x1 = x0 - dt div F_X, with F_X the mass flux
+// of f times X = xs / rho (rho: the stage's primitive density) reconstructed
+// by m on the upwind side; interior cells.  x1 may be x0.
+template <class T>
+void launch_scalar_update(const Geo& g, const T* rho, Flux<T> f, Scal<T> x0, Scal<T> xs,
+                          Scal<T> x1, int ns, Muscl<T> m, DtRef dt, hipStream_t st);
+template <class T>
+void launch_scalar_ghosts(const Geo& g, Scal<T> x, int ns, hipStream_t st);
+// Interior [ns][nz][ny][nx] <-> padded scalar arrays.
+template <class T>
+void launch_scalar_copy(const Geo& g, Scal<T> x, int ns, T* interior, bool in, hipStream_t st);
 // Psi of the stage density rho (padded primitive array) and its gradient
 // into gr (mhd_gravity.hip).
 template <class T>

@@ -35,6 +35,7 @@ class MHDConfig:
     p_floor: float = 0.0
     inflow: tuple = field(default_factory=lambda: (0.0,) * 8)
     riemann: int = L.RIEMANN_HLLD
+    nscalar: int = 0
 
     def to_c(self) -> L.mhd_config:
         c = L.mhd_config()
@@ -52,6 +53,7 @@ class MHDConfig:
         for i in range(8):
             c.inflow[i] = float(self.inflow[i])
         c.riemann = int(self.riemann)
+        c.nscalar = int(self.nscalar)
         return c
 
     @property
@@ -67,12 +69,13 @@ class MHDConfig:
 
 
 def config_from_problem(pb, precision=L.MHD_FP64, recon=L.RECON_PAPER, kappa=1.0 / 3.0,
-                        cfl=None, riemann=L.RIEMANN_HLLD) -> MHDConfig:
+                        cfl=None, riemann=L.RIEMANN_HLLD, nscalar=0) -> MHDConfig:
     return MHDConfig(nx=pb.nx, ny=pb.ny, nz=pb.nz, dx=pb.dx, dy=pb.dy, dz=pb.dz, x0=pb.x0,
                      y0=pb.y0, z0=pb.z0, precision=precision, gamma=pb.gamma,
                      cfl=pb.cfl if cfl is None else cfl, bc=tuple(pb.bc), recon=recon,
                      kappa=kappa, source=pb.source, src=tuple(pb.src), rho_floor=pb.rho_floor,
-                     p_floor=pb.p_floor, inflow=tuple(pb.inflow), riemann=riemann)
+                     p_floor=pb.p_floor, inflow=tuple(pb.inflow), riemann=riemann,
+                     nscalar=nscalar)
 
 
 def workspace_bytes(cfg: MHDConfig) -> int:
@@ -214,6 +217,21 @@ class Sim:
         L.check(self.L.mhd_mlp_samples(self.ctx, _ptr(acc), dt_coarse, n, _ptr(faces), _ptr(x),
                                        _ptr(t), _ptr(m)), "mhd_mlp_samples")
         return x, t, m
+
+    # ---- passive scalars ------------------------------------------------------
+
+    def set_scalars(self, rho_x):
+        """Replace the passive scalars rho X_s ([nscalar][nz][ny][nx])."""
+        cfg = self.cfg
+        a = _dev(rho_x, cfg.dtype, self.device)
+        assert tuple(a.shape) == (cfg.nscalar, cfg.nz, cfg.ny, cfg.nx), a.shape
+        L.check(self.L.mhd_set_scalars(self.ctx, _ptr(a)), "mhd_set_scalars")
+
+    def get_scalars(self) -> torch.Tensor:
+        cfg = self.cfg
+        a = torch.empty((cfg.nscalar, cfg.nz, cfg.ny, cfg.nx), dtype=cfg.dtype, device=self.device)
+        L.check(self.L.mhd_get_scalars(self.ctx, _ptr(a)), "mhd_get_scalars")
+        return a
 
     def get_state(self):
         cfg = self.cfg

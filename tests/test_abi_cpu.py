@@ -39,7 +39,7 @@ def test_workspace_bytes_valid():
     dict(nx=0), dict(ny=-3), dict(dx=0.0), dict(dz=-1.0), dict(gamma=1.0), dict(cfl=0.0),
     dict(cfl=1.5), dict(precision=2), dict(recon=5), dict(kappa=1.0), dict(source=9),
     dict(rho_floor=-1.0), dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(7, 7, 0, 0, 0, 0)),
-    dict(nx=1 << 21), dict(nx=2048, ny=2048, nz=1024),
+    dict(nx=1 << 21), dict(nx=2048, ny=2048, nz=1024), dict(nscalar=-1), dict(nscalar=9),
 ])
 def test_workspace_bytes_rejects(bad):
     c = _cfg(**bad).to_c()
@@ -57,6 +57,8 @@ def test_null_arguments_rejected():
     assert lib.mhd_diag(None, None) == L.MHD_E_ARG
     assert lib.mhd_destroy(None) == L.MHD_E_ARG
     assert lib.mhd_get_state(None, None, None, None, None) == L.MHD_E_ARG
+    assert lib.mhd_set_scalars(None, None) == L.MHD_E_ARG
+    assert lib.mhd_get_scalars(None, None) == L.MHD_E_ARG
     ctx = C.c_void_p()
     assert lib.mhd_init(C.byref(c), None, 0, None, None, None, None, None,
                         C.byref(ctx)) == L.MHD_E_ARG
@@ -87,3 +89,12 @@ def test_self_gravity_needs_periodic_power_of_two_box():
     # the gravity buffers come on top of the plain step's
     plain = workspace_bytes(MHDConfig(nx=32, ny=16, nz=8, dx=0.1, dy=0.1, dz=0.1))
     assert workspace_bytes(MHDConfig(nx=32, ny=16, nz=8, **base)) > plain
+
+
+def test_scalars_add_two_padded_arrays_each():
+    """Each passive scalar takes two padded arrays (t^n and t^{n+1/2})."""
+    base = workspace_bytes(_cfg())
+    arr = (16 + 5) * (8 + 5) * (4 + 5) * 8
+    arr = (arr + 255) // 256 * 256
+    for ns in (1, 3, 8):
+        assert workspace_bytes(_cfg(nscalar=ns)) == base + 2 * ns * arr

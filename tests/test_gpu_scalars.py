@@ -1,0 +1,199 @@
+"""GPU parity of the passive scalars (mass fractions carried by the upwinded
+mass flux, conserved as rho X) against the FP64 oracle: same seeded inputs,
+same time steps, every interior cell of every scalar compared element by
+element (relative to the scalar's max), tolerance 1e-11 in FP64; sampled
+parity on the full-size box; invariants in FP32 and with the learned
+correction on."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from mhd_inputs import problems as P
+from oracle import pyorc as O
+from tests import subbox
+from tests.gpu_util import field_errors, gpu_sim, host_state, needs_gpu, rel_err
+from tests.helpers import orc_config
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+TOL = 1e-11
+
+
+def _pair(pb, rx, precision=0, recon=O.RECON_PAPER, riemann=O.RIEMANN_HLLD):
+    from paper_1502_02935_amd import Sim, config_from_problem
+    cfg = orc_config(pb, recon=recon, riemann=riemann)
+    cfg.nscalar = rx.shape[0]
+    o = O.Oracle(cfg)
+    assert o.set_state(pb.cell5, pb.bx, pb.by, pb.bz) == 0
+    o.set_scalars(rx)
+    gc = config_from_problem(pb, precision=precision, recon=recon, riemann=riemann,
+                             nscalar=rx.shape[0])
+    s = Sim(gc, pb.cell5, pb.bx, pb.by, pb.bz)
+    s.set_scalars(rx)
+    return o, s
+
+
+def _run_both(o, s, nsteps):
+    dts = []
+    for _ in range(nsteps):
+        dts.append(o.dt())
+        o.step(dts[-1])
+    s.step(nsteps, dt=dts)
+    return dts
+
+
+def _scalar_errors(s, o):
+    g = s.get_scalars().double().cpu().numpy()
+    r = o.get_scalars()
+    return [rel_err(g[m], r[m]) for m in range(r.shape[0])]
+
+
+def test_set_get_roundtrip_and_errors():
+    import torch
+    from paper_1502_02935_amd import _lib as L
+    pb = P.random_smooth((20, 9, 7), seed=1)
+    rx = P.mass_fractions(pb, 3, "random", seed=2)
+    _, s = _pair(pb, rx)
+    np.testing.assert_array_equal(s.get_scalars().cpu().numpy(), rx)
+    s0 = gpu_sim(pb)
+    with pytest.raises(L.MHDError):
+        s0.get_scalars()
+    buf = torch.zeros((1, pb.nz, pb.ny, pb.nx), dtype=torch.float64, device="cuda")
+    assert s0.L.mhd_set_scalars(s0.ctx, buf.data_ptr()) == L.MHD_E_ARG
+
+
+@pytest.mark.parametrize("bc", [(P.PERIODIC,) * 6,
+                                (P.INFLOW, P.OUTFLOW, P.OUTFLOW, P.OUTFLOW, P.PERIODIC,
+                                 P.PERIODIC)])
+def test_random_box_parity(bc):
+    """Three random fractions on a ragged 3-D box (several span blocks and a
+    ragged tail), 8 steps; periodic, and inflow/outflow sides.  The inflow
+    state moves across the box too: with zero transverse velocity the mass
+    flux between two inflow ghost cells is zero in exact arithmetic and its
+    sign -- which picks the upwind side of the corner EMF -- is rounding
+    noise that no two implementations share."""
+    pb = P.random_smooth((70, 19, 13), seed=3, bc=bc)
+    if bc[0] == P.INFLOW:
+        pb = replace(pb, inflow=(1.0, 0.4, 0.15, -0.1, 0.5, 0.6, 0.3, -0.2))
+    rx = P.mass_fractions(pb, 3, "random", seed=4)
+    o, s = _pair(pb, rx)
+    _run_both(o, s, 8)
+    err = _scalar_errors(s, o)
+    assert max(err) <= TOL, err
+    ferr = field_errors(host_state(s), o.get_state())
+    assert max(ferr.values()) <= TOL, ferr
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_sod_step_parity_each_axis(axis):
+    """Sod tube along each axis with a step fraction and its complement."""
+    pb = P.sod(100, axis=axis)
+    rx = P.mass_fractions(pb, 2, "step", axis=axis, x_split=0.0)
+    o, s = _pair(pb, rx)
+    _run_both(o, s, 40)
+    err = _scalar_errors(s, o)
+    assert max(err) <= TOL, err
+
+
+@pytest.mark.parametrize("recon,riemann", [(O.RECON_KAPPA, O.RIEMANN_HLLD),
+                                           (O.RECON_PAPER, O.RIEMANN_HLLC)])
+def test_parity_other_reconstruction_and_solver(recon, riemann):
+    """kappa-MUSCL with HLLD; HLLC (gas dynamics: no field in the box)."""
+    if riemann == O.RIEMANN_HLLC:
+        pb = P.random_smooth((24, 20, 16), seed=5, b0=(0.0, 0.0, 0.0), b_amp=0.0)
+    else:
+        pb = P.random_smooth((24, 20, 16), seed=5)
+    rx = P.mass_fractions(pb, 2, "random", seed=6)
+    o, s = _pair(pb, rx, recon=recon, riemann=riemann)
+    _run_both(o, s, 5)
+    err = _scalar_errors(s, o)
+    assert max(err) <= TOL, err
+
+
+def test_eight_scalars_self_dt():
+    """The largest scalar count, steps with the device's own CFL dt."""
+    pb = P.random_smooth((16, 12, 10), seed=7)
+    rx = P.mass_fractions(pb, 8, "random", seed=8)
+    o, s = _pair(pb, rx)
+    for _ in range(4):
+        o.step()
+    s.step(4)
+    err = _scalar_errors(s, o)
+    assert max(err) <= TOL, err
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_uniform_fraction_and_totals_with_learned_correction(precision):
+    """With the learned correction on, the scalar still rides on the final
+    mass flux: a uniform X stays uniform, totals stay constant."""
+    import torch
+    pb = P.random_smooth((24, 20, 16), seed=9)
+    rx = np.concatenate([P.mass_fractions(pb, 1, "const", const=0.4),
+                         P.mass_fractions(pb, 1, "random", seed=10)])
+    if precision == 1:
+        pb = pb.astype("float32")
+        rx = rx.astype(np.float32).astype(np.float64)
+    _, s = _pair(pb, rx, precision=precision)
+    params = np.random.default_rng(11).normal(0, 0.05, O.MLP_NPARAM)
+    pt = torch.as_tensor(params, dtype=torch.float32, device="cuda")
+    s.set_mlp(pt, tau=0.5, jump=0.5, tau_flux=0.5)
+    s.step(4)
+    assert s.diag()["n_mlp_faces"] > 0
+    rho = s.get_state()[0][0].double()
+    ry = s.get_scalars().double()
+    x0 = ry[0] / rho
+    tol_u = 1e-13 if precision == 0 else 2e-6
+    assert float((x0 - 0.4).abs().max()) <= tol_u
+    tol_c = 1e-13 if precision == 0 else 1e-6
+    for m in range(2):
+        t0, t1 = float(rx[m].sum()), float(ry[m].sum())
+        assert abs(t1 - t0) <= tol_c * abs(t0), (m, t0, t1)
+
+
+N, STEPS, DT, M, MARGIN = 256, 4, 1.5e-4, 48, 14
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fullsize_sampled(precision):
+    """The 256^3 turbulent box with four fractions: the GPU advances the
+    whole box, the oracle 48^3 boxes cut around seeded points; cells 14 or
+    more in from a cut's sides compared (FP64 1e-11; FP32 from the
+    FP32-rounded state: max 1e-4 of the scalar's scale, L1 1e-6)."""
+    pb = P.turbulent_ism(N, seed=1)
+    rx = P.mass_fractions(pb, 4, "random", seed=12)
+    if precision == 1:
+        pb = pb.astype("float32")
+        rx = rx.astype(np.float32).astype(np.float64)
+    from paper_1502_02935_amd import Sim, config_from_problem
+    s = Sim(config_from_problem(pb, precision=precision, nscalar=4), pb.cell5, pb.bx, pb.by,
+            pb.bz)
+    s.set_scalars(rx)
+    s.step(STEPS, dt=[DT] * STEPS)
+    assert s.diag()["status"] == 0
+    g = s.get_scalars().double().cpu().numpy()
+    s.close()
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        lo = tuple(int(v) for v in rng.integers(0, N, 3))
+        sub = subbox.cut(pb, lo, M)
+        iz, iy, ix = (np.arange(lo[a], lo[a] + M) % N for a in (2, 1, 0))
+        rxs = np.ascontiguousarray(rx[:, iz][:, :, iy][:, :, :, ix])
+        cfg = orc_config(sub)
+        cfg.nscalar = 4
+        o = O.Oracle(cfg)
+        assert o.set_state(sub.cell5, sub.bx, sub.by, sub.bz) == 0
+        o.set_scalars(rxs)
+        for _ in range(STEPS):
+            o.step(DT)
+        k = np.arange(MARGIN, M - MARGIN)
+        ref = o.get_scalars()[:, k][:, :, k][:, :, :, k]
+        gz, gy, gx = ((lo[a] + k) % N for a in (2, 1, 0))
+        got = g[:, gz][:, :, gy][:, :, :, gx]
+        for m in range(4):
+            e = rel_err(got[m], ref[m])
+            if precision == 0:
+                assert e <= TOL, (lo, m, e)
+            else:
+                assert e <= 1e-4, (lo, m, e)
+                assert np.abs(got[m] - ref[m]).mean() <= 1e-6 * np.abs(ref[m]).mean(), (lo, m)
