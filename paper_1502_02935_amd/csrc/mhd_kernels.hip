@@ -36,34 +36,54 @@ static dim3 grid_for(int nx, int ny, int nz) {
 
 // ------------------------------------------------------------------------
 // Sweep geometry.  A sweep visits the points lo..hi (inclusive, per axis) of
-// the padded grid.  Each z-plane's rows lo_y..hi_y are walked as one run of
-// whole padded x-rows (row stride sy), kSpanThreads points per block, so a
-// wave's 64 lanes always touch 64 consecutive addresses and only the few
-// padding columns outside lo_x..hi_x idle (a 64-wide tiling of the x-rows
-// alone leaves a mostly empty fifth wave on every row of a 256-wide box).
-// Blocks are renumbered so that each XCD -- the hardware deals blocks out
-// round-robin, block b to XCD b mod 8 -- walks a contiguous range of planes
-// and finds its neighbour planes in its own L2.
+// the padded grid.  The rows lo_y..hi_y are cut into slabs of `rows` rows;
+// each z-plane of a slab is walked as one run of whole padded x-rows (row
+// stride sy), kSpanThreads points per block, so a wave's 64 lanes always
+// touch 64 consecutive addresses and only the few padding columns outside
+// lo_x..hi_x idle (a 64-wide tiling of the x-rows alone leaves a mostly
+// empty fifth wave on every row of a 256-wide box).  Blocks are numbered
+// slab by slab, plane by plane within a slab, and renumbered so that each
+// XCD -- the hardware deals blocks out round-robin, block b to XCD b mod 8 --
+// walks a contiguous range of them: an XCD marches through the planes of
+// its own slabs, and the planes a z-stencil reaches back to (plus the
+// blocks in flight) stay within its L2, which whole planes of a large box
+// would not (the neighbour planes were fetched from memory again).
 // ------------------------------------------------------------------------
 
 constexpr int kSpanThreads = 256;
 
 struct Span {
   int lo[3], hi[3];
-  int per_plane;  // sy * (hi_y - lo_y + 1)
-  int bpp;        // blocks per plane
+  int rows;       // rows per slab (the last slab may be shorter)
+  int per_plane;  // points of one slab plane: sy * rows
+  int bpp;        // blocks per slab plane
+  int bps;        // blocks per slab: bpp * planes
   int nblk;
-  float inv_sy, inv_bpp;
+  float inv_sy, inv_bpp, inv_bps;
 };
+
+// Rows per slab: whole planes for small boxes (they fit an XCD's L2), else a
+// multiple of 8 slabs of at most 36 rows, so that every XCD gets the same
+// number of slabs.
+static int slab_rows(int nrows) {
+  if (nrows <= 160) return nrows;
+  const int nslab = 8 * ((nrows + 8 * 36 - 1) / (8 * 36));
+  return (nrows + nslab - 1) / nslab;
+}
 
 static Span make_span(const Geo& g, int ilo, int ihi, int jlo, int jhi, int klo, int khi) {
   Span s;
   s.lo[0] = ilo, s.hi[0] = ihi, s.lo[1] = jlo, s.hi[1] = jhi, s.lo[2] = klo, s.hi[2] = khi;
-  s.per_plane = g.sy * (jhi - jlo + 1);
+  const int nrows = jhi - jlo + 1;
+  s.rows = slab_rows(nrows);
+  const int nslab = (nrows + s.rows - 1) / s.rows;
+  s.per_plane = g.sy * s.rows;
   s.bpp = (s.per_plane + kSpanThreads - 1) / kSpanThreads;
-  s.nblk = s.bpp * (khi - klo + 1);
+  s.bps = s.bpp * (khi - klo + 1);
+  s.nblk = s.bps * nslab;
   s.inv_sy = 1.0f / (float)g.sy;
   s.inv_bpp = 1.0f / (float)s.bpp;
+  s.inv_bps = 1.0f / (float)s.bps;
   return s;
 }
 
@@ -87,14 +107,16 @@ __device__ __forceinline__ Pt span_point(const Geo& g, const Span& s) {
   const unsigned nb = (unsigned)s.nblk, b0 = blockIdx.x;
   const unsigned q = nb >> 3, r = nb & 7u, x = b0 & 7u;
   const int b = (int)(x * q + (x < r ? x : r) + (b0 >> 3));
-  const int plane = div_small(b, s.bpp, s.inv_bpp);
-  const int t = (b - plane * s.bpp) * kSpanThreads + (int)threadIdx.x;
+  const int slab = div_small(b, s.bps, s.inv_bps);
+  const int bs = b - slab * s.bps;
+  const int plane = div_small(bs, s.bpp, s.inv_bpp);
+  const int t = (bs - plane * s.bpp) * kSpanThreads + (int)threadIdx.x;
   const int row = div_small(t, g.sy, s.inv_sy);
   Pt o;
   o.i = t - row * g.sy - NG;
-  o.j = s.lo[1] + row;
+  o.j = s.lo[1] + slab * s.rows + row;
   o.k = s.lo[2] + plane;
-  o.valid = t < s.per_plane && o.i >= s.lo[0] && o.i <= s.hi[0];
+  o.valid = t < s.per_plane && o.j <= s.hi[1] && o.i >= s.lo[0] && o.i <= s.hi[0];
   o.p = pidx(g, o.i, o.j, o.k);
   return o;
 }
@@ -397,29 +419,58 @@ __device__ __forceinline__ int riemann_flux(const Physics& ph, const Face<T>& L,
   return hlld(L, R, bn, (T)ph.gamma, (T)ph.igm1, F);
 }
 
-// Flux of the A-face at point p: limited reconstruction (Eq. 12-14) of the
-// seven face variables from cells p - 2s .. p + s, HLLD, the sign of the
-// mass flux.  Returns the HLLD branch code (bit 0 HLL fallback, bit 1
-// degenerate; 0 for the other solvers).
-template <class T, int A, int RS>
-__device__ __forceinline__ int face_flux(const Physics& ph, int stride, unsigned bytes,
-                                         const Prim<T>& w, const T* __restrict__ bn,
-                                         const Flux<T>& f, const Muscl<T>& mu, int p) {
+// The stencil of the A-face at point p: the seven face variables of cells
+// p - 2s .. p + s (FO: first order, only p - s and p are loaded) and the
+// face-normal field.  Buffer loads: an offset outside the array (a stencil
+// of a face the sweep skips) reads 0 and never faults.
+template <class T>
+struct Stencil {
+  T v[7][4];
+  T bn;
+};
+
+template <class T, int A, bool FO>
+__device__ __forceinline__ Stencil<T> load_stencil(int stride, unsigned bytes, const Prim<T>& w,
+                                                   const T* __restrict__ bn, int p) {
   constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
   const unsigned s = (unsigned)stride * (unsigned)sizeof(T);
   const unsigned o = (unsigned)p * (unsigned)sizeof(T);
   const T* src[7] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2], w.w[4], w.w[5 + A1], w.w[5 + A2]};
-  T l[7], r[7];
+  Stencil<T> st;
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const auto q = rsrc(src[v], bytes);
-    muscl_lr(mu, bld(T(), q, o - 2 * s), bld(T(), q, o - s), bld(T(), q, o), bld(T(), q, o + s),
-             l[v], r[v]);
+    st.v[v][0] = FO ? T(0) : bld(T(), q, o - 2 * s);
+    st.v[v][1] = bld(T(), q, o - s);
+    st.v[v][2] = bld(T(), q, o);
+    st.v[v][3] = FO ? T(0) : bld(T(), q, o + s);
+  }
+  st.bn = bld(T(), rsrc(bn, bytes), o);
+  return st;
+}
+
+// Flux of the A-face at point p from its stencil: limited reconstruction
+// (Eq. 12-14; FO: first order), the Riemann solver, the sign of the mass
+// flux.  Returns the HLLD branch code (bit 0 HLL fallback, bit 1
+// degenerate; 0 for the other solvers).
+template <class T, int A, int RS, bool FO>
+__device__ __forceinline__ int face_flux(const Physics& ph, unsigned bytes, const Stencil<T>& st,
+                                         const Flux<T>& f, const Muscl<T>& mu, int p) {
+  const unsigned o = (unsigned)p * (unsigned)sizeof(T);
+  T l[7], r[7];
+#pragma unroll
+  for (int v = 0; v < 7; ++v) {
+    if constexpr (FO) {
+      l[v] = st.v[v][1];
+      r[v] = st.v[v][2];
+    } else {
+      muscl_lr(mu, st.v[v][0], st.v[v][1], st.v[v][2], st.v[v][3], l[v], r[v]);
+    }
   }
   const Face<T> L{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
   const Face<T> R{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
   T F[7];
-  const int code = riemann_flux<T, RS>(ph, L, R, bld(T(), rsrc(bn, bytes), o), F);
+  const int code = riemann_flux<T, RS>(ph, L, R, st.bn, F);
 #pragma unroll
   for (int m = 0; m < 7; ++m) bst(F[m], rsrc(f.f[A][m], bytes), o);
   const int sg = F[0] > T(0) ? 1 : (F[0] < T(0) ? -1 : 0);
@@ -428,7 +479,12 @@ __device__ __forceinline__ int face_flux(const Physics& ph, int stride, unsigned
   return code;
 }
 
-template <class T, int RS>
+// FP32: the loads of all three stencils are issued before the first
+// Riemann solve, so each wave keeps 84 loads in flight instead of 28 (the
+// sweep waits on memory latency more than on either roof; fewer waves fit,
+// 4-5 per SIMD instead of 7, and the launch is still about 10 % faster).
+// FP64 holds half as many values per register file and goes face by face.
+template <class T, int RS, bool FO>
 __global__ void __launch_bounds__(kSpanThreads) k_flux(Geo g, Physics ph, Span sp, Prim<T> w,
                                                        const T* __restrict__ bx,
                                                        const T* __restrict__ by,
@@ -438,9 +494,24 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux(Geo g, Physics ph, Span s
   int cx = 0, cy = 0, cz = 0;
   if (pt.valid) {
     const unsigned bytes = (unsigned)g.np * (unsigned)sizeof(T);
-    if (pt.i >= 0) cx = face_flux<T, 0, RS>(ph, 1, bytes, w, bx, f, mu, pt.p);
-    if (pt.j >= 0) cy = face_flux<T, 1, RS>(ph, g.sy, bytes, w, by, f, mu, pt.p);
-    if (pt.k >= 0) cz = face_flux<T, 2, RS>(ph, g.sz, bytes, w, bz, f, mu, pt.p);
+    if constexpr (sizeof(T) == 4) {
+      const Stencil<T> sx = load_stencil<T, 0, FO>(1, bytes, w, bx, pt.p);
+      const Stencil<T> sy = load_stencil<T, 1, FO>(g.sy, bytes, w, by, pt.p);
+      const Stencil<T> sz = load_stencil<T, 2, FO>(g.sz, bytes, w, bz, pt.p);
+      if (pt.i >= 0) cx = face_flux<T, 0, RS, FO>(ph, bytes, sx, f, mu, pt.p);
+      if (pt.j >= 0) cy = face_flux<T, 1, RS, FO>(ph, bytes, sy, f, mu, pt.p);
+      if (pt.k >= 0) cz = face_flux<T, 2, RS, FO>(ph, bytes, sz, f, mu, pt.p);
+    } else {
+      if (pt.i >= 0)
+        cx = face_flux<T, 0, RS, FO>(ph, bytes, load_stencil<T, 0, FO>(1, bytes, w, bx, pt.p), f,
+                                     mu, pt.p);
+      if (pt.j >= 0)
+        cy = face_flux<T, 1, RS, FO>(ph, bytes, load_stencil<T, 1, FO>(g.sy, bytes, w, by, pt.p),
+                                     f, mu, pt.p);
+      if (pt.k >= 0)
+        cz = face_flux<T, 2, RS, FO>(ph, bytes, load_stencil<T, 2, FO>(g.sz, bytes, w, bz, pt.p),
+                                     f, mu, pt.p);
+    }
   }
   wave_count((cx & 1) != 0, cnt.hll);
   wave_count((cy & 1) != 0, cnt.hll);
@@ -450,20 +521,28 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux(Geo g, Physics ph, Span s
   wave_count((cz & 2) != 0, cnt.deg);
 }
 
+template <class T, int RS>
+static void launch_flux_rs(const Geo& g, const Span& sp, const Physics& ph, Prim<T> w, Cons<T> s,
+                           Flux<T> f, Muscl<T> m, Counters c, hipStream_t st) {
+  const dim3 gr = span_grid(sp), bl(kSpanThreads);
+  if (m.first_order)
+    hipLaunchKernelGGL((k_flux<T, RS, true>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1], s.b[2],
+                       f, m, c);
+  else
+    hipLaunchKernelGGL((k_flux<T, RS, false>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
+                       s.b[2], f, m, c);
+}
+
 template <class T>
 void launch_flux(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f, Muscl<T> m,
                  Counters c, hipStream_t st) {
   const Span sp = make_span(g, -1, g.n[0], -1, g.n[1], -1, g.n[2]);
-  const dim3 gr = span_grid(sp), bl(kSpanThreads);
   if (ph.riemann == kRiemannHLL)
-    hipLaunchKernelGGL((k_flux<T, kRiemannHLL>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
-                       s.b[2], f, m, c);
+    launch_flux_rs<T, kRiemannHLL>(g, sp, ph, w, s, f, m, c, st);
   else if (ph.riemann == kRiemannHLLC)
-    hipLaunchKernelGGL((k_flux<T, kRiemannHLLC>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
-                       s.b[2], f, m, c);
+    launch_flux_rs<T, kRiemannHLLC>(g, sp, ph, w, s, f, m, c, st);
   else
-    hipLaunchKernelGGL((k_flux<T, kRiemannHLLD>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
-                       s.b[2], f, m, c);
+    launch_flux_rs<T, kRiemannHLLD>(g, sp, ph, w, s, f, m, c, st);
 }
 
 // ------------------------------------------------------------------------
