@@ -125,11 +125,12 @@ STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
 # FETCH_SIZE + WRITE_SIZE: a plain 1 GiB copy reads as 512 MiB of
 # FETCH_SIZE and 1 GiB of WRITE_SIZE), valid only for the kernel sources
 # with this hash.
-PROFILED_FLUX = {"sources_sha256_16": "e74632a9a8e14a90", "n": 256,
-                 "bytes_per_launch": 3.454e9}
-KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_kernels.hip",
-                  "paper_1502_02935_amd/csrc/mhd_physics.hpp",
-                  "paper_1502_02935_amd/csrc/mhd_kernels.hpp")
+PROFILED_FLUX = {"sources_sha256_16": "7056ce5c3cdc88d9", "n": 256,
+                 "bytes_per_launch": 2.335e9}
+# The sources that define the flux kernel's code (sweep, geometry, solver).
+KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_flux.hip",
+                  "paper_1502_02935_amd/csrc/mhd_span.hpp",
+                  "paper_1502_02935_amd/csrc/mhd_physics.hpp")
 
 
 def kernel_sources_hash():

@@ -8,129 +8,9 @@
 
 #include "mhd_kernels.hpp"
 #include "mhd_mlp.hpp"
+#include "mhd_span.hpp"
 
 namespace mhd {
-
-constexpr int BX = 64;  // block x extent = one wavefront
-constexpr int BY = 4;   // waves per block
-
-__device__ __forceinline__ int pidx(const Geo& g, int i, int j, int k) {
-  return (i + NG) + g.sy * (j + NG) + g.sz * (k + NG);
-}
-
-__device__ __forceinline__ int stride_of(const Geo& g, int a) {
-  return a == 0 ? 1 : (a == 1 ? g.sy : g.sz);
-}
-
-// Frame component of axis a that holds global conserved component m
-// (0 rho, 1..3 momentum, 4 energy).
-__device__ __forceinline__ int frame_comp(int a, int m) {
-  if (m == 0 || m == 4) return m;
-  const int d = m - 1;
-  return d == a ? 1 : (d == (a + 1) % 3 ? 2 : 3);
-}
-
-static dim3 grid_for(int nx, int ny, int nz) {
-  return dim3((unsigned)((nx + BX - 1) / BX), (unsigned)((ny + BY - 1) / BY), (unsigned)nz);
-}
-
-// ------------------------------------------------------------------------
-// Sweep geometry.  A sweep visits the points lo..hi (inclusive, per axis) of
-// the padded grid.  The rows lo_y..hi_y are cut into slabs of `rows` rows;
-// each z-plane of a slab is walked as one run of whole padded x-rows (row
-// stride sy), kSpanThreads points per block, so a wave's 64 lanes always
-// touch 64 consecutive addresses and only the few padding columns outside
-// lo_x..hi_x idle (a 64-wide tiling of the x-rows alone leaves a mostly
-// empty fifth wave on every row of a 256-wide box).  Blocks are numbered
-// slab by slab, plane by plane within a slab, and renumbered so that each
-// XCD -- the hardware deals blocks out round-robin, block b to XCD b mod 8 --
-// walks a contiguous range of them: an XCD marches through the planes of
-// its own slabs, and the planes a z-stencil reaches back to (plus the
-// blocks in flight) stay within its L2, which whole planes of a large box
-// would not (the neighbour planes were fetched from memory again).
-// ------------------------------------------------------------------------
-
-constexpr int kSpanThreads = 256;
-
-struct Span {
-  int lo[3], hi[3];
-  int rows;       // rows per slab (the last slab may be shorter)
-  int per_plane;  // points of one slab plane: sy * rows
-  int bpp;        // blocks per slab plane
-  int bps;        // blocks per slab: bpp * planes
-  int nblk;
-  float inv_sy, inv_bpp, inv_bps;
-};
-
-// Rows per slab: whole planes for small boxes (they fit an XCD's L2), else a
-// multiple of 8 slabs of at most 36 rows, so that every XCD gets the same
-// number of slabs.
-static int slab_rows(int nrows) {
-  if (nrows <= 160) return nrows;
-  const int nslab = 8 * ((nrows + 8 * 36 - 1) / (8 * 36));
-  return (nrows + nslab - 1) / nslab;
-}
-
-static Span make_span(const Geo& g, int ilo, int ihi, int jlo, int jhi, int klo, int khi) {
-  Span s;
-  s.lo[0] = ilo, s.hi[0] = ihi, s.lo[1] = jlo, s.hi[1] = jhi, s.lo[2] = klo, s.hi[2] = khi;
-  const int nrows = jhi - jlo + 1;
-  s.rows = slab_rows(nrows);
-  const int nslab = (nrows + s.rows - 1) / s.rows;
-  s.per_plane = g.sy * s.rows;
-  s.bpp = (s.per_plane + kSpanThreads - 1) / kSpanThreads;
-  s.bps = s.bpp * (khi - klo + 1);
-  s.nblk = s.bps * nslab;
-  s.inv_sy = 1.0f / (float)g.sy;
-  s.inv_bpp = 1.0f / (float)s.bpp;
-  s.inv_bps = 1.0f / (float)s.bps;
-  return s;
-}
-
-static dim3 span_grid(const Span& s) { return dim3((unsigned)s.nblk); }
-
-// q = floor(a / d) for 0 <= a < 2^31, d > 0: a float estimate (off by at
-// most one step below 2^23, a few above), corrected to exact in integers.
-__device__ __forceinline__ int div_small(int a, int d, float inv_d) {
-  int q = (int)(((float)a + 0.5f) * inv_d);
-  while (q * d > a) --q;
-  while ((q + 1) * d <= a) ++q;
-  return q;
-}
-
-struct Pt {
-  int i, j, k, p;
-  bool valid;
-};
-
-__device__ __forceinline__ Pt span_point(const Geo& g, const Span& s) {
-  const unsigned nb = (unsigned)s.nblk, b0 = blockIdx.x;
-  const unsigned q = nb >> 3, r = nb & 7u, x = b0 & 7u;
-  const int b = (int)(x * q + (x < r ? x : r) + (b0 >> 3));
-  const int slab = div_small(b, s.bps, s.inv_bps);
-  const int bs = b - slab * s.bps;
-  const int plane = div_small(bs, s.bpp, s.inv_bpp);
-  const int t = (bs - plane * s.bpp) * kSpanThreads + (int)threadIdx.x;
-  const int row = div_small(t, g.sy, s.inv_sy);
-  Pt o;
-  o.i = t - row * g.sy - NG;
-  o.j = s.lo[1] + slab * s.rows + row;
-  o.k = s.lo[2] + plane;
-  o.valid = t < s.per_plane && o.j <= s.hi[1] && o.i >= s.lo[0] && o.i <= s.hi[0];
-  o.p = pidx(g, o.i, o.j, o.k);
-  return o;
-}
-
-// Count lanes with `flag` set into the counter's slot of this block, with
-// one atomic per wave.  Must be reached by every lane of the wave.
-__device__ __forceinline__ void wave_count(bool flag, unsigned long long* ctr) {
-  const unsigned long long m = __ballot(flag);
-  if (m != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(1)) - 1)) {
-    const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    atomicAdd(ctr + (size_t)(b % kCounterSlots) * kCounterStride,
-              (unsigned long long)__popcll(m));
-  }
-}
 
 // ------------------------------------------------------------------------
 // Ghost fill.  Every ghost point takes the value of the interior point found
@@ -376,173 +256,6 @@ void launch_prim(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters
   const Span sp = prim_span(g);
   hipLaunchKernelGGL((k_prim<T, false>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s,
                      w, c, nullptr);
-}
-
-// ------------------------------------------------------------------------
-// Fluxes of all three face families in one sweep.  The point p of cell
-// (i, j, k) carries the faces at the lower x, y and z sides of that cell;
-// the sweep visits i, j, k in -1..n and computes the A-face wherever the
-// A-index is >= 0 (faces 0..n along A, rows -1..n across it: the boundary
-// edges' EMFs need one ghost row of transverse fluxes).  One launch instead
-// of three per-axis sweeps: the A-stencils of neighbouring points overlap,
-// so the primitives are fetched from HBM about once instead of three times.
-// Addressing: buffer loads and stores, a 32-bit byte offset per stencil
-// point shared by all arrays (no 64-bit address arithmetic per access), each
-// array's resource bounded by its size.
-// ------------------------------------------------------------------------
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, unsigned bytes) {
-  // word 3 0x00020000: 32-bit data format, the untyped-buffer setting of gfx9
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ float bld(float, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ double bld(double, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ void bst(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
-}
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
-}
-
-// Flux of the face states with Riemann solver RS (a template parameter: a
-// run-time switch would size every kernel's registers for the largest).
-template <class T, int RS>
-__device__ __forceinline__ int riemann_flux(const Physics& ph, const Face<T>& L, const Face<T>& R,
-                                            T bn, T F[7]) {
-  if constexpr (RS == kRiemannHLL) return hll(L, R, bn, (T)ph.gamma, (T)ph.igm1, F);
-  if constexpr (RS == kRiemannHLLC) return hllc(L, R, (T)ph.gamma, (T)ph.igm1, F);
-  return hlld(L, R, bn, (T)ph.gamma, (T)ph.igm1, F);
-}
-
-// The stencil of the A-face at point p: the seven face variables of cells
-// p - 2s .. p + s (FO: first order, only p - s and p are loaded) and the
-// face-normal field.  Buffer loads: an offset outside the array (a stencil
-// of a face the sweep skips) reads 0 and never faults.
-template <class T>
-struct Stencil {
-  T v[7][4];
-  T bn;
-};
-
-template <class T, int A, bool FO>
-__device__ __forceinline__ Stencil<T> load_stencil(int stride, unsigned bytes, const Prim<T>& w,
-                                                   const T* __restrict__ bn, int p) {
-  constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
-  const unsigned s = (unsigned)stride * (unsigned)sizeof(T);
-  const unsigned o = (unsigned)p * (unsigned)sizeof(T);
-  const T* src[7] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2], w.w[4], w.w[5 + A1], w.w[5 + A2]};
-  Stencil<T> st;
-#pragma unroll
-  for (int v = 0; v < 7; ++v) {
-    const auto q = rsrc(src[v], bytes);
-    st.v[v][0] = FO ? T(0) : bld(T(), q, o - 2 * s);
-    st.v[v][1] = bld(T(), q, o - s);
-    st.v[v][2] = bld(T(), q, o);
-    st.v[v][3] = FO ? T(0) : bld(T(), q, o + s);
-  }
-  st.bn = bld(T(), rsrc(bn, bytes), o);
-  return st;
-}
-
-// Flux of the A-face at point p from its stencil: limited reconstruction
-// (Eq. 12-14; FO: first order), the Riemann solver, the sign of the mass
-// flux.  Returns the HLLD branch code (bit 0 HLL fallback, bit 1
-// degenerate; 0 for the other solvers).
-template <class T, int A, int RS, bool FO>
-__device__ __forceinline__ int face_flux(const Physics& ph, unsigned bytes, const Stencil<T>& st,
-                                         const Flux<T>& f, const Muscl<T>& mu, int p) {
-  const unsigned o = (unsigned)p * (unsigned)sizeof(T);
-  T l[7], r[7];
-#pragma unroll
-  for (int v = 0; v < 7; ++v) {
-    if constexpr (FO) {
-      l[v] = st.v[v][1];
-      r[v] = st.v[v][2];
-    } else {
-      muscl_lr(mu, st.v[v][0], st.v[v][1], st.v[v][2], st.v[v][3], l[v], r[v]);
-    }
-  }
-  const Face<T> L{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
-  const Face<T> R{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
-  T F[7];
-  const int code = riemann_flux<T, RS>(ph, L, R, st.bn, F);
-#pragma unroll
-  for (int m = 0; m < 7; ++m) bst(F[m], rsrc(f.f[A][m], bytes), o);
-  const int sg = F[0] > T(0) ? 1 : (F[0] < T(0) ? -1 : 0);
-  __builtin_amdgcn_raw_buffer_store_b8((unsigned char)sg, rsrc(f.sg[A], bytes / sizeof(T)),
-                                       (unsigned)p, 0, 0);
-  return code;
-}
-
-// FP32: the loads of all three stencils are issued before the first
-// Riemann solve, so each wave keeps 84 loads in flight instead of 28 (the
-// sweep waits on memory latency more than on either roof; fewer waves fit,
-// 4-5 per SIMD instead of 7, and the launch is still about 10 % faster).
-// FP64 holds half as many values per register file and goes face by face.
-template <class T, int RS, bool FO>
-__global__ void __launch_bounds__(kSpanThreads) k_flux(Geo g, Physics ph, Span sp, Prim<T> w,
-                                                       const T* __restrict__ bx,
-                                                       const T* __restrict__ by,
-                                                       const T* __restrict__ bz, Flux<T> f,
-                                                       Muscl<T> mu, Counters cnt) {
-  const Pt pt = span_point(g, sp);
-  int cx = 0, cy = 0, cz = 0;
-  if (pt.valid) {
-    const unsigned bytes = (unsigned)g.np * (unsigned)sizeof(T);
-    if constexpr (sizeof(T) == 4) {
-      const Stencil<T> sx = load_stencil<T, 0, FO>(1, bytes, w, bx, pt.p);
-      const Stencil<T> sy = load_stencil<T, 1, FO>(g.sy, bytes, w, by, pt.p);
-      const Stencil<T> sz = load_stencil<T, 2, FO>(g.sz, bytes, w, bz, pt.p);
-      if (pt.i >= 0) cx = face_flux<T, 0, RS, FO>(ph, bytes, sx, f, mu, pt.p);
-      if (pt.j >= 0) cy = face_flux<T, 1, RS, FO>(ph, bytes, sy, f, mu, pt.p);
-      if (pt.k >= 0) cz = face_flux<T, 2, RS, FO>(ph, bytes, sz, f, mu, pt.p);
-    } else {
-      if (pt.i >= 0)
-        cx = face_flux<T, 0, RS, FO>(ph, bytes, load_stencil<T, 0, FO>(1, bytes, w, bx, pt.p), f,
-                                     mu, pt.p);
-      if (pt.j >= 0)
-        cy = face_flux<T, 1, RS, FO>(ph, bytes, load_stencil<T, 1, FO>(g.sy, bytes, w, by, pt.p),
-                                     f, mu, pt.p);
-      if (pt.k >= 0)
-        cz = face_flux<T, 2, RS, FO>(ph, bytes, load_stencil<T, 2, FO>(g.sz, bytes, w, bz, pt.p),
-                                     f, mu, pt.p);
-    }
-  }
-  wave_count((cx & 1) != 0, cnt.hll);
-  wave_count((cy & 1) != 0, cnt.hll);
-  wave_count((cz & 1) != 0, cnt.hll);
-  wave_count((cx & 2) != 0, cnt.deg);
-  wave_count((cy & 2) != 0, cnt.deg);
-  wave_count((cz & 2) != 0, cnt.deg);
-}
-
-template <class T, int RS>
-static void launch_flux_rs(const Geo& g, const Span& sp, const Physics& ph, Prim<T> w, Cons<T> s,
-                           Flux<T> f, Muscl<T> m, Counters c, hipStream_t st) {
-  const dim3 gr = span_grid(sp), bl(kSpanThreads);
-  if (m.first_order)
-    hipLaunchKernelGGL((k_flux<T, RS, true>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1], s.b[2],
-                       f, m, c);
-  else
-    hipLaunchKernelGGL((k_flux<T, RS, false>), gr, bl, 0, st, g, ph, sp, w, s.b[0], s.b[1],
-                       s.b[2], f, m, c);
-}
-
-template <class T>
-void launch_flux(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f, Muscl<T> m,
-                 Counters c, hipStream_t st) {
-  const Span sp = make_span(g, -1, g.n[0], -1, g.n[1], -1, g.n[2]);
-  if (ph.riemann == kRiemannHLL)
-    launch_flux_rs<T, kRiemannHLL>(g, sp, ph, w, s, f, m, c, st);
-  else if (ph.riemann == kRiemannHLLC)
-    launch_flux_rs<T, kRiemannHLLC>(g, sp, ph, w, s, f, m, c, st);
-  else
-    launch_flux_rs<T, kRiemannHLLD>(g, sp, ph, w, s, f, m, c, st);
 }
 
 // ------------------------------------------------------------------------
@@ -1293,8 +1006,6 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
                                hipStream_t);                                                     \
   template void launch_prim_cfl<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, double*,        \
                                    double*, Counters, hipStream_t);                              \
-  template void launch_flux<T>(const Geo&, const Physics&, Prim<T>, Cons<T>, Flux<T>, Muscl<T>,  \
-                               Counters, hipStream_t);                                           \
   template void launch_emf<T>(const Geo&, Prim<T>, Flux<T>, Edge<T>, hipStream_t);              \
   template void launch_flux_mlp<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>,        \
                                    Muscl<T>, Counters, MlpRef, hipStream_t);                     \

@@ -81,8 +81,10 @@ def main(argv=None):
     ap.add_argument("mode", choices=("throughput",))
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--counts", type=int, nargs="+", default=[0, 1, 4, 8],
+                    help="scalar counts to run")
     a = ap.parse_args(argv)
-    print(json.dumps(throughput(a.n, a.steps)), flush=True)
+    print(json.dumps(throughput(a.n, a.steps, counts=tuple(a.counts))), flush=True)
 
 
 if __name__ == "__main__":
