@@ -582,3 +582,81 @@ def mass_fractions(pb: Problem, ns: int, kind: str = "random", *, seed: int = 0,
             raise ValueError(kind)
         out[s] = rho * x
     return out
+
+
+# ---------------------------------------------------------------------------
+# N-body particles (positions and velocities [3][n], masses [n])
+# ---------------------------------------------------------------------------
+
+def gravity_box(n=(32, 32, 32), *, G=1.0, couple_gas=False, rho=1e-6, p=1e-9,
+                d=None) -> Problem:
+    """Periodic box for particle runs: a uniform gas at rest without field
+    (rho, p), self-gravity with constant G; couple_gas False sets src[1] = 1
+    (the gas neither sources nor feels the potential: particles only)."""
+    nx, ny, nz = n
+    if d is None:
+        d = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+    pb = uniform(n, rho=rho, v=(0.0, 0.0, 0.0), p=p, b=(0.0, 0.0, 0.0), d=d)
+    return replace(pb, name="gravity_box", source=SRC_SELF_GRAVITY,
+                   src=(G, 0.0 if couple_gas else 1.0, 0.0, 0.0))
+
+
+def particles_plane_wave(pb: Problem, *, amp=0.01, axis=0, mass_total=1.0, per_cell=1):
+    """Cold lattice (per_cell^3 particles per cell, at the cell corners and
+    their subdivisions) displaced along `axis` by amp * d sin(2 pi x / L),
+    at rest; equal masses summing to mass_total."""
+    nc = (pb.nx, pb.ny, pb.nz)
+    d = (pb.dx, pb.dy, pb.dz)
+    lo = (pb.x0, pb.y0, pb.z0)
+    axes = [lo[a] + np.arange(nc[a] * per_cell) * d[a] / per_cell for a in range(3)]
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    x = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    L = nc[axis] * d[axis]
+    x[axis] += amp * d[axis] * np.sin(2.0 * math.pi * (x[axis] - lo[axis]) / L)
+    n = x.shape[1]
+    return x, np.zeros_like(x), np.full(n, mass_total / n)
+
+
+def particles_plummer(pb: Problem, n: int, *, seed=0, scale=0.08, mass_total=1.0, G=1.0,
+                      centre=None, virial=True, rmax=None):
+    """Plummer sphere of n equal-mass particles (scale radius `scale`, total
+    mass mass_total) centred in the box, truncated at rmax (5 scale radii);
+    velocities from the Plummer distribution function by rejection sampling
+    (virial=True) or at rest."""
+    rng = np.random.default_rng(seed)
+    if centre is None:
+        centre = (pb.x0 + 0.5 * pb.nx * pb.dx, pb.y0 + 0.5 * pb.ny * pb.dy,
+                  pb.z0 + 0.5 * pb.nz * pb.dz)
+    r = np.empty(n)
+    k = 0
+    while k < n:
+        u = rng.uniform(0.0, 1.0, n)
+        rr = scale / np.sqrt(u ** (-2.0 / 3.0) - 1.0)
+        rr = rr[rr < (5.0 * scale if rmax is None else rmax)]
+        take = min(len(rr), n - k)
+        r[k:k + take] = rr[:take]
+        k += take
+    mu = rng.uniform(-1.0, 1.0, n)
+    ph = rng.uniform(0.0, 2.0 * math.pi, n)
+    s = np.sqrt(1.0 - mu * mu)
+    x = np.stack([r * s * np.cos(ph), r * s * np.sin(ph), r * mu])
+    for a in range(3):
+        x[a] += centre[a]
+    v = np.zeros_like(x)
+    if virial:
+        vesc = np.sqrt(2.0 * G * mass_total) * (r * r + scale * scale) ** -0.25
+        q = np.empty(n)
+        k = 0
+        while k < n:
+            qq = rng.uniform(0.0, 1.0, 4 * n)
+            yy = rng.uniform(0.0, 0.1, 4 * n)
+            ok = qq[yy < qq * qq * (1.0 - qq * qq) ** 3.5]
+            take = min(len(ok), n - k)
+            q[k:k + take] = ok[:take]
+            k += take
+        sp = q * vesc
+        mu = rng.uniform(-1.0, 1.0, n)
+        ph = rng.uniform(0.0, 2.0 * math.pi, n)
+        s = np.sqrt(1.0 - mu * mu)
+        v = np.stack([sp * s * np.cos(ph), sp * s * np.sin(ph), sp * mu])
+    return x, v, np.full(n, mass_total / n)

@@ -76,6 +76,9 @@ struct orc_grid {
   int64_t n_mlp, n_gated;
   /* self-gravity: potential and its central gradient at the cells (padded) */
   double *psi, *gpsi[3];
+  /* particles: positions, velocities ([3][npart]), masses; half-step
+     positions of the current step */
+  double *xp, *vp, *mp, *xh;
   /* passive scalars: rho X at t^n and t^{n+1/2}, X of the stage, fluxes */
   double *xs[ORC_MAX_SCALAR], *xss[ORC_MAX_SCALAR], *xw[ORC_MAX_SCALAR];
   double *xf[3][ORC_MAX_SCALAR];
@@ -592,6 +595,16 @@ orc_grid *orc_create(const orc_config *cfg) {
   for (m = 0; m < 8; ++m) g->w[m] = alloc_arr(g->np);
   g->shock = (unsigned char *)calloc((size_t)g->np, 1);
   if (cfg->nscalar < 0 || cfg->nscalar > ORC_MAX_SCALAR) { orc_destroy(g); return NULL; }
+  if (cfg->npart < 0 || (cfg->npart > 0 && cfg->source != ORC_SRC_SELF_GRAVITY)) {
+    orc_destroy(g);
+    return NULL;
+  }
+  if (cfg->npart > 0) {
+    g->xp = alloc_arr(3 * cfg->npart);
+    g->vp = alloc_arr(3 * cfg->npart);
+    g->mp = alloc_arr(cfg->npart);
+    g->xh = alloc_arr(3 * cfg->npart);
+  }
   for (m = 0; m < cfg->nscalar; ++m) {
     g->xs[m] = alloc_arr(g->np);
     g->xss[m] = alloc_arr(g->np);
@@ -633,6 +646,7 @@ void orc_destroy(orc_grid *g) {
   free(g->mlp);
   free(g->psi);
   for (a = 0; a < 3; ++a) free(g->gpsi[a]);
+  free(g->xp); free(g->vp); free(g->mp); free(g->xh);
   for (m = 0; m < ORC_MAX_SCALAR; ++m) {
     free(g->xs[m]); free(g->xss[m]); free(g->xw[m]);
     for (a = 0; a < 3; ++a) free(g->xf[a][m]);
@@ -1066,15 +1080,90 @@ void orc_poisson_periodic(int nx, int ny, int nz, double dx, double dy, double d
 
 /* Psi of the stage density (primitives w[0]) and its central gradient at
    every interior cell, with periodic wrap. */
-static void self_gravity(orc_grid *g) {
+/* ------------------------------------------------------------------------ */
+/* N-body particles: cloud-in-cell weights, deposit, interpolation.         */
+/* ------------------------------------------------------------------------ */
+
+static int gas_decoupled(const orc_grid *g) {
+  return g->c.source == ORC_SRC_SELF_GRAVITY && g->c.src[1] == 1.0;
+}
+
+/* Along axis a: the particle's cube [x - d/2, x + d/2] overlaps cells c0
+   and c0 + 1 (wrapped) with fractions w0 = 1 - f, w1 = f; in cell-centre
+   units s = (x - x0)/d - 1/2, c0 = floor(s), f = s - c0. */
+static void cic_axis(const orc_grid *g, int a, double x, int c[2], double w[2]) {
+  double x0 = a == 0 ? g->c.x0 : (a == 1 ? g->c.y0 : g->c.z0);
+  double s = (x - x0) / g->d[a] - 0.5;
+  double fl = floor(s);
+  int n = g->n[a];
+  long c0 = (long)fl;
+  c[0] = (int)(((c0 % n) + n) % n);
+  c[1] = (c[0] + 1) % n;
+  w[1] = s - fl;
+  w[0] = 1.0 - w[1];
+}
+
+void orc_particle_deposit(const orc_grid *g, const double *x, double *rho) {
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+  long N = (long)nx * ny * nz, n = g->c.npart, q;
+  double idv = 1.0 / (g->d[0] * g->d[1] * g->d[2]);
+  for (q = 0; q < N; ++q) rho[q] = 0.0;
+  for (q = 0; q < n; ++q) {
+    int ci[2], cj[2], ck[2], a, b, e;
+    double wi[2], wj[2], wk[2];
+    cic_axis(g, 0, x[q], ci, wi);
+    cic_axis(g, 1, x[n + q], cj, wj);
+    cic_axis(g, 2, x[2 * n + q], ck, wk);
+    for (e = 0; e < 2; ++e)
+      for (b = 0; b < 2; ++b)
+        for (a = 0; a < 2; ++a)
+          rho[((long)ck[e] * ny + cj[b]) * nx + ci[a]] += g->mp[q] * wi[a] * wj[b] * wk[e] * idv;
+  }
+}
+
+void orc_particle_interp(const orc_grid *g, const double *f, const double *x, long n,
+                         double *out) {
+  int nx = g->n[0], ny = g->n[1];
+  long q;
+  for (q = 0; q < n; ++q) {
+    int ci[2], cj[2], ck[2], a, b, e;
+    double wi[2], wj[2], wk[2], s = 0.0;
+    cic_axis(g, 0, x[q], ci, wi);
+    cic_axis(g, 1, x[n + q], cj, wj);
+    cic_axis(g, 2, x[2 * n + q], ck, wk);
+    for (e = 0; e < 2; ++e)
+      for (b = 0; b < 2; ++b)
+        for (a = 0; a < 2; ++a) s += wi[a] * wj[b] * wk[e] * f[((long)ck[e] * ny + cj[b]) * nx + ci[a]];
+    out[q] = s;
+  }
+}
+
+/* x mapped into [lo, lo + L) */
+static double wrap_coord(double x, double lo, double L) {
+  return x - L * floor((x - lo) / L);
+}
+
+static void wrap_positions(const orc_grid *g, double *x) {
+  long n = g->c.npart, q;
+  double lo[3] = {g->c.x0, g->c.y0, g->c.z0};
+  int a;
+  for (a = 0; a < 3; ++a)
+    for (q = 0; q < n; ++q) x[a * n + q] = wrap_coord(x[a * n + q], lo[a], g->n[a] * g->d[a]);
+}
+
+/* Potential of the gas density of the stage (unless decoupled) plus the
+   particles deposited at xpart (if any), and its central gradient. */
+static void self_gravity(orc_grid *g, const double *xpart) {
   int nx = g->n[0], ny = g->n[1], nz = g->n[2];
   long N = (long)nx * ny * nz;
   double *rho = (double *)calloc((size_t)N, sizeof(double));
   double *psi = (double *)calloc((size_t)N, sizeof(double));
   int i, j, k;
-  for (k = 0; k < nz; ++k)
-    for (j = 0; j < ny; ++j)
-      for (i = 0; i < nx; ++i) rho[((long)k * ny + j) * nx + i] = g->w[0][at(g, i, j, k)];
+  if (xpart) orc_particle_deposit(g, xpart, rho);
+  if (!gas_decoupled(g))
+    for (k = 0; k < nz; ++k)
+      for (j = 0; j < ny; ++j)
+        for (i = 0; i < nx; ++i) rho[((long)k * ny + j) * nx + i] += g->w[0][at(g, i, j, k)];
   orc_poisson_periodic(nx, ny, nz, g->d[0], g->d[1], g->d[2], g->c.src[0], rho, psi);
   for (k = 0; k < nz; ++k)
     for (j = 0; j < ny; ++j)
@@ -1154,7 +1243,9 @@ static void update(orc_grid *g, double dt, double *const u0[5], double *const b0
           double x = g->c.x0 + (i + 0.5) * g->d[0];
           double y = g->c.y0 + (j + 0.5) * g->d[1];
           double z = g->c.z0 + (k + 0.5) * g->d[2];
-          if (g->c.source == ORC_SRC_SELF_GRAVITY) {
+          if (gas_decoupled(g)) {
+            gp[0] = gp[1] = gp[2] = 0.0;
+          } else if (g->c.source == ORC_SRC_SELF_GRAVITY) {
             gp[0] = g->gpsi[0][p];
             gp[1] = g->gpsi[1][p];
             gp[2] = g->gpsi[2][p];
@@ -1218,7 +1309,39 @@ double orc_dt(orc_grid *g) {
         }
       }
   }
+  /* particles: no particle crosses more than cfl cells along an axis */
+  {
+    long n = g->c.npart, q;
+    int a;
+    for (a = 0; a < 3; ++a)
+      for (q = 0; q < n; ++q) {
+        double v = fabs(g->vp[a * n + q]);
+        if (v > 0.0 && g->d[a] / v < best) best = g->d[a] / v;
+      }
+  }
   return g->c.cfl * best;
+}
+
+/* Kick with the corrector's potential at the half-step positions, then
+   the second half drift. */
+static void particles_kick_drift(orc_grid *g, double dt) {
+  long n = g->c.npart, q;
+  int nx = g->n[0], ny = g->n[1], nz = g->n[2], a, i, j, k;
+  long N = (long)nx * ny * nz;
+  double *f = (double *)malloc((size_t)N * sizeof(double));
+  double *acc = (double *)malloc((size_t)n * sizeof(double));
+  for (a = 0; a < 3; ++a) {
+    for (k = 0; k < nz; ++k)
+      for (j = 0; j < ny; ++j)
+        for (i = 0; i < nx; ++i) f[((long)k * ny + j) * nx + i] = g->gpsi[a][at(g, i, j, k)];
+    orc_particle_interp(g, f, g->xh, n, acc);
+    for (q = 0; q < n; ++q) g->vp[a * n + q] -= dt * acc[q];
+  }
+  for (a = 0; a < 3; ++a)
+    for (q = 0; q < n; ++q) g->xp[a * n + q] = g->xh[a * n + q] + 0.5 * dt * g->vp[a * n + q];
+  wrap_positions(g, g->xp);
+  free(f);
+  free(acc);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1231,7 +1354,7 @@ double orc_step(orc_grid *g, double dt) {
   /* predictor: first-order fluxes of U^n, half step */
   primitives(g, g->u, g->b);
   scalar_prims(g, g->xs);
-  if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g);
+  if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g, g->c.npart ? g->xp : NULL);
   for (a = 0; a < 3; ++a) sweep(g, a, g->b, ORC_RECON_FIRST);
   for (a = 0; a < 3; ++a) corner_emf(g, a);
   update(g, 0.5 * dt, g->u, g->b, g->us, g->bs, g->xs, g->xss);
@@ -1240,13 +1363,19 @@ double orc_step(orc_grid *g, double dt) {
   /* corrector: MUSCL fluxes of U*, full step from U^n */
   primitives(g, g->us, g->bs);
   scalar_prims(g, g->xss);
-  if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g);
+  if (g->c.npart) {
+    long n = g->c.npart, q;
+    for (q = 0; q < 3 * n; ++q) g->xh[q] = g->xp[q] + 0.5 * dt * g->vp[q];
+    wrap_positions(g, g->xh);
+  }
+  if (g->c.source == ORC_SRC_SELF_GRAVITY) self_gravity(g, g->c.npart ? g->xh : NULL);
   if (g->mlp) shock_cells(g);
   for (a = 0; a < 3; ++a) sweep(g, a, g->bs, g->c.recon);
   for (a = 0; a < 3; ++a) corner_emf(g, a);
   update(g, dt, g->u, g->b, g->u, g->b, g->xs, g->xs);
   fill_ghosts(g, g->u, g->b);
   fill_ghosts_scalars(g, g->xs);
+  if (g->c.npart) particles_kick_drift(g, dt);
   g->t += dt;
   g->step += 1;
   return dt;
@@ -1255,6 +1384,24 @@ double orc_step(orc_grid *g, double dt) {
 /* ------------------------------------------------------------------------ */
 /* State in / out                                                           */
 /* ------------------------------------------------------------------------ */
+
+void orc_set_particles(orc_grid *g, const double *x, const double *v, const double *m) {
+  long n = g->c.npart, q;
+  for (q = 0; q < 3 * n; ++q) {
+    g->xp[q] = x[q];
+    g->vp[q] = v[q];
+  }
+  for (q = 0; q < n; ++q) g->mp[q] = m[q];
+  wrap_positions(g, g->xp);
+}
+
+void orc_get_particles(const orc_grid *g, double *x, double *v) {
+  long n = g->c.npart, q;
+  for (q = 0; q < 3 * n; ++q) {
+    x[q] = g->xp[q];
+    v[q] = g->vp[q];
+  }
+}
 
 void orc_set_scalars(orc_grid *g, const double *rho_x) {
   int nx = g->n[0], ny = g->n[1], nz = g->n[2], i, j, k, m;

@@ -71,7 +71,22 @@ typedef struct orc_config {
   int32_t riemann;        /* ORC_RIEMANN_* */
   int32_t nscalar;        /* passive scalars (mass fractions X_s, conserved as rho X_s),
                              0..ORC_MAX_SCALAR */
+  int64_t npart;          /* N-body particles (needs ORC_SRC_SELF_GRAVITY), >= 0 */
 } orc_config;
+
+/* N-body particles (section 2.1, particle-in-cell dynamics), sharing the
+   periodic potential with the gas.  Mass assignment: each particle is a
+   cube of one cell's size; a cell receives the particle's mass times the
+   fraction of the cube's volume inside it (cloud in cell), divided by the
+   cell volume.  The force on a particle is minus the cell-centred central
+   gradient of Psi interpolated with the same weights.  Integrator
+   ("flip-flop": leapfrog with one force evaluation per step), aligned with
+   the gas stages: x_h = x + dt/2 v; v += dt a(x_h); x = x_h + dt/2 v, where
+   a(x_h) comes from the corrector's potential (gas density of U* plus the
+   particles deposited at x_h); the predictor's potential uses the
+   particles at x.  Positions wrap periodically.  src[1] = 1 decouples the
+   gas: it neither sources the potential nor feels it (particles only).
+   The CFL step also obeys dt <= cfl min_p,a d_a / |v_a|. */
 
 /* Passive scalars (the code's multi-species advection): each X_s is carried
    by the mass flux, F_{rho X} = F_rho X_up with X_up the reconstructed face
@@ -100,6 +115,16 @@ int orc_set_state(orc_grid *g, const double *cell5, const double *bx,
 void orc_get_state(const orc_grid *g, double *cell5, double *bx, double *by,
                    double *bz);
 void orc_set_time(orc_grid *g, double t, int64_t step);
+/* Particles: x and v as [3][npart] (x, y, z rows), m as [npart]. */
+void orc_set_particles(orc_grid *g, const double *x, const double *v, const double *m);
+void orc_get_particles(const orc_grid *g, double *x, double *v);
+/* Cloud-in-cell deposit of the grid's particle masses at positions x
+   [3][npart] into rho [nz][ny][nx] (overwritten; periodic wrap). */
+void orc_particle_deposit(const orc_grid *g, const double *x, double *rho);
+/* Cloud-in-cell interpolation of a cell field f [nz][ny][nx] at n
+   positions x [3][n] (periodic wrap) into out [n]. */
+void orc_particle_interp(const orc_grid *g, const double *f, const double *x, long n,
+                         double *out);
 /* Passive scalars rho X_s, interior cells [nscalar][nz][ny][nx] (all zero
    after orc_create). */
 void orc_set_scalars(orc_grid *g, const double *rho_x);

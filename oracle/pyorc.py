@@ -36,6 +36,7 @@ class _Cfg(C.Structure):
         ("inflow", C.c_double * 8),
         ("riemann", C.c_int32),
         ("nscalar", C.c_int32),
+        ("npart", C.c_int64),
     ]
 
 
@@ -74,6 +75,7 @@ class OrcConfig:
     inflow: tuple = field(default_factory=lambda: (0.0,) * 8)
     riemann: int = RIEMANN_HLLD
     nscalar: int = 0
+    npart: int = 0
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -92,6 +94,7 @@ class OrcConfig:
             c.inflow[i] = float(self.inflow[i])
         c.riemann = int(self.riemann)
         c.nscalar = int(self.nscalar)
+        c.npart = int(self.npart)
         return c
 
 
@@ -154,6 +157,10 @@ def load_oracle():
     L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
     L.orc_set_time.argtypes = [C.c_void_p, C.c_double, C.c_int64]
     L.orc_set_scalars.argtypes = [C.c_void_p, dp]
+    L.orc_set_particles.argtypes = [C.c_void_p, dp, dp, dp]
+    L.orc_get_particles.argtypes = [C.c_void_p, dp, dp]
+    L.orc_particle_deposit.argtypes = [C.c_void_p, dp, dp]
+    L.orc_particle_interp.argtypes = [C.c_void_p, dp, dp, C.c_long, dp]
     L.orc_get_scalars.argtypes = [C.c_void_p, dp]
     L.orc_dt.restype = C.c_double
     L.orc_dt.argtypes = [C.c_void_p]
@@ -242,6 +249,35 @@ class Oracle:
         bx, by, bz = (np.empty(s) for s in fs)
         self.L.orc_get_state(self.h, _ptr(c5), _ptr(bx), _ptr(by), _ptr(bz))
         return c5, bx, by, bz
+
+    def set_particles(self, x, v, m):
+        """Particles: x, v [3][npart], m [npart] (positions wrap into the box)."""
+        n = self.cfg.npart
+        x, v, m = _f64(x), _f64(v), _f64(m)
+        assert x.shape == (3, n) and v.shape == (3, n) and m.shape == (n,)
+        self.L.orc_set_particles(self.h, _ptr(x), _ptr(v), _ptr(m))
+
+    def get_particles(self):
+        n = self.cfg.npart
+        x, v = np.empty((3, n)), np.empty((3, n))
+        self.L.orc_get_particles(self.h, _ptr(x), _ptr(v))
+        return x, v
+
+    def particle_deposit(self, x):
+        """Cloud-in-cell density [nz][ny][nx] of the particle masses at x [3][npart]."""
+        x = _f64(x)
+        assert x.shape == (3, self.cfg.npart)
+        rho = np.empty((self.cfg.nz, self.cfg.ny, self.cfg.nx))
+        self.L.orc_particle_deposit(self.h, _ptr(x), _ptr(rho))
+        return rho
+
+    def particle_interp(self, f, x):
+        """Cloud-in-cell interpolation of the cell field f at positions x [3][n]."""
+        f, x = _f64(f), _f64(x)
+        assert f.shape == (self.cfg.nz, self.cfg.ny, self.cfg.nx) and x.shape[0] == 3
+        out = np.empty(x.shape[1])
+        self.L.orc_particle_interp(self.h, _ptr(f), _ptr(x), x.shape[1], _ptr(out))
+        return out
 
     def set_scalars(self, rho_x):
         """Passive scalars rho X_s, shape (nscalar, nz, ny, nx)."""
