@@ -105,6 +105,8 @@ typedef struct mhd_config {
   int32_t riemann;        /* MHD_RIEMANN_*: HLLD (0, default), or the gas-dynamic HLL or HLLC */
   int32_t nscalar;        /* passive scalars, 0..MHD_MAX_SCALARS (see mhd_set_scalars) */
   int32_t reserved[2];    /* must be 0 */
+  int64_t npart;          /* N-body particles, >= 0; > 0 needs MHD_SRC_SELF_GRAVITY (see
+                             mhd_set_particles) */
 } mhd_config;
 
 /* Most passive scalars per context. */
@@ -140,7 +142,7 @@ const char *mhd_strerror(int code);
 
 /* Device workspace bytes needed for cfg (padded state, half-step state,
    primitives, fluxes, edge EMFs, reduction scratch, passive scalars at the
-   two time levels).  Returns MHD_E_ARG for
+   two time levels, particles).  Returns MHD_E_ARG for
    an invalid configuration. */
 int mhd_workspace_bytes(const mhd_config *cfg, size_t *out);
 
@@ -194,6 +196,30 @@ int mhd_get_state(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_b
 int mhd_set_scalars(mhd_ctx *ctx, const void *d_rho_x);
 int mhd_get_scalars(mhd_ctx *ctx, void *d_rho_x);
 
+/* N-body particles (section 2.1: particle-in-cell dynamics with the
+   "flip-flop" integrator and a mass-conserving second-order mass
+   assignment), moving in the periodic self-gravity potential together with
+   the gas.  Mass assignment is cloud in cell: a particle is a cube of one
+   cell's size, and each cell receives the particle's mass times the
+   fraction of the cube inside it, divided by the cell volume.  The force is
+   minus the cell-centred central gradient of Psi interpolated with the
+   same weights (so the total momentum of gas and particles is kept).  The
+   leapfrog of each step, with the gas stages: the predictor's potential
+   uses the particles at x; the corrector's uses them at x_h = x + dt/2 v;
+   then v += dt (-grad Psi)(x_h) and x = x_h + dt/2 v.  Positions wrap
+   into the box.  With src[1] = 1 the gas is decoupled: it neither sources
+   nor feels the potential (particles only).  The CFL step also obeys
+   dt <= cfl min over particles and axes of d_a / |v_a|.  The deposit adds
+   with atomics, so runs with particles are not bitwise reproducible.
+   d_x, d_v: device arrays [3][npart] (rows x, y, z), d_m: [npart], of the
+   context precision.  mhd_init sets every particle to rest at the box
+   corner with zero mass; mhd_set_particles replaces them (positions
+   wrapped), mhd_get_particles copies positions and velocities out (either
+   pointer may be NULL).  Both synchronise; MHD_E_ARG if the context has no
+   particles or a required pointer is NULL. */
+int mhd_set_particles(mhd_ctx *ctx, const void *d_x, const void *d_v, const void *d_m);
+int mhd_get_particles(mhd_ctx *ctx, void *d_x, void *d_v);
+
 /* Copies one internal padded array of the last corrector stage to d_out
    (element type of the context precision, [nz+5][ny+5][nx+5], x fastest,
    interior cell (i,j,k) at ((k+2)(ny+5) + j+2)(nx+5) + i+2):
@@ -221,7 +247,8 @@ enum {
   MHD_K_OTHER = 8,
   MHD_K_GRAVITY = 9,  /* self-gravity Poisson solve (FFTs, k-space division, gradient) */
   MHD_K_SCALARS = 10, /* passive-scalar face fluxes and update, and their ghost fill */
-  MHD_K_COUNT = 11
+  MHD_K_NBODY = 11,   /* particle kick and drift (their deposit is part of MHD_K_GRAVITY) */
+  MHD_K_COUNT = 12
 };
 
 typedef struct mhd_profile_t {

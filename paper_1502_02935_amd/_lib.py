@@ -38,6 +38,7 @@ class mhd_config(C.Structure):
         ("riemann", C.c_int32),
         ("nscalar", C.c_int32),
         ("reserved", C.c_int32 * 2),
+        ("npart", C.c_int64),
     ]
 
 
@@ -67,7 +68,7 @@ class mhd_profile_t(C.Structure):
 
 
 KERNEL_KINDS = ("ghosts", "prim", "flux", "flux_mlp", "shock", "emf", "update", "cfl", "other",
-                "gravity", "scalars")
+                "gravity", "scalars", "nbody")
 MAX_SCALARS = 8
 
 
@@ -106,6 +107,10 @@ def load() -> C.CDLL:
     L.mhd_diag.argtypes = [vp, C.POINTER(mhd_diag_t)]
     L.mhd_get_state.restype = C.c_int
     L.mhd_get_state.argtypes = [vp, vp, vp, vp, vp]
+    L.mhd_set_particles.restype = C.c_int
+    L.mhd_set_particles.argtypes = [vp, vp, vp, vp]
+    L.mhd_get_particles.restype = C.c_int
+    L.mhd_get_particles.argtypes = [vp, vp, vp]
     L.mhd_set_scalars.restype = C.c_int
     L.mhd_set_scalars.argtypes = [vp, vp]
     L.mhd_get_scalars.restype = C.c_int

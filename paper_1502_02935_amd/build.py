@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmhd.so")
-SOURCES = ["mhd_kernels.hip", "mhd_flux.hip", "mhd_mlp.hip", "mhd_gravity.hip", "mhd_abi.hip"]
+SOURCES = ["mhd_kernels.hip", "mhd_flux.hip", "mhd_mlp.hip", "mhd_gravity.hip", "mhd_nbody.hip",
+           "mhd_abi.hip"]
 HEADERS = ["mhd_kernels.hpp", "mhd_physics.hpp", "mhd_mlp.hpp", "mhd_span.hpp"]
 ARCH = os.environ.get("MHD_OFFLOAD_ARCH", "gfx950")
 

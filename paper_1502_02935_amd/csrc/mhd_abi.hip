@@ -39,6 +39,7 @@ struct Layout {
                     // [nz][ny][nx] array, twiddle and eigenvalue tables (0 bytes if off)
   size_t off_scal;  // passive scalars: nscalar padded T arrays at t^n, then nscalar at
                     // t^{n+1/2}
+  size_t off_part;  // particles: x [3][npart], v [3][npart], m [npart]
   size_t total;
 };
 
@@ -93,6 +94,8 @@ bool config_ok(const mhd_config* c) {
   if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0)) return false;
   if (c->riemann < MHD_RIEMANN_HLLD || c->riemann > MHD_RIEMANN_HLLC) return false;
   if (c->nscalar < 0 || c->nscalar > MHD_MAX_SCALARS) return false;
+  if (c->npart < 0 || c->npart > (1ll << 40)) return false;
+  if (c->npart > 0 && c->source != MHD_SRC_SELF_GRAVITY) return false;
   for (int q = 0; q < 2; ++q)
     if (c->reserved[q] != 0) return false;
   Geo g;
@@ -125,7 +128,8 @@ Layout layout_of(const mhd_config* c) {
     for (int a = 0; a < 3; ++a) grav += align_up((size_t)g.n[a] * 2 * es);  // twiddles, eigenvalues
   }
   L.off_scal = L.off_grav + grav;
-  L.total = L.off_scal + 2 * (size_t)c->nscalar * L.arr;
+  L.off_part = L.off_scal + 2 * (size_t)c->nscalar * L.arr;
+  L.total = L.off_part + align_up(7 * (size_t)c->npart * es);
   return L;
 }
 
@@ -253,6 +257,18 @@ struct mhd_ctx {
       s.x[m] = (T*)(ws + L.off_scal + ((size_t)set * cfg.nscalar + m) * L.arr);
     return s;
   }
+  template <class T>
+  Parts<T> parts() const {
+    Parts<T> p{};
+    p.n = cfg.npart;
+    if (p.n > 0) {
+      T* b = (T*)(ws + L.off_part);
+      p.x = b;
+      p.v = b + 3 * p.n;
+      p.m = b + 6 * p.n;
+    }
+    return p;
+  }
   bool gravity() const { return cfg.source == MHD_SRC_SELF_GRAVITY; }
   template <class T>
   Grav<T> grav() const {
@@ -339,16 +355,20 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   const Muscl<T> second = muscl_of<T>(c->cfg.recon, c->cfg.kappa);
   const int ns = c->nscalar();
   const Scal<T> Xn = c->scal<T>(0), Xh = c->scal<T>(1);
+  const Parts<T> Pp = c->parts<T>();
+  DtRef at_n = dt, at_half = dt;  // particle positions of the two potentials
+  at_n.factor = 0.0;
+  at_half.factor = 0.5;
   // predictor: first-order fluxes of U^n, half step into U*; a step that
   // takes its dt from the device gets it from the same primitives pass
   c->mark(MHD_K_PRIM);
   if (dt.ptr)
-    launch_prim_cfl<T>(g, c->ph, U, W, c->cfl_part(), c->misc() + M_DT, cnt, c->st);
+    launch_prim_cfl<T>(g, c->ph, U, W, c->cfl_part(), c->misc() + M_DT, cnt, Pp, c->st);
   else
     launch_prim<T>(g, c->ph, U, W, cnt, c->st);
   if (c->gravity()) {
     c->mark(MHD_K_GRAVITY);
-    launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), c->st);
+    launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_n, c->st);
   }
   c->mark(MHD_K_FLUX);
   launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
@@ -370,7 +390,8 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   launch_prim<T>(g, c->ph, Us, W, cnt, c->st);
   if (c->gravity()) {
     c->mark(MHD_K_GRAVITY);
-    launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), c->st);
+    launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_half,
+                           c->st);
   }
   if (c->mlp_params) {
     c->mark(MHD_K_SHOCK);
@@ -400,6 +421,10 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   }
   c->mark(MHD_K_GHOSTS);
   launch_ghosts<T>(g, c->ph, U, c->st);
+  if (Pp.n > 0) {
+    c->mark(MHD_K_NBODY);
+    launch_kick_drift<T>(g, Pp, c->grav<T>(), dt, c->st);
+  }
   c->mark(MHD_K_OTHER);
   launch_advance_time(c->misc() + M_T, (long long*)(c->misc() + M_STEP), dt, c->st);
   c->mark(-1);
@@ -409,7 +434,7 @@ template <class T>
 void enqueue_cfl(mhd_ctx* c) {
   c->mark(MHD_K_CFL);
   launch_cfl<T>(c->g, c->ph, c->cons<T>(0), c->cfl_part(), c->misc() + M_DT, c->counters(),
-                c->st);
+                c->parts<T>(), c->st);
   c->mark(-1);
 }
 
@@ -490,7 +515,7 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
   c->sticky = false;
   if (hipMemsetAsync(c->misc(), 0, 64 * sizeof(double), c->st) != hipSuccess ||
       hipMemsetAsync(c->counter_slots(), 0, L.off_cfl - L.off_cnt, c->st) != hipSuccess ||
-      (cfg->nscalar > 0 &&
+      (L.total > L.off_scal &&
        hipMemsetAsync(c->ws + L.off_scal, 0, L.total - L.off_scal, c->st) != hipSuccess)) {
     delete c;
     return MHD_E_HIP;
@@ -634,6 +659,36 @@ static int scalar_copy(mhd_ctx* c, void* d, bool in) {
   if (hip_status() != MHD_OK) return MHD_E_HIP;
   if (hipStreamSynchronize(c->st) != hipSuccess) return MHD_E_HIP;
   return MHD_OK;
+}
+
+int mhd_set_particles(mhd_ctx* c, const void* d_x, const void* d_v, const void* d_m) {
+  if (!c || !d_x || !d_v || !d_m || c->cfg.npart <= 0) return MHD_E_ARG;
+  const size_t es = c->cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
+  const size_t n = (size_t)c->cfg.npart;
+  char* b = c->ws + c->L.off_part;
+  if (hipMemcpyAsync(b, d_x, 3 * n * es, hipMemcpyDeviceToDevice, c->st) != hipSuccess ||
+      hipMemcpyAsync(b + 3 * n * es, d_v, 3 * n * es, hipMemcpyDeviceToDevice, c->st) !=
+          hipSuccess ||
+      hipMemcpyAsync(b + 6 * n * es, d_m, n * es, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+    return MHD_E_HIP;
+  if (c->cfg.precision == MHD_FP64)
+    launch_wrap_positions<double>(c->g, c->parts<double>(), c->st);
+  else
+    launch_wrap_positions<float>(c->g, c->parts<float>(), c->st);
+  if (hip_status() != MHD_OK) return MHD_E_HIP;
+  return hipStreamSynchronize(c->st) == hipSuccess ? MHD_OK : MHD_E_HIP;
+}
+
+int mhd_get_particles(mhd_ctx* c, void* d_x, void* d_v) {
+  if (!c || c->cfg.npart <= 0 || (!d_x && !d_v)) return MHD_E_ARG;
+  const size_t es = c->cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
+  const size_t n = (size_t)c->cfg.npart;
+  const char* b = c->ws + c->L.off_part;
+  if ((d_x && hipMemcpyAsync(d_x, b, 3 * n * es, hipMemcpyDeviceToDevice, c->st) != hipSuccess) ||
+      (d_v && hipMemcpyAsync(d_v, b + 3 * n * es, 3 * n * es, hipMemcpyDeviceToDevice, c->st) !=
+                  hipSuccess))
+    return MHD_E_HIP;
+  return hipStreamSynchronize(c->st) == hipSuccess ? MHD_OK : MHD_E_HIP;
 }
 
 int mhd_set_scalars(mhd_ctx* c, const void* d_rho_x) {

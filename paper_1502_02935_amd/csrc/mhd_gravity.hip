@@ -34,15 +34,18 @@ __device__ __forceinline__ long cidx(const Geo& g, int i, int j, int k) {
   return ((long)k * g.n[1] + j) * g.n[0] + i;
 }
 
+// The source density: the stage's gas density, or zero for a gas that is
+// decoupled from gravity (particles only; they are added by the deposit).
 template <class T>
-__global__ void __launch_bounds__(256) k_grav_load(Geo g, const T* __restrict__ rho, Cplx<T>* c) {
+__global__ void __launch_bounds__(256) k_grav_load(Geo g, const T* __restrict__ rho, Cplx<T>* c,
+                                                   int with_gas) {
   const long q = (long)blockIdx.x * 256 + threadIdx.x;
   const long N = (long)g.n[0] * g.n[1] * g.n[2];
   if (q >= N) return;
   const int i = (int)(q % g.n[0]);
   const int j = (int)((q / g.n[0]) % g.n[1]);
   const int k = (int)(q / ((long)g.n[0] * g.n[1]));
-  c[q] = Cplx<T>{rho[(i + NG) + g.sy * (j + NG) + g.sz * (k + NG)], T(0)};
+  c[q] = Cplx<T>{with_gas ? rho[(i + NG) + g.sy * (j + NG) + g.sz * (k + NG)] : T(0), T(0)};
 }
 
 // Batched FFT of all lines along axis A of c ([nz][ny][nx]); sign -1 forward,
@@ -166,13 +169,15 @@ static void fft_axis(const Geo& g, Cplx<T>* c, const Cplx<T>* tw, int sign, hipS
 
 template <class T>
 void launch_self_gravity(const Geo& g, const Physics& ph, const T* rho, GravFFT<T> f, Grav<T> gr,
-                         hipStream_t st) {
+                         Parts<T> pp, DtRef h, hipStream_t st) {
   const long N = (long)g.n[0] * g.n[1] * g.n[2];
   const unsigned blocks = (unsigned)((N + 255) / 256);
   Cplx<T>* c = (Cplx<T>*)f.c;
   const Cplx<T>* tw[3] = {(const Cplx<T>*)f.tw[0], (const Cplx<T>*)f.tw[1],
                           (const Cplx<T>*)f.tw[2]};
-  hipLaunchKernelGGL(k_grav_load<T>, dim3(blocks), dim3(256), 0, st, g, rho, c);
+  hipLaunchKernelGGL(k_grav_load<T>, dim3(blocks), dim3(256), 0, st, g, rho, c,
+                     ph.src[1] == 1.0 ? 0 : 1);
+  if (pp.n > 0) launch_deposit<T>(g, pp, h, f.c, st);
   fft_axis<T, 0>(g, c, tw[0], -1, st);
   fft_axis<T, 1>(g, c, tw[1], -1, st);
   fft_axis<T, 2>(g, c, tw[2], -1, st);
@@ -186,8 +191,9 @@ void launch_self_gravity(const Geo& g, const Physics& ph, const T* rho, GravFFT<
 }
 
 template void launch_self_gravity<double>(const Geo&, const Physics&, const double*,
-                                          GravFFT<double>, Grav<double>, hipStream_t);
+                                          GravFFT<double>, Grav<double>, Parts<double>, DtRef,
+                                          hipStream_t);
 template void launch_self_gravity<float>(const Geo&, const Physics&, const float*, GravFFT<float>,
-                                         Grav<float>, hipStream_t);
+                                         Grav<float>, Parts<float>, DtRef, hipStream_t);
 
 }  // namespace mhd

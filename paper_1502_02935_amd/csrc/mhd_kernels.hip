@@ -509,7 +509,9 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
       T S[5] = {T(0), T(0), T(0), T(0), T(0)};
       if (ph.source != 0) {
         double gp[3];
-        if (ph.source == 4) {
+        if (ph.source == 4 && ph.src[1] == 1.0) {  // gas decoupled from gravity
+          gp[0] = gp[1] = gp[2] = 0.0;
+        } else if (ph.source == 4) {
           gp[0] = gr.g[0][p];
           gp[1] = gr.g[1][p];
           gp[2] = gr.g[2][p];
@@ -638,29 +640,37 @@ static Span cfl_span(const Geo& g) {
 
 int cfl_blocks(const Geo& g) {
   const int nb = cfl_span(g).nblk, np = prim_span(g).nblk;
-  return (nb > np ? nb : np) + kCflReduce;
+  return (nb > np ? nb : np) + kPartCflBlocks + kCflReduce;
 }
 
 template <class T>
 void launch_prim_cfl(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, double* part,
-                     double* dt_out, Counters c, hipStream_t st) {
+                     double* dt_out, Counters c, Parts<T> pp, hipStream_t st) {
   const Span sp = prim_span(g);
+  int nb = sp.nblk;
+  if (pp.n > 0) {  // the particles' partials follow the cells'
+    launch_particle_cfl<T>(g, pp, part + nb, st);
+    nb += kPartCflBlocks;
+  }
   hipLaunchKernelGGL((k_prim<T, true>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s, w,
                      c, part);
-  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, sp.nblk,
-                     part + sp.nblk);
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + sp.nblk, ph.cfl, dt_out);
+  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, nb, part + nb);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + nb, ph.cfl, dt_out);
 }
 
 template <class T>
 void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
-                Counters c, hipStream_t st) {
+                Counters c, Parts<T> pp, hipStream_t st) {
   static_assert(kCflReduce == 64, "k_cfl_final folds one wave");
   const Span sp = cfl_span(g);
+  int nb = sp.nblk;
+  if (pp.n > 0) {
+    launch_particle_cfl<T>(g, pp, part + nb, st);
+    nb += kPartCflBlocks;
+  }
   hipLaunchKernelGGL(k_cfl<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s, part, c);
-  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, sp.nblk,
-                     part + sp.nblk);
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + sp.nblk, ph.cfl, dt_out);
+  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, nb, part + nb);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + nb, ph.cfl, dt_out);
 }
 
 __global__ void k_advance_time(double* t, long long* step, DtRef dtr) {
@@ -1005,7 +1015,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_prim<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,           \
                                hipStream_t);                                                     \
   template void launch_prim_cfl<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, double*,        \
-                                   double*, Counters, hipStream_t);                              \
+                                   double*, Counters, Parts<T>, hipStream_t);                    \
   template void launch_emf<T>(const Geo&, Prim<T>, Flux<T>, Edge<T>, hipStream_t);              \
   template void launch_flux_mlp<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>,        \
                                    Muscl<T>, Counters, MlpRef, hipStream_t);                     \
@@ -1013,7 +1023,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Flux<T>, \
                                  Edge<T>, Grav<T>, DtRef, Counters, hipStream_t);                \
   template void launch_cfl<T>(const Geo&, const Physics&, Cons<T>, double*, double*, Counters,   \
-                              hipStream_t);                                                      \
+                              Parts<T>, hipStream_t);                                            \
   template void launch_diag<T>(const Geo&, const Physics&, Cons<T>, double*, double*,           \
                                hipStream_t);                                                     \
   template void launch_scatter<T>(const Geo&, const T*, const T*, const T*, const T*, Cons<T>,  \

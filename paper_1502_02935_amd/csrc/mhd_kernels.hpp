@@ -118,6 +118,17 @@ struct Scal {
   T* x[kMaxScalars];
 };
 
+// N-body particles (context precision, structure of arrays): positions and
+// velocities [3][n] (x, y, z rows), masses [n]; n = 0: none.
+template <class T>
+struct Parts {
+  T* x;
+  T* v;
+  T* m;
+  long long n;
+};
+constexpr int kPartCflBlocks = 1024;  // per-block CFL partials of the particles
+
 // Time-step source: a value, or (if ptr != nullptr) a device scalar.
 struct DtRef {
   double value;
@@ -134,7 +145,7 @@ void launch_prim(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters
 // reduced to dt_out (= cfl x min): the start of a step with its own dt.
 template <class T>
 void launch_prim_cfl(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, double* part,
-                     double* dt_out, Counters c, hipStream_t st);
+                     double* dt_out, Counters c, Parts<T> pp, hipStream_t st);
 // Fluxes of all three face families (normal B from the face arrays of s).
 template <class T>
 void launch_flux(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f, Muscl<T> m,
@@ -164,13 +175,30 @@ void launch_scalar_copy(const Geo& g, Scal<T> x, int ns, T* interior, bool in, h
 // into gr (mhd_gravity.hip).
 template <class T>
 void launch_self_gravity(const Geo& g, const Physics& ph, const T* rho, GravFFT<T> f, Grav<T> gr,
-                         hipStream_t st);
+                         Parts<T> pp, DtRef h, hipStream_t st);
 // CFL: per-block minima into part (size cfl_blocks(g), which also fits the
-// partials of launch_prim_cfl), then dt_out = cfl min.
+// partials of launch_prim_cfl and of the particles), then dt_out = cfl min
+// over cells and (if pp.n) particles.
 int cfl_blocks(const Geo& g);
 template <class T>
 void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
-                Counters c, hipStream_t st);
+                Counters c, Parts<T> pp, hipStream_t st);
+// Particles (mhd_nbody.hip).  Per-block minima over the particles of
+// d_a / |v_a| into part[0 .. kPartCflBlocks).
+template <class T>
+void launch_particle_cfl(const Geo& g, Parts<T> pp, double* part, hipStream_t st);
+// Adds the cloud-in-cell density of the particles at x + h v (h = dt x
+// dt.factor, positions wrapped) to the real parts of the complex array c
+// ([nz][ny][nx] pairs).
+template <class T>
+void launch_deposit(const Geo& g, Parts<T> pp, DtRef h, T* c, hipStream_t st);
+// Leapfrog with the potential gradient of gr (cell-centred, the corrector's):
+// x_h = x + dt/2 v, v -= dt grad Psi(x_h), x = x_h + dt/2 v, positions wrapped.
+template <class T>
+void launch_kick_drift(const Geo& g, Parts<T> pp, Grav<T> gr, DtRef dt, hipStream_t st);
+// Positions wrapped into the box (after the caller sets them).
+template <class T>
+void launch_wrap_positions(const Geo& g, Parts<T> pp, hipStream_t st);
 void launch_advance_time(double* t, long long* step, DtRef dt, hipStream_t st);
 
 // Diagnostics: writes 14 doubles to out: mass, M(3), E, bsum(3), divb_max,

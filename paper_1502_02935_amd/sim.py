@@ -36,6 +36,7 @@ class MHDConfig:
     inflow: tuple = field(default_factory=lambda: (0.0,) * 8)
     riemann: int = L.RIEMANN_HLLD
     nscalar: int = 0
+    npart: int = 0
 
     def to_c(self) -> L.mhd_config:
         c = L.mhd_config()
@@ -54,6 +55,7 @@ class MHDConfig:
             c.inflow[i] = float(self.inflow[i])
         c.riemann = int(self.riemann)
         c.nscalar = int(self.nscalar)
+        c.npart = int(self.npart)
         return c
 
     @property
@@ -69,13 +71,13 @@ class MHDConfig:
 
 
 def config_from_problem(pb, precision=L.MHD_FP64, recon=L.RECON_PAPER, kappa=1.0 / 3.0,
-                        cfl=None, riemann=L.RIEMANN_HLLD, nscalar=0) -> MHDConfig:
+                        cfl=None, riemann=L.RIEMANN_HLLD, nscalar=0, npart=0) -> MHDConfig:
     return MHDConfig(nx=pb.nx, ny=pb.ny, nz=pb.nz, dx=pb.dx, dy=pb.dy, dz=pb.dz, x0=pb.x0,
                      y0=pb.y0, z0=pb.z0, precision=precision, gamma=pb.gamma,
                      cfl=pb.cfl if cfl is None else cfl, bc=tuple(pb.bc), recon=recon,
                      kappa=kappa, source=pb.source, src=tuple(pb.src), rho_floor=pb.rho_floor,
                      p_floor=pb.p_floor, inflow=tuple(pb.inflow), riemann=riemann,
-                     nscalar=nscalar)
+                     nscalar=nscalar, npart=npart)
 
 
 def workspace_bytes(cfg: MHDConfig) -> int:
@@ -217,6 +219,28 @@ class Sim:
         L.check(self.L.mhd_mlp_samples(self.ctx, _ptr(acc), dt_coarse, n, _ptr(faces), _ptr(x),
                                        _ptr(t), _ptr(m)), "mhd_mlp_samples")
         return x, t, m
+
+    # ---- N-body particles -----------------------------------------------------
+
+    def set_particles(self, x, v, m):
+        """Replace the particles: positions and velocities [3][npart], masses
+        [npart] (positions wrap into the box)."""
+        cfg = self.cfg
+        n = cfg.npart
+        xs = _dev(x, cfg.dtype, self.device)
+        vs = _dev(v, cfg.dtype, self.device)
+        ms = _dev(m, cfg.dtype, self.device)
+        assert tuple(xs.shape) == (3, n) and tuple(vs.shape) == (3, n) and tuple(ms.shape) == (n,)
+        L.check(self.L.mhd_set_particles(self.ctx, _ptr(xs), _ptr(vs), _ptr(ms)),
+                "mhd_set_particles")
+
+    def get_particles(self):
+        """(positions, velocities), each [3][npart] on the device."""
+        cfg = self.cfg
+        x = torch.empty((3, cfg.npart), dtype=cfg.dtype, device=self.device)
+        v = torch.empty_like(x)
+        L.check(self.L.mhd_get_particles(self.ctx, _ptr(x), _ptr(v)), "mhd_get_particles")
+        return x, v
 
     # ---- passive scalars ------------------------------------------------------
 

@@ -40,6 +40,7 @@ def test_workspace_bytes_valid():
     dict(cfl=1.5), dict(precision=2), dict(recon=5), dict(kappa=1.0), dict(source=9),
     dict(rho_floor=-1.0), dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(7, 7, 0, 0, 0, 0)),
     dict(nx=1 << 21), dict(nx=2048, ny=2048, nz=1024), dict(nscalar=-1), dict(nscalar=9),
+    dict(npart=-1), dict(npart=10),
 ])
 def test_workspace_bytes_rejects(bad):
     c = _cfg(**bad).to_c()
@@ -58,6 +59,8 @@ def test_null_arguments_rejected():
     assert lib.mhd_destroy(None) == L.MHD_E_ARG
     assert lib.mhd_get_state(None, None, None, None, None) == L.MHD_E_ARG
     assert lib.mhd_set_scalars(None, None) == L.MHD_E_ARG
+    assert lib.mhd_set_particles(None, None, None, None) == L.MHD_E_ARG
+    assert lib.mhd_get_particles(None, None, None) == L.MHD_E_ARG
     assert lib.mhd_get_scalars(None, None) == L.MHD_E_ARG
     ctx = C.c_void_p()
     assert lib.mhd_init(C.byref(c), None, 0, None, None, None, None, None,
@@ -98,3 +101,14 @@ def test_scalars_add_two_padded_arrays_each():
     arr = (arr + 255) // 256 * 256
     for ns in (1, 3, 8):
         assert workspace_bytes(_cfg(nscalar=ns)) == base + 2 * ns * arr
+
+
+def test_particles_need_self_gravity_and_add_seven_values_each():
+    base = dict(nx=16, ny=8, nz=4, dx=0.1, dy=0.1, dz=0.1, source=L.SRC_SELF_GRAVITY,
+                src=(1.0, 0.0, 0.0, 0.0))
+    w0 = workspace_bytes(MHDConfig(**base))
+    for n, es, prec in ((1000, 8, 0), (1000, 4, 1), (12345, 4, 1)):
+        w = workspace_bytes(MHDConfig(npart=n, precision=prec, **base))
+        w0p = workspace_bytes(MHDConfig(precision=prec, **base))
+        assert w - w0p == (7 * n * es + 255) // 256 * 256
+    assert w0 > 0
