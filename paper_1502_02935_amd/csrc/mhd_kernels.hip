@@ -424,8 +424,7 @@ __device__ __forceinline__ T upwind(int8_t sgn, T from_low, T from_high) {
 }
 
 template <class T, int C>
-__device__ __forceinline__ void corner(const Geo& g, const Prim<T>& w, const Flux<T>& f,
-                                       const Edge<T>& e, int p) {
+__device__ __forceinline__ T corner(const Geo& g, const Prim<T>& w, const Flux<T>& f, int p) {
   constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
   const int sa = stride_of(g, A), sb = stride_of(g, B);
   const T* __restrict__ fa = f.f[A][5];  // B_b flux at a-faces (t1 of the a-frame)
@@ -440,18 +439,24 @@ __device__ __forceinline__ void corner(const Geo& g, const Prim<T>& w, const Flu
   const T db3 = upwind(ga[p - sb], Y1 - c00, Y0 - c10);
   const T da1 = upwind(gb[p], c10 - X1, c11 - X0);
   const T da3 = upwind(gb[p - sa], X1 - c00, X0 - c01);
-  e.e[C][p] = T(0.25) * (X0 + X1 + Y0 + Y1) + T(0.25) * (db3 - db1) + T(0.25) * (da3 - da1);
+  return T(0.25) * (X0 + X1 + Y0 + Y1) + T(0.25) * (db3 - db1) + T(0.25) * (da3 - da1);
 }
 
+// All three edges' loads are issued before any store (each edge of a point
+// at the span's upper end is still inside the padded arrays; it is just not
+// stored), so a wave makes one memory round trip instead of three.
 template <class T>
 __global__ void __launch_bounds__(kSpanThreads) k_emf(Geo g, Span sp, Prim<T> w, Flux<T> f,
                                                       Edge<T> e) {
   const Pt pt = span_point(g, sp);
   if (!pt.valid) return;
   const int p = pt.p;
-  if (pt.i < g.n[0]) corner<T, 0>(g, w, f, e, p);
-  if (pt.j < g.n[1]) corner<T, 1>(g, w, f, e, p);
-  if (pt.k < g.n[2]) corner<T, 2>(g, w, f, e, p);
+  const T ex = corner<T, 0>(g, w, f, p);
+  const T ey = corner<T, 1>(g, w, f, p);
+  const T ez = corner<T, 2>(g, w, f, p);
+  if (pt.i < g.n[0]) e.e[0][p] = ex;
+  if (pt.j < g.n[1]) e.e[1][p] = ey;
+  if (pt.k < g.n[2]) e.e[2][p] = ez;
 }
 
 template <class T>
@@ -484,66 +489,74 @@ __device__ __forceinline__ void grad_phi(const Physics& ph, double x, double y, 
   }
 }
 
+// Every load of a point is issued whether or not the point's cell or faces
+// are updated (the padded arrays hold every index the span reaches, and
+// values of points that are not updated are discarded): guarding the loads
+// per face family would split a wave's memory traffic into four dependent
+// round trips.
 template <class T>
 __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span sp, Cons<T> s0,
                                                          Cons<T> s1, Prim<T> w, Flux<T> f,
                                                          Edge<T> e, Grav<T> gr, DtRef dtr) {
   const Pt pt = span_point(g, sp);
+  if (!pt.valid) return;
   const int i = pt.i, j = pt.j, k = pt.k;
-  if (pt.valid) {
-    const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
-    const int p = pt.p;
-    const int cc[3] = {i, j, k};
-    const int st[3] = {1, g.sy, g.sz};
+  const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
+  const int p = pt.p;
+  const int cc[3] = {i, j, k};
+  const int st[3] = {1, g.sy, g.sz};
+  T bnew[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int b = (a + 1) % 3, c = (a + 2) % 3;
-      if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) {
-        const T rb = (T)(dt / g.d[b]), rc = (T)(dt / g.d[c]);
-        const T* Ec = e.e[c];
-        const T* Eb = e.e[b];
-        s1.b[a][p] = s0.b[a][p] - rb * (Ec[p + st[b]] - Ec[p]) + rc * (Eb[p + st[c]] - Eb[p]);
-      }
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const T rb = (T)(dt / g.d[b]), rc = (T)(dt / g.d[c]);
+    const T* Ec = e.e[c];
+    const T* Eb = e.e[b];
+    bnew[a] = s0.b[a][p] - rb * (Ec[p + st[b]] - Ec[p]) + rc * (Eb[p + st[c]] - Eb[p]);
+  }
+  T S[5] = {T(0), T(0), T(0), T(0), T(0)};
+  if (ph.source != 0) {
+    double gp[3];
+    if (ph.source == 4 && ph.src[1] == 1.0) {  // gas decoupled from gravity
+      gp[0] = gp[1] = gp[2] = 0.0;
+    } else if (ph.source == 4) {
+      gp[0] = gr.g[0][p];
+      gp[1] = gr.g[1][p];
+      gp[2] = gr.g[2][p];
+    } else {
+      grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
+               g.x0[2] + (k + 0.5) * g.d[2], gp);
     }
-    if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
-      T S[5] = {T(0), T(0), T(0), T(0), T(0)};
-      if (ph.source != 0) {
-        double gp[3];
-        if (ph.source == 4 && ph.src[1] == 1.0) {  // gas decoupled from gravity
-          gp[0] = gp[1] = gp[2] = 0.0;
-        } else if (ph.source == 4) {
-          gp[0] = gr.g[0][p];
-          gp[1] = gr.g[1][p];
-          gp[2] = gr.g[2][p];
-        } else {
-          grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
-                   g.x0[2] + (k + 0.5) * g.d[2], gp);
-        }
-        const T rho = w.w[0][p];
-        const T gx = (T)gp[0], gy = (T)gp[1], gz = (T)gp[2];
-        S[1] = -rho * gx;
-        S[2] = -rho * gy;
-        S[3] = -rho * gz;
-        S[4] = -rho * (w.w[1][p] * gx + w.w[2][p] * gy + w.w[3][p] * gz);
-      }
-      const T rx = (T)(dt / g.d[0]), ry = (T)(dt / g.d[1]), rz = (T)(dt / g.d[2]);
-      const T dtT = (T)dt;
-      T u[5];
+    const T rho = w.w[0][p];
+    const T gx = (T)gp[0], gy = (T)gp[1], gz = (T)gp[2];
+    S[1] = -rho * gx;
+    S[2] = -rho * gy;
+    S[3] = -rho * gz;
+    S[4] = -rho * (w.w[1][p] * gx + w.w[2][p] * gy + w.w[3][p] * gz);
+  }
+  const T rx = (T)(dt / g.d[0]), ry = (T)(dt / g.d[1]), rz = (T)(dt / g.d[2]);
+  const T dtT = (T)dt;
+  T u[5];
 #pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        const T* fx = f.f[0][frame_comp(0, m)];
-        const T* fy = f.f[1][frame_comp(1, m)];
-        const T* fz = f.f[2][frame_comp(2, m)];
-        T v = s0.u[m][p];
-        v -= rx * (fx[p + 1] - fx[p]);
-        v -= ry * (fy[p + g.sy] - fy[p]);
-        v -= rz * (fz[p + g.sz] - fz[p]);
-        v += dtT * S[m];
-        u[m] = v;
-      }
+  for (int m = 0; m < 5; ++m) {
+    const T* fx = f.f[0][frame_comp(0, m)];
+    const T* fy = f.f[1][frame_comp(1, m)];
+    const T* fz = f.f[2][frame_comp(2, m)];
+    T v = s0.u[m][p];
+    v -= rx * (fx[p + 1] - fx[p]);
+    v -= ry * (fy[p + g.sy] - fy[p]);
+    v -= rz * (fz[p + g.sz] - fz[p]);
+    v += dtT * S[m];
+    u[m] = v;
+  }
 #pragma unroll
-      for (int m = 0; m < 5; ++m) s1.u[m][p] = u[m];
-    }
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) s1.b[a][p] = bnew[a];
+  }
+  if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s1.u[m][p] = u[m];
   }
 }
 
