@@ -9,8 +9,9 @@
 // in padded arrays that the update reads for S = (0, -rho grad Psi,
 // -rho v.grad Psi, 0).  Extents are powers of two up to 1024.
 //
-// FFT lines: a block takes a tile of lines of one axis into LDS (bit-reversed
-// order), runs the log2(n) butterfly stages there and writes the tile back.
+// FFT lines: a block takes a tile of lines of one axis into LDS, splits
+// each line's n = R1 R2 points into R2 DFTs of R1 points and R1 DFTs of R2
+// points done in registers (two LDS passes), and writes the result out.
 // x-lines are contiguous; y- and z-lines are tiled over consecutive x, so
 // each element row of a tile is one contiguous run in HBM.
 #include <math.h>
@@ -26,8 +27,6 @@ template <class T>
 struct Cplx {
   T re, im;
 };
-
-__device__ __forceinline__ int ilog2(int n) { return 31 - __clz(n); }
 
 // Interior index of cell (i, j, k) in [nz][ny][nx].
 __device__ __forceinline__ long cidx(const Geo& g, int i, int j, int k) {
@@ -48,20 +47,70 @@ __global__ void __launch_bounds__(256) k_grav_load(Geo g, const T* __restrict__ 
   c[q] = Cplx<T>{with_gas ? rho[(i + NG) + g.sy * (j + NG) + g.sz * (k + NG)] : T(0), T(0)};
 }
 
-// Batched FFT of all lines along axis A of c ([nz][ny][nx]); sign -1 forward,
-// +1 inverse (unnormalised).  tw: n/2 values exp(-2 pi i q / n).  tl: lines
-// per block (tl * n <= kFftTileElems; for A = 1, 2 tl divides nx).
-template <class T, int A>
+// In-register DFT of R points (R a power of two): the radix-2
+// decimation-in-time butterflies, fully unrolled.  tw: n/2 values
+// exp(-2 pi i q / n) (n a multiple of R); W_R^j = tw[j n / R]; sign -1
+// forward, +1 inverse (conjugate twiddles).
+template <int R>
+__device__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) r = (r << 1) | ((i & b) ? 1 : 0);
+  return r;
+}
+
+template <class T, int R>
+__device__ __forceinline__ void dft_reg(Cplx<T> a[R], const Cplx<T>* __restrict__ tw, int n,
+                                        int sign) {
+  Cplx<T> b[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) b[bitrev<R>(i)] = a[i];
+#pragma unroll
+  for (int m = 1; m < R; m <<= 1) {
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      Cplx<T> w{T(1), T(0)};
+      if (j > 0) {
+        w = tw[j * (n / (2 * m))];
+        if (sign > 0) w.im = -w.im;
+      }
+#pragma unroll
+      for (int k = j; k < R; k += 2 * m) {
+        const Cplx<T> u = b[k], v = b[k + m];
+        T vr = v.re, vi = v.im;
+        if (j > 0) {
+          vr = v.re * w.re - v.im * w.im;
+          vi = v.re * w.im + v.im * w.re;
+        }
+        b[k] = Cplx<T>{u.re + vr, u.im + vi};
+        b[k + m] = Cplx<T>{u.re - vr, u.im - vi};
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = b[i];
+}
+
+// Batched FFT of all lines along axis A of c ([nz][ny][nx]) of n = R1 R2
+// points: the "four-step" split within a block.  A tile of tl lines goes
+// to LDS (line stride n + 1 complex values, so lines do not share banks);
+// step 1: for each n2 < R2, an R1-point DFT over x[R2 n1 + n2], times
+// W_n^(n2 k1), back in place; step 2: for each k1 < R1, an R2-point DFT
+// over the R2 contiguous values, written to element k1 + R1 k2 of the line
+// in HBM.  Two LDS passes and two barriers instead of log2(n) radix-2
+// stages.  Threads take consecutive elements of a line (x-lines) or
+// consecutive lines (y-, z-lines, tiled over consecutive x), so every HBM
+// access of a wave is contiguous.  sign -1 forward, +1 inverse
+// (unnormalised).
+template <class T, int A, int R1, int R2>
 __global__ void __launch_bounds__(kFftThreads) k_fft(Geo g, Cplx<T>* c, const Cplx<T>* __restrict__ tw,
                                                      int sign, int tl) {
   extern __shared__ unsigned char lds_raw[];
   Cplx<T>* buf = (Cplx<T>*)lds_raw;
+  constexpr int n = R1 * R2;
+  constexpr int ls = n + 1;
   const int nx = g.n[0], ny = g.n[1];
-  const int n = g.n[A];
-  const int lg = ilog2(n);
   const long estride = A == 0 ? 1 : (A == 1 ? (long)nx : (long)nx * ny);
   const long l0 = (long)blockIdx.x * tl;
-  // line l -> offset of its element 0
   auto base = [&](long l) -> long {
     if (A == 0) return l * nx;
     if (A == 1) return (l % nx) + (l / nx) * (long)nx * ny;
@@ -77,39 +126,52 @@ __global__ void __launch_bounds__(kFftThreads) k_fft(Geo g, Cplx<T>* c, const Cp
       e = t / tl;
       line = t - e * tl;
     }
-    const int rev = (int)(__brev((unsigned)e) >> (32 - lg));
-    buf[line * n + rev] = c[base(l0 + line) + (long)e * estride];
+    buf[line * ls + e] = c[base(l0 + line) + (long)e * estride];
   }
   __syncthreads();
-  for (int s = 1; s <= lg; ++s) {
-    const int m = 1 << (s - 1);
-    const int half = n >> 1;
-    for (int b = threadIdx.x; b < tl * half; b += kFftThreads) {
-      const int line = b / half;
-      const int jj = b - line * half;
-      const int r = jj & (m - 1);
-      const int i0 = ((jj >> (s - 1)) << s) + r;
-      const int i1 = i0 + m;
-      const Cplx<T> w0 = tw[r << (lg - s)];
-      const T wr = w0.re, wi = sign < 0 ? w0.im : -w0.im;
-      Cplx<T>* L = buf + line * n;
-      const Cplx<T> u = L[i0], v = L[i1];
-      const T vr = v.re * wr - v.im * wi, vi = v.re * wi + v.im * wr;
-      L[i0] = Cplx<T>{u.re + vr, u.im + vi};
-      L[i1] = Cplx<T>{u.re - vr, u.im - vi};
-    }
-    __syncthreads();
-  }
-  for (int t = threadIdx.x; t < tot; t += kFftThreads) {
-    int line, e;
+  for (int jb = threadIdx.x; jb < tl * R2; jb += kFftThreads) {
+    int line, n2;
     if (A == 0) {
-      line = t / n;
-      e = t - line * n;
+      line = jb / R2;
+      n2 = jb - line * R2;
     } else {
-      e = t / tl;
-      line = t - e * tl;
+      n2 = jb / tl;
+      line = jb - n2 * tl;
     }
-    c[base(l0 + line) + (long)e * estride] = buf[line * n + e];
+    Cplx<T>* L = buf + line * ls;
+    Cplx<T> a[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) a[n1] = L[R2 * n1 + n2];
+    dft_reg<T, R1>(a, tw, n, sign);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      const int q = (n2 * k1) & (n - 1);  // W_n^q, q < n
+      Cplx<T> w = tw[q & (n / 2 - 1)];
+      if (q >= n / 2) w = Cplx<T>{-w.re, -w.im};
+      if (sign > 0) w.im = -w.im;
+      const Cplx<T> v = a[k1];
+      L[R2 * k1 + n2] = (q == 0) ? v
+                                 : Cplx<T>{v.re * w.re - v.im * w.im, v.re * w.im + v.im * w.re};
+    }
+  }
+  __syncthreads();
+  for (int jb = threadIdx.x; jb < tl * R1; jb += kFftThreads) {
+    int line, k1;
+    if (A == 0) {
+      line = jb / R1;
+      k1 = jb - line * R1;
+    } else {
+      k1 = jb / tl;
+      line = jb - k1 * tl;
+    }
+    const Cplx<T>* L = buf + line * ls;
+    Cplx<T> a[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) a[n2] = L[R2 * k1 + n2];
+    dft_reg<T, R2>(a, tw, n, sign);
+    const long b0 = base(l0 + line);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) c[b0 + (long)(k1 + R1 * k2) * estride] = a[k2];
   }
 }
 
@@ -153,6 +215,13 @@ __global__ void __launch_bounds__(256) k_grav_grad(Geo g, const Cplx<T>* __restr
   gr.g[2][p] = (c[cidx(g, i, j, kp)].re - c[cidx(g, i, j, km)].re) * (T)(0.5 / g.d[2]);
 }
 
+template <class T, int A, int R1, int R2>
+static void fft_launch(unsigned blocks, size_t lds, hipStream_t st, const Geo& g, Cplx<T>* c,
+                       const Cplx<T>* tw, int sign, int tl) {
+  hipLaunchKernelGGL((k_fft<T, A, R1, R2>), dim3(blocks), dim3(kFftThreads), lds, st, g, c, tw,
+                     sign, tl);
+}
+
 template <class T, int A>
 static void fft_axis(const Geo& g, Cplx<T>* c, const Cplx<T>* tw, int sign, hipStream_t st) {
   const int n = g.n[A];
@@ -163,8 +232,19 @@ static void fft_axis(const Geo& g, Cplx<T>* c, const Cplx<T>* tw, int sign, hipS
   if (tl > lines) tl = (int)lines;
   if (A != 0 && tl > g.n[0]) tl = g.n[0];  // tiles of consecutive x (powers of two)
   const unsigned blocks = (unsigned)(lines / tl);
-  const size_t lds = (size_t)tl * n * sizeof(Cplx<T>);
-  hipLaunchKernelGGL((k_fft<T, A>), dim3(blocks), dim3(kFftThreads), lds, st, g, c, tw, sign, tl);
+  const size_t lds = (size_t)tl * (n + 1) * sizeof(Cplx<T>);
+  switch (n) {  // n = R1 R2
+    case 2: fft_launch<T, A, 2, 1>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 4: fft_launch<T, A, 2, 2>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 8: fft_launch<T, A, 4, 2>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 16: fft_launch<T, A, 4, 4>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 32: fft_launch<T, A, 8, 4>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 64: fft_launch<T, A, 8, 8>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 128: fft_launch<T, A, 16, 8>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 256: fft_launch<T, A, 16, 16>(blocks, lds, st, g, c, tw, sign, tl); break;
+    case 512: fft_launch<T, A, 32, 16>(blocks, lds, st, g, c, tw, sign, tl); break;
+    default: fft_launch<T, A, 32, 32>(blocks, lds, st, g, c, tw, sign, tl); break;  // 1024
+  }
 }
 
 template <class T>

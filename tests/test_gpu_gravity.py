@@ -21,8 +21,11 @@ def _gravity_box(shape, seed, G=2.0):
     return pb
 
 
-@pytest.mark.parametrize("shape", [(16, 8, 32), (32, 4, 1), (8, 8, 8)])
+@pytest.mark.parametrize("shape", [(16, 8, 32), (32, 4, 1), (8, 8, 8), (1024, 2, 4), (4, 512, 2),
+                                   (2, 4, 256), (128, 64, 2)])
 def test_potential_and_state_match_oracle(shape):
+    """Every FFT line length from 2 to 1024 (each splits n = R1 R2
+    differently) along each axis."""
     pb = _gravity_box(shape, seed=41)
     o = oracle_of(pb)
     s = gpu_sim(pb)
