@@ -39,7 +39,8 @@ struct Layout {
                     // [nz][ny][nx] array, twiddle and eigenvalue tables (0 bytes if off)
   size_t off_scal;  // passive scalars: nscalar padded T arrays at t^n, then nscalar at
                     // t^{n+1/2}
-  size_t off_part;  // particles: x [3][npart], v [3][npart], m [npart]
+  size_t off_part;  // particles: two buffers of x [3][npart], v [3][npart], m [npart];
+                    // two id arrays [npart]; tile counters, offsets, cursors
   size_t total;
 };
 
@@ -94,7 +95,7 @@ bool config_ok(const mhd_config* c) {
   if (!(c->rho_floor >= 0.0) || !(c->p_floor >= 0.0)) return false;
   if (c->riemann < MHD_RIEMANN_HLLD || c->riemann > MHD_RIEMANN_HLLC) return false;
   if (c->nscalar < 0 || c->nscalar > MHD_MAX_SCALARS) return false;
-  if (c->npart < 0 || c->npart > (1ll << 40)) return false;
+  if (c->npart < 0 || c->npart > 0x7fffffffll) return false;
   if (c->npart > 0 && c->source != MHD_SRC_SELF_GRAVITY) return false;
   for (int q = 0; q < 2; ++q)
     if (c->reserved[q] != 0) return false;
@@ -103,6 +104,11 @@ bool config_ok(const mhd_config* c) {
   // the flux kernel addresses every padded array with 32-bit byte offsets
   const unsigned long long es = c->precision == MHD_FP64 ? 8ull : 4ull;
   return (unsigned long long)g.np * es <= 0xFFFFFFFFull;
+}
+
+int ntiles_of(const Geo& g) {
+  return ((g.n[0] + kTile - 1) / kTile) * ((g.n[1] + kTile - 1) / kTile) *
+         ((g.n[2] + kTile - 1) / kTile);
 }
 
 Layout layout_of(const mhd_config* c) {
@@ -129,7 +135,14 @@ Layout layout_of(const mhd_config* c) {
   }
   L.off_scal = L.off_grav + grav;
   L.off_part = L.off_scal + 2 * (size_t)c->nscalar * L.arr;
-  L.total = L.off_part + align_up(7 * (size_t)c->npart * es);
+  size_t part = 0;
+  if (c->npart > 0) {
+    const size_t np = (size_t)c->npart, nt = (size_t)ntiles_of(g);
+    const size_t mc = np / kChunk + nt;  // chunks of at most kChunk particles per tile
+    part = 2 * align_up(7 * np * es) + 2 * align_up(np * sizeof(int)) +
+           align_up((4 * nt + 2 + 1 + 3 * mc) * sizeof(int));
+  }
+  L.total = L.off_part + part;
   return L;
 }
 
@@ -257,17 +270,66 @@ struct mhd_ctx {
       s.x[m] = (T*)(ws + L.off_scal + ((size_t)set * cfg.nscalar + m) * L.arr);
     return s;
   }
+  // particles: buffer `part_cur` holds the current order
+  int part_cur = 0;
   template <class T>
-  Parts<T> parts() const {
+  char* part_base(int which) const {
+    const size_t np = (size_t)cfg.npart;
+    return ws + L.off_part + (size_t)which * align_up(7 * np * sizeof(T));
+  }
+  template <class T>
+  int* part_ids(int which) const {
+    const size_t np = (size_t)cfg.npart;
+    return (int*)(ws + L.off_part + 2 * align_up(7 * np * sizeof(T)) +
+                  (size_t)which * align_up(np * sizeof(int)));
+  }
+  int* tile_ints() const {
+    const size_t np = (size_t)cfg.npart;
+    const size_t es = cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
+    return (int*)(ws + L.off_part + 2 * align_up(7 * np * es) + 2 * align_up(np * sizeof(int)));
+  }
+  template <class T>
+  Parts<T> parts(int which) const {
     Parts<T> p{};
     p.n = cfg.npart;
     if (p.n > 0) {
-      T* b = (T*)(ws + L.off_part);
+      T* b = (T*)part_base<T>(which);
       p.x = b;
       p.v = b + 3 * p.n;
       p.m = b + 6 * p.n;
+      p.id = part_ids<T>(which);
+      const int nt = ntiles_of(g);
+      // tile ints: counters [nt], offsets [nt + 1], cursors [nt], chunk
+      // offsets [nt + 1], chunk list [1 + 3 max_chunks]
+      p.toff = tile_ints() + nt;
+      p.chunk = tile_ints() + 4 * nt + 2;
+      for (int a = 0; a < 3; ++a) p.nt[a] = (g.n[a] + kTile - 1) / kTile;
+      p.ntiles = nt;
+      p.max_chunks = (int)(cfg.npart / kChunk + nt);
     }
     return p;
+  }
+  template <class T>
+  Parts<T> parts() const {
+    return parts<T>(part_cur);
+  }
+  template <class T>
+  PartSort<T> part_sort(int which) const {
+    PartSort<T> s{};
+    if (cfg.npart > 0) {
+      const Parts<T> p = parts<T>(which);
+      s.x = p.x;
+      s.v = p.v;
+      s.m = p.m;
+      s.id = p.id;
+      const int nt = ntiles_of(g);
+      s.cnt = tile_ints();
+      s.off = s.cnt + nt;
+      s.cur = s.off + nt + 1;
+      s.coff = s.cur + nt;
+      s.chunk = s.coff + nt + 1;
+    }
+    return s;
   }
   bool gravity() const { return cfg.source == MHD_SRC_SELF_GRAVITY; }
   template <class T>
@@ -355,6 +417,11 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   const Muscl<T> second = muscl_of<T>(c->cfg.recon, c->cfg.kappa);
   const int ns = c->nscalar();
   const Scal<T> Xn = c->scal<T>(0), Xh = c->scal<T>(1);
+  if (c->cfg.npart > 0) {  // particles sorted by tile at the start of every step
+    c->mark(MHD_K_NBODY);
+    launch_particle_sort<T>(g, c->parts<T>(), c->part_sort<T>(1 - c->part_cur), c->st);
+    c->part_cur = 1 - c->part_cur;
+  }
   const Parts<T> Pp = c->parts<T>();
   DtRef at_n = dt, at_half = dt;  // particle positions of the two potentials
   at_n.factor = 0.0;
@@ -520,6 +587,12 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
     delete c;
     return MHD_E_HIP;
   }
+  if (cfg->npart > 0) {
+    if (cfg->precision == MHD_FP64)
+      launch_particles_init<double>(c->g, c->parts<double>(), c->st);
+    else
+      launch_particles_init<float>(c->g, c->parts<float>(), c->st);
+  }
   if (c->gravity()) {
     const int rc = cfg->precision == MHD_FP64 ? upload_gravity_tables<double>(c)
                                               : upload_gravity_tables<float>(c);
@@ -665,29 +738,28 @@ int mhd_set_particles(mhd_ctx* c, const void* d_x, const void* d_v, const void* 
   if (!c || !d_x || !d_v || !d_m || c->cfg.npart <= 0) return MHD_E_ARG;
   const size_t es = c->cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
   const size_t n = (size_t)c->cfg.npart;
-  char* b = c->ws + c->L.off_part;
+  char* b = es == sizeof(double) ? c->part_base<double>(c->part_cur)
+                                 : c->part_base<float>(c->part_cur);
   if (hipMemcpyAsync(b, d_x, 3 * n * es, hipMemcpyDeviceToDevice, c->st) != hipSuccess ||
       hipMemcpyAsync(b + 3 * n * es, d_v, 3 * n * es, hipMemcpyDeviceToDevice, c->st) !=
           hipSuccess ||
       hipMemcpyAsync(b + 6 * n * es, d_m, n * es, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
     return MHD_E_HIP;
   if (c->cfg.precision == MHD_FP64)
-    launch_wrap_positions<double>(c->g, c->parts<double>(), c->st);
+    launch_particles_init<double>(c->g, c->parts<double>(), c->st);
   else
-    launch_wrap_positions<float>(c->g, c->parts<float>(), c->st);
+    launch_particles_init<float>(c->g, c->parts<float>(), c->st);
   if (hip_status() != MHD_OK) return MHD_E_HIP;
   return hipStreamSynchronize(c->st) == hipSuccess ? MHD_OK : MHD_E_HIP;
 }
 
 int mhd_get_particles(mhd_ctx* c, void* d_x, void* d_v) {
   if (!c || c->cfg.npart <= 0 || (!d_x && !d_v)) return MHD_E_ARG;
-  const size_t es = c->cfg.precision == MHD_FP64 ? sizeof(double) : sizeof(float);
-  const size_t n = (size_t)c->cfg.npart;
-  const char* b = c->ws + c->L.off_part;
-  if ((d_x && hipMemcpyAsync(d_x, b, 3 * n * es, hipMemcpyDeviceToDevice, c->st) != hipSuccess) ||
-      (d_v && hipMemcpyAsync(d_v, b + 3 * n * es, 3 * n * es, hipMemcpyDeviceToDevice, c->st) !=
-                  hipSuccess))
-    return MHD_E_HIP;
+  if (c->cfg.precision == MHD_FP64)
+    launch_particles_out<double>(c->parts<double>(), (double*)d_x, (double*)d_v, c->st);
+  else
+    launch_particles_out<float>(c->parts<float>(), (float*)d_x, (float*)d_v, c->st);
+  if (hip_status() != MHD_OK) return MHD_E_HIP;
   return hipStreamSynchronize(c->st) == hipSuccess ? MHD_OK : MHD_E_HIP;
 }
 

@@ -119,13 +119,37 @@ struct Scal {
 };
 
 // N-body particles (context precision, structure of arrays): positions and
-// velocities [3][n] (x, y, z rows), masses [n]; n = 0: none.
+// velocities [3][n] (x, y, z rows), masses [n], and each particle's index in
+// the caller's order; n = 0: none.  The library keeps them sorted by tile
+// (kTile^3 cells, the tile holding the particle's cell): toff[t] .. toff[t+1]
+// are tile t's particles.
+constexpr int kTile = 8;
+constexpr int kChunk = 2048;  // particles per block of the deposit and the kick
 template <class T>
 struct Parts {
   T* x;
   T* v;
   T* m;
+  int* id;
   long long n;
+  const int* toff;   // [ntiles + 1]
+  const int* chunk;  // [1 + 3 max_chunks]: count, then (tile, first, end) per chunk
+  int nt[3];         // tiles per axis
+  int ntiles;
+  int max_chunks;    // n / kChunk + ntiles
+};
+// Scratch of the sort: the other buffer and the per-tile counters.
+template <class T>
+struct PartSort {
+  T* x;
+  T* v;
+  T* m;
+  int* id;
+  int* cnt;    // [ntiles]
+  int* off;    // [ntiles + 1]
+  int* cur;    // [ntiles]
+  int* coff;   // [ntiles + 1] chunk offsets
+  int* chunk;  // [1 + 3 max_chunks]
 };
 constexpr int kPartCflBlocks = 1024;  // per-block CFL partials of the particles
 
@@ -196,9 +220,17 @@ void launch_deposit(const Geo& g, Parts<T> pp, DtRef h, T* c, hipStream_t st);
 // x_h = x + dt/2 v, v -= dt grad Psi(x_h), x = x_h + dt/2 v, positions wrapped.
 template <class T>
 void launch_kick_drift(const Geo& g, Parts<T> pp, Grav<T> gr, DtRef dt, hipStream_t st);
-// Positions wrapped into the box (after the caller sets them).
+// Positions wrapped into the box and ids set to 0..n-1 (after the caller
+// sets the particles).
 template <class T>
-void launch_wrap_positions(const Geo& g, Parts<T> pp, hipStream_t st);
+void launch_particles_init(const Geo& g, Parts<T> pp, hipStream_t st);
+// Counting sort of pp by tile into the buffers of s (which then hold the
+// current order, with s.off the tile offsets).
+template <class T>
+void launch_particle_sort(const Geo& g, Parts<T> pp, PartSort<T> s, hipStream_t st);
+// Positions and velocities in the caller's order (x_out, v_out may be null).
+template <class T>
+void launch_particles_out(Parts<T> pp, T* x_out, T* v_out, hipStream_t st);
 void launch_advance_time(double* t, long long* step, DtRef dt, hipStream_t st);
 
 // Diagnostics: writes 14 doubles to out: mass, M(3), E, bsum(3), divb_max,

@@ -103,12 +103,18 @@ def test_scalars_add_two_padded_arrays_each():
         assert workspace_bytes(_cfg(nscalar=ns)) == base + 2 * ns * arr
 
 
-def test_particles_need_self_gravity_and_add_seven_values_each():
+def test_particles_need_self_gravity_and_add_their_buffers():
+    """Per particle: two buffers of 7 values (x, v, m; the sort's target)
+    and two ids; per 8^3-cell tile: counter, offset, cursor, chunk offset;
+    the chunk list (tile, first, end) of at most n / 2048 + tiles chunks."""
     base = dict(nx=16, ny=8, nz=4, dx=0.1, dy=0.1, dz=0.1, source=L.SRC_SELF_GRAVITY,
                 src=(1.0, 0.0, 0.0, 0.0))
-    w0 = workspace_bytes(MHDConfig(**base))
+    a = lambda b: (b + 255) // 256 * 256
+    nt = 2 * 1 * 1
     for n, es, prec in ((1000, 8, 0), (1000, 4, 1), (12345, 4, 1)):
         w = workspace_bytes(MHDConfig(npart=n, precision=prec, **base))
-        w0p = workspace_bytes(MHDConfig(precision=prec, **base))
-        assert w - w0p == (7 * n * es + 255) // 256 * 256
-    assert w0 > 0
+        w0 = workspace_bytes(MHDConfig(precision=prec, **base))
+        mc = n // 2048 + nt
+        assert w - w0 == 2 * a(7 * n * es) + 2 * a(4 * n) + a(4 * (4 * nt + 3 + 3 * mc))
+    with pytest.raises(L.MHDError):
+        workspace_bytes(MHDConfig(npart=1 << 31, **base))
