@@ -11,10 +11,9 @@
 // weights, which keeps the total momentum.
 //
 // The particles are kept sorted by tile (kTile^3 cells): every step starts
-// with a counting sort by the tile of each particle's cell (wave-aggregated
-// atomics: one per run of equal tiles in a wave, which in sorted order is
-// about one per wave), and each tile's particles are cut into chunks of at
-// most kChunk.  One block per chunk then works in LDS: the deposit
+// with a counting sort by the tile of each particle's cell (counts gathered
+// per block in LDS, one global atomic per distinct tile and block), and
+// each tile's particles are cut into chunks of at most kChunk.  One block per chunk then works in LDS: the deposit
 // adds into a private copy of the cells the tile's particles can reach (the
 // tile and 2 cells around it: a particle moves at most half a cell between
 // the sort and the half-step deposit under the CFL limit) and flushes it
@@ -86,27 +85,6 @@ __device__ __forceinline__ int win_index(int c, int o, int n) {
 __device__ __forceinline__ void atomic_add_t(double* p, double v) { atomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_t(float* p, float v) { atomicAdd(p, v); }
 
-// Adds k to ctr[key] for every lane with key >= 0, one atomic per distinct
-// key in the wave; returns this lane's slot (the old value plus its rank
-// among the wave's lanes of the same key).  Reached by every lane.
-__device__ __forceinline__ int wave_agg_add(int* ctr, int key) {
-  const unsigned lane = threadIdx.x & 63u;
-  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  unsigned long long todo = __ballot(key >= 0);
-  int slot = 0;
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int k = __shfl(key, leader, 64);
-    const unsigned long long match = __ballot(key == k) & todo;
-    int base = 0;
-    if ((int)lane == leader) base = atomicAdd(ctr + k, (int)__popcll(match));
-    base = __shfl(base, leader, 64);
-    if (key == k) slot = base + (int)__popcll(match & lt);
-    todo &= ~match;
-  }
-  return slot;
-}
-
 // ---------------------------------------------------------------------------
 // Sort by tile
 // ---------------------------------------------------------------------------
@@ -116,17 +94,71 @@ __global__ void __launch_bounds__(kPartThreads) k_tile_zero(int* cnt, int ntiles
     cnt[t] = 0;
 }
 
+// Block-level aggregation of the sort's counters: a block takes kSortChunk
+// consecutive particles -- in the order of the last sort, so a few tiles
+// and their neighbours -- and gathers their per-tile counts in an LDS hash
+// table (kSortSlots slots, linear probing) before one global atomic per
+// distinct tile.  A key the table cannot place within kSortProbes probes
+// goes to HBM directly (the first sort of particles in arbitrary order).
+// (Per-wave aggregation alone still piled ~2000 atomics per step onto the
+// counter of a dense core tile.)
+constexpr int kSortChunk = 4096;
+constexpr int kSortSlots = 512;
+constexpr int kSortProbes = 32;  // a key not placed within this many probes goes to HBM
+
+struct SortTable {
+  int key[kSortSlots];
+  int cnt[kSortSlots];
+  int base[kSortSlots];
+};
+
+__device__ __forceinline__ void table_clear(SortTable& tb) {
+  for (int i = threadIdx.x; i < kSortSlots; i += kPartThreads) {
+    tb.key[i] = -1;
+    tb.cnt[i] = 0;
+  }
+}
+
+// Slot of key in the table (inserted if absent), or -1 if it is not found
+// within kSortProbes probes.
+__device__ __forceinline__ int table_find(SortTable& tb, int key, bool insert) {
+  int h = (int)(((unsigned)key * 2654435761u) >> 20) & (kSortSlots - 1);
+  for (int probe = 0; probe < kSortProbes; ++probe) {
+    const int k = __atomic_load_n(&tb.key[h], __ATOMIC_RELAXED);
+    if (k == key) return h;
+    if (k == -1) {
+      if (!insert) return -1;
+      const int old = atomicCAS(&tb.key[h], -1, key);
+      if (old == -1 || old == key) return h;
+    }
+    h = (h + 1) & (kSortSlots - 1);
+  }
+  return -1;
+}
+
+static unsigned sort_blocks(long long n) {
+  return (unsigned)((n + kSortChunk - 1) / kSortChunk);
+}
+
 template <class T>
 __global__ void __launch_bounds__(kPartThreads) k_tile_count(Geo g, Parts<T> pp, int* cnt) {
+  __shared__ SortTable tb;
+  table_clear(tb);
+  __syncthreads();
   const long long n = pp.n;
-  const long long stride = (long long)gridDim.x * kPartThreads;
-  const long long q0 = (long long)blockIdx.x * kPartThreads + threadIdx.x;
-  const long long rounds = (n + stride - 1) / stride;  // the same for every lane of the grid
-  for (long long r = 0; r < rounds; ++r) {
-    const long long q = q0 + r * stride;
-    const int key = q < n ? tile_of(g, pp, q) : -1;
-    wave_agg_add(cnt, key);
+  const long long q0 = (long long)blockIdx.x * kSortChunk;
+  const long long q1 = q0 + kSortChunk < n ? q0 + kSortChunk : n;
+  for (long long q = q0 + threadIdx.x; q < q1; q += kPartThreads) {
+    const int key = tile_of(g, pp, q);
+    const int h = table_find(tb, key, true);
+    if (h >= 0)
+      atomicAdd(&tb.cnt[h], 1);
+    else
+      atomicAdd(cnt + key, 1);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSortSlots; i += kPartThreads)
+    if (tb.cnt[i] > 0) atomicAdd(cnt + tb.key[i], tb.cnt[i]);
 }
 
 // Exclusive scan of cnt into off (ntiles + 1 entries) and, if cur, cur =
@@ -154,25 +186,38 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int* cnt, int* off, in
   if (threadIdx.x == 1023) off[ntiles] = part[1023];
 }
 
+// Same blocks and table: each distinct tile reserves its block's range of
+// slots with one global atomic on its cursor; particles take slots from
+// LDS counters (their order within a tile's range is not deterministic).
 template <class T>
 __global__ void __launch_bounds__(kPartThreads) k_tile_scatter(Geo g, Parts<T> pp, PartSort<T> s) {
+  __shared__ SortTable tb;
+  table_clear(tb);
+  __syncthreads();
   const long long n = pp.n;
-  const long long stride = (long long)gridDim.x * kPartThreads;
-  const long long q0 = (long long)blockIdx.x * kPartThreads + threadIdx.x;
-  const long long rounds = (n + stride - 1) / stride;
-  for (long long r = 0; r < rounds; ++r) {
-    const long long q = q0 + r * stride;
-    const int key = q < n ? tile_of(g, pp, q) : -1;
-    const int slot = wave_agg_add(s.cur, key);
-    if (q < n) {
+  const long long q0 = (long long)blockIdx.x * kSortChunk;
+  const long long q1 = q0 + kSortChunk < n ? q0 + kSortChunk : n;
+  for (long long q = q0 + threadIdx.x; q < q1; q += kPartThreads) {
+    const int h = table_find(tb, tile_of(g, pp, q), true);
+    if (h >= 0) atomicAdd(&tb.cnt[h], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSortSlots; i += kPartThreads) {
+    if (tb.cnt[i] > 0) tb.base[i] = atomicAdd(s.cur + tb.key[i], tb.cnt[i]);
+    tb.cnt[i] = 0;
+  }
+  __syncthreads();
+  for (long long q = q0 + threadIdx.x; q < q1; q += kPartThreads) {
+    const int key = tile_of(g, pp, q);
+    const int h = table_find(tb, key, false);
+    const int slot = h >= 0 ? tb.base[h] + atomicAdd(&tb.cnt[h], 1) : atomicAdd(s.cur + key, 1);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        s.x[a * n + slot] = pp.x[a * n + q];
-        s.v[a * n + slot] = pp.v[a * n + q];
-      }
-      s.m[slot] = pp.m[q];
-      s.id[slot] = pp.id[q];
+    for (int a = 0; a < 3; ++a) {
+      s.x[a * n + slot] = pp.x[a * n + q];
+      s.v[a * n + slot] = pp.v[a * n + q];
     }
+    s.m[slot] = pp.m[q];
+    s.id[slot] = pp.id[q];
   }
 }
 
@@ -203,10 +248,10 @@ void launch_particle_sort(const Geo& g, Parts<T> pp, PartSort<T> s, hipStream_t 
   if (pp.n <= 0) return;
   const unsigned tb = (unsigned)((pp.ntiles + kPartThreads - 1) / kPartThreads);
   hipLaunchKernelGGL(k_tile_zero, dim3(tb), dim3(kPartThreads), 0, st, s.cnt, pp.ntiles);
-  hipLaunchKernelGGL(k_tile_count<T>, dim3(part_blocks(pp.n)), dim3(kPartThreads), 0, st, g, pp,
+  hipLaunchKernelGGL(k_tile_count<T>, dim3(sort_blocks(pp.n)), dim3(kPartThreads), 0, st, g, pp,
                      s.cnt);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, s.cnt, s.off, s.cur, pp.ntiles);
-  hipLaunchKernelGGL(k_tile_scatter<T>, dim3(part_blocks(pp.n)), dim3(kPartThreads), 0, st, g,
+  hipLaunchKernelGGL(k_tile_scatter<T>, dim3(sort_blocks(pp.n)), dim3(kPartThreads), 0, st, g,
                      pp, s);
   // the cursors are spent: they take the chunk counts
   hipLaunchKernelGGL(k_chunk_count, dim3(tb), dim3(kPartThreads), 0, st, s.cnt, s.cur, pp.ntiles);
