@@ -874,18 +874,34 @@ __device__ __forceinline__ T scalar_flux(T F, T xl, T xr) {
   return F > T(0) ? F * xl : (F < T(0) ? F * xr : T(0));
 }
 
-template <class T>
+// NS (the scalar count) is a template parameter so that every load of a
+// point -- 13 stencil values per scalar, the stage density and mass fluxes
+// -- is issued before the first store (with a run-time count the stores of
+// one scalar could alias the next one's loads and would order them).
+template <class T, int NS>
 __global__ void __launch_bounds__(kSpanThreads) k_scalar_update(Geo g, Span sp,
                                                                 const T* __restrict__ rho,
                                                                 Flux<T> f, Scal<T> x0, Scal<T> xs,
-                                                                Scal<T> x1, int ns, Muscl<T> mu,
+                                                                Scal<T> x1, Muscl<T> mu,
                                                                 DtRef dtr) {
   const Pt pt = span_point(g, sp);
   if (!pt.valid) return;
   const int p = pt.p;
   const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
   const int st[3] = {1, g.sy, g.sz};
-  // 1 / rho on the stencil p + (o - 2) s_a; mass fluxes of the low and high face
+  // stencil point o of axis a: p + (o - 2) s_a (o = 2: the cell itself)
+  T xv[NS][3][5], v0[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const T* q = xs.x[m];
+    const T c = q[p];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < 5; ++o) xv[m][a][o] = o == 2 ? c : q[p + (o - 2) * st[a]];
+    v0[m] = x0.x[m][p];
+  }
+  // 1 / rho on the stencil; mass fluxes of the low and high face
   T ir[3][5], flo[3], fhi[3], r[3];
   const T ic = rcp(rho[p]);
 #pragma unroll
@@ -896,21 +912,31 @@ __global__ void __launch_bounds__(kSpanThreads) k_scalar_update(Geo g, Span sp,
     fhi[a] = f.f[a][0][p + st[a]];
     r[a] = (T)(dt / g.d[a]);
   }
-  for (int m = 0; m < ns; ++m) {
-    const T* q = xs.x[m];
-    T v = x0.x[m][p];
+  T out[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    T v = v0[m];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       T X[5];
 #pragma unroll
-      for (int o = 0; o < 5; ++o) X[o] = q[p + (o - 2) * st[a]] * ir[a][o];
+      for (int o = 0; o < 5; ++o) X[o] = xv[m][a][o] * ir[a][o];
       T l0, r0, l1, r1;
       muscl_lr(mu, X[0], X[1], X[2], X[3], l0, r0);
       muscl_lr(mu, X[1], X[2], X[3], X[4], l1, r1);
       v -= r[a] * (scalar_flux(fhi[a], l1, r1) - scalar_flux(flo[a], l0, r0));
     }
-    x1.x[m][p] = v;
+    out[m] = v;
   }
+#pragma unroll
+  for (int m = 0; m < NS; ++m) x1.x[m][p] = out[m];
+}
+
+template <class T, int NS>
+static void scalar_update_ns(const Geo& g, const Span& sp, const T* rho, Flux<T> f, Scal<T> x0,
+                             Scal<T> xs, Scal<T> x1, Muscl<T> m, DtRef dt, hipStream_t st) {
+  hipLaunchKernelGGL((k_scalar_update<T, NS>), span_grid(sp), dim3(kSpanThreads), 0, st, g, sp,
+                     rho, f, x0, xs, x1, m, dt);
 }
 
 template <class T>
@@ -918,8 +944,16 @@ void launch_scalar_update(const Geo& g, const T* rho, Flux<T> f, Scal<T> x0, Sca
                           Scal<T> x1, int ns, Muscl<T> m, DtRef dt, hipStream_t st) {
   if (ns <= 0) return;
   const Span sp = make_span(g, 0, g.n[0] - 1, 0, g.n[1] - 1, 0, g.n[2] - 1);
-  hipLaunchKernelGGL(k_scalar_update<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, sp, rho, f,
-                     x0, xs, x1, ns, m, dt);
+  switch (ns) {
+    case 1: scalar_update_ns<T, 1>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+    case 2: scalar_update_ns<T, 2>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+    case 3: scalar_update_ns<T, 3>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+    case 4: scalar_update_ns<T, 4>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+    case 5: scalar_update_ns<T, 5>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+    case 6: scalar_update_ns<T, 6>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+    case 7: scalar_update_ns<T, 7>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+    default: scalar_update_ns<T, 8>(g, sp, rho, f, x0, xs, x1, m, dt, st); break;
+  }
 }
 
 // Ghost points of the scalar arrays: periodic wrap / outflow copy as for the
