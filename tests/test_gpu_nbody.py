@@ -192,3 +192,32 @@ def test_fullsize_poisson_and_kick_sampled():
         acc = o.particle_interp(grad[a], xh[:, sel])
         got = v1[a, sel]
         assert np.abs(got - (v[a, sel] - dt * acc)).max() <= 1e-12 * (np.abs(v[a]).max() + 1.0)
+
+
+def test_gas_scalars_particles_together_parity():
+    """Everything at once, FP64: coupled self-gravity, two passive scalars
+    and 800 particles on a ragged 32 x 16 x 8 box, 4 steps with the oracle's
+    steps: gas state, scalars and particles within 1e-11."""
+    from paper_1502_02935_amd import Sim, config_from_problem
+    pb = P.random_smooth((32, 16, 8), seed=11, d=(1 / 32, 1 / 16, 1 / 8))
+    pb.source, pb.src = P.SRC_SELF_GRAVITY, (0.7, 0.0, 0.0, 0.0)
+    x, v, m = P.particles_plummer(pb, 800, seed=12, scale=0.15, mass_total=1.5, G=0.7)
+    rx = P.mass_fractions(pb, 2, "random", seed=13)
+    cfg = orc_config(pb)
+    cfg.npart, cfg.nscalar = x.shape[1], 2
+    o = O.Oracle(cfg)
+    assert o.set_state(pb.cell5, pb.bx, pb.by, pb.bz) == 0
+    o.set_particles(x, v, m)
+    o.set_scalars(rx)
+    s = Sim(config_from_problem(pb, precision=0, npart=x.shape[1], nscalar=2), pb.cell5, pb.bx,
+            pb.by, pb.bz)
+    s.set_particles(x, v, m)
+    s.set_scalars(rx)
+    _run_both(o, s, 4)
+    ex, ev = _particle_errors(s, o, pb)
+    assert ex <= TOL and ev <= TOL, (ex, ev)
+    err = field_errors(host_state(s), o.get_state())
+    assert max(err.values()) <= TOL, err
+    g = s.get_scalars().double().cpu().numpy()
+    r = o.get_scalars()
+    assert max(rel_err(g[k], r[k]) for k in range(2)) <= TOL
