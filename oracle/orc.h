@@ -19,9 +19,24 @@
  *     and the two gas-dynamic solvers the code also offers: HLL, and HLLC
  *     for pure gas dynamics (B = 0)                                (sec. 2.1)
  *   - kappa-MUSCL reconstruction with minmod                      (Eq. 12-14)
+ *   - source S from a fixed potential or from self-gravity, the periodic
+ *     Poisson equation Lap Psi = 4 pi G rho solved by the discrete Fourier
+ *     transform written out from its definition                   (Eq. 15)
+ *   - passive scalars carried by the mass flux (multi-species gas) (sec. 1)
+ *   - N-body particles: cloud-in-cell deposit and force, leapfrog
+ *     ("flip-flop") in the same potential                         (sec. 2.1)
+ *   - the learned flux correction of the coarse runs (an extension)
  * Readings where the paper is silent or misprinted (time integrator, CFL,
  * sign of the Eq. 10 correction, ...) are listed in the project design notes
  * and restated next to the code that implements each one.
+ *
+ * Pins (the tests check this code against closed forms, textbook solutions,
+ * independent formulations and invariants, not against itself): every part
+ * above has at least one.  Parity unpinned: the density and pressure floors
+ * (they act only in the disc workload, where the GPU path is checked against
+ * this code but nothing fixes the floors' effect independently) and the
+ * exact value of the HLLD degenerate-state threshold (pinned only to keep
+ * the flux bounded near it).
  *
  * All arrays handed across this interface are host memory, FP64, interior
  * cells only, x fastest:
