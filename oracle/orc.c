@@ -1269,9 +1269,18 @@ static void update(orc_grid *g, double dt, double *const u0[5], double *const b0
         if (g->c.rho_floor > 0.0 || g->c.p_floor > 0.0) {
           int hit = 0;
           if (u1[0][p] < g->c.rho_floor) { u1[0][p] = g->c.rho_floor; hit = 1; }
-          double bcx = 0.5 * (b1[0][p] + b1[0][p + g->st[0]]);
-          double bcy = 0.5 * (b1[1][p] + b1[1][p + g->st[1]]);
-          double bcz = 0.5 * (b1[2][p] + b1[2][p + g->st[2]]);
+          /* cell-centred B of the updated faces; on a periodic axis the
+             upper face of the last cell is the first face (its ghost copy
+             is not written until the next ghost fill) */
+          int idx[3];
+          double bcn[3];
+          idx[0] = i; idx[1] = j; idx[2] = k;
+          for (m = 0; m < 3; ++m) {
+            long up = p + g->st[m];
+            if (g->per[m] && idx[m] == g->n[m] - 1) up = p - (long)(g->n[m] - 1) * g->st[m];
+            bcn[m] = 0.5 * (b1[m][p] + b1[m][up]);
+          }
+          double bcx = bcn[0], bcy = bcn[1], bcz = bcn[2];
           double rho = u1[0][p];
           double ke = 0.5 * (u1[1][p] * u1[1][p] + u1[2][p] * u1[2][p] + u1[3][p] * u1[3][p]) / rho;
           double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);

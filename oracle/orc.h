@@ -32,11 +32,10 @@
  *
  * Pins (the tests check this code against closed forms, textbook solutions,
  * independent formulations and invariants, not against itself): every part
- * above has at least one.  Parity unpinned: the density and pressure floors
- * (they act only in the disc workload, where the GPU path is checked against
- * this code but nothing fixes the floors' effect independently) and the
- * exact value of the HLLD degenerate-state threshold (pinned only to keep
- * the flux bounded near it).
+ * above has at least one (the density and pressure floors, which the paper
+ * leaves open, through the closed forms they give on uniform states).
+ * Parity unpinned: the exact value of the HLLD degenerate-state threshold
+ * (pinned only to keep the flux bounded near it).
  *
  * All arrays handed across this interface are host memory, FP64, interior
  * cells only, x fastest:
