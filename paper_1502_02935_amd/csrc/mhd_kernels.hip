@@ -578,12 +578,20 @@ __global__ void __launch_bounds__(kSpanThreads) k_floors(Geo g, Physics ph, Span
       hit = true;
     }
     const T gam = (T)ph.gamma;
+    // Upper faces of the cell; on a periodic axis (nf = n) the last cell's
+    // upper face is the first face, whose ghost copy the next ghost fill
+    // writes.
+    const int cc[3] = {pt.i, pt.j, pt.k};
+    const int st[3] = {1, g.sy, g.sz};
+    int up[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      up[a] = (g.nf[a] == g.n[a] && cc[a] == g.n[a] - 1) ? p - (g.n[a] - 1) * st[a] : p + st[a];
     T bcx, bcy, bcz;
     bool rec;
     const T E = s.u[4][p];
-    const T P = pressure(gam, rho, s.u[1][p], s.u[2][p], s.u[3][p], E, s.b[0][p], s.b[0][p + 1],
-                         s.b[1][p], s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz], bcx, bcy, bcz,
-                         rec);
+    const T P = pressure(gam, rho, s.u[1][p], s.u[2][p], s.u[3][p], E, s.b[0][p], s.b[0][up[0]],
+                         s.b[1][p], s.b[1][up[1]], s.b[2][p], s.b[2][up[2]], bcx, bcy, bcz, rec);
     if (P < (T)ph.p_floor) {
       s.u[4][p] = E + ((T)ph.p_floor - P) / (gam - T(1));
       hit = true;

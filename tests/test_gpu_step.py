@@ -135,6 +135,30 @@ def test_disc_outflow_source_floors():
     assert s.diag()["n_floor"] == o.diag()["n_floor"]
 
 
+def _cell_pressure(pb):
+    """Gas pressure of a periodic problem's cells (face-mean B)."""
+    rho, mx, my, mz, e = pb.cell5
+    bcx = 0.5 * (pb.bx + np.roll(pb.bx, -1, axis=2))
+    bcy = 0.5 * (pb.by + np.roll(pb.by, -1, axis=1))
+    bcz = 0.5 * (pb.bz + np.roll(pb.bz, -1, axis=0))
+    return (pb.gamma - 1.0) * (e - 0.5 * (mx * mx + my * my + mz * mz) / rho
+                               - 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz))
+
+
+@pytest.mark.parametrize("which", ["rho", "p", "both"])
+def test_floors_periodic(which):
+    """Floors acting in about a third of a periodic box's cells (the last
+    cell of each periodic axis takes its upper face from the first face)."""
+    pb = P.random_smooth((20, 16, 12), seed=41, amp=0.5)
+    if which in ("rho", "both"):
+        pb.rho_floor = float(np.quantile(pb.cell5[0], 0.3))
+    if which in ("p", "both"):
+        pb.p_floor = float(np.quantile(_cell_pressure(pb), 0.3))
+    s, o, err = _parity(pb, 3)
+    assert o.diag()["n_floor"] > 0
+    assert s.diag()["n_floor"] == o.diag()["n_floor"]
+
+
 def test_uniform_gravity_source():
     pb = P.random_smooth((20, 16, 12), seed=33)
     pb.source, pb.src = P.SRC_UNIFORM, (0.3, -0.2, 0.5, 0.0)
