@@ -21,7 +21,10 @@ using namespace mhd;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kNumT = 51;  // T arrays: U 8, U* 8, W 8 + Ec 3, fluxes 21, edges 3
+// T arrays: two state sets (5 cells + 3 faces each), the primitives and cell
+// EMF of the current state (8 + 3), fluxes 21, edges 3, the primitives and
+// cell EMF of the half step (8 + 3).
+constexpr int kNumT = 62;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -233,18 +236,26 @@ struct mhd_ctx {
     c.status = (unsigned int*)(misc() + M_STATUS);
     return c;
   }
+  // The corrector writes the new faces into the half step's face arrays
+  // (the cells in place): fcur names the face set that holds U's faces.
+  int fcur = 0;
+  // w_valid: prim<T>(0) holds the primitives of U (interior and ghost
+  // shell), as the last step left them; cfl_valid: cfl_part() holds that
+  // step's update_cfl_blocks() partials of U's time-step candidates.
+  bool w_valid = false, cfl_valid = false;
   template <class T>
   Cons<T> cons(int set) const {  // set 0: U (t^n), 1: U* (half step)
     Cons<T> s;
     for (int m = 0; m < 5; ++m) s.u[m] = (T*)arr(8 * set + m);
-    for (int a = 0; a < 3; ++a) s.b[a] = (T*)arr(8 * set + 5 + a);
+    for (int a = 0; a < 3; ++a) s.b[a] = (T*)arr(8 * (set ^ fcur) + 5 + a);
     return s;
   }
   template <class T>
-  Prim<T> prim() const {
+  Prim<T> prim(int set) const {  // set 0: of U, 1: of U* (the corrector's input)
+    const int q = set ? 51 : 16;
     Prim<T> w;
-    for (int m = 0; m < 8; ++m) w.w[m] = (T*)arr(16 + m);
-    for (int a = 0; a < 3; ++a) w.ec[a] = (T*)arr(24 + a);
+    for (int m = 0; m < 8; ++m) w.w[m] = (T*)arr(q + m);
+    for (int a = 0; a < 3; ++a) w.ec[a] = (T*)arr(q + 8 + a);
     return w;
   }
   template <class T>
@@ -410,7 +421,10 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   const Geo& g = c->g;
   const Counters cnt = c->counters();
   const Cons<T> U = c->cons<T>(0), Us = c->cons<T>(1);
-  const Prim<T> W = c->prim<T>();
+  // the corrector's result: U's cells in place, the new faces in the half
+  // step's face arrays (which become U's at the end of the step)
+  const Cons<T> Un = {{U.u[0], U.u[1], U.u[2], U.u[3], U.u[4]}, {Us.b[0], Us.b[1], Us.b[2]}};
+  const Prim<T> W = c->prim<T>(0), Ws = c->prim<T>(1);
   const Flux<T> F = c->flux<T>();
   const Edge<T> E = c->edge<T>();
   const Muscl<T> first = muscl_of<T>(MHD_RECON_FIRST, c->cfg.kappa);
@@ -426,17 +440,27 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   DtRef at_n = dt, at_half = dt;  // particle positions of the two potentials
   at_n.factor = 0.0;
   at_half.factor = 0.5;
-  // predictor: first-order fluxes of U^n, half step into U*; a step that
-  // takes its dt from the device gets it from the same primitives pass
+  // primitives of U^n (and the step's own dt): left by the previous step's
+  // corrector, else one pass over U
   c->mark(MHD_K_PRIM);
-  if (dt.ptr)
-    launch_prim_cfl<T>(g, c->ph, U, W, c->cfl_part(), c->misc() + M_DT, cnt, Pp, c->st);
-  else
-    launch_prim<T>(g, c->ph, U, W, cnt, c->st);
+  if (!c->w_valid) {
+    if (dt.ptr)
+      launch_prim_cfl<T>(g, c->ph, U, W, c->cfl_part(), c->misc() + M_DT, cnt, Pp, c->st);
+    else
+      launch_prim<T>(g, c->ph, U, W, cnt, c->st);
+  } else if (dt.ptr) {
+    if (c->cfl_valid)
+      launch_cfl_reduce<T>(g, c->ph, c->cfl_part(), update_cfl_blocks(g), c->misc() + M_DT, Pp,
+                           c->st);
+    else
+      launch_cfl<T>(g, c->ph, U, c->cfl_part(), c->misc() + M_DT, cnt, Pp, c->st);
+  }
   if (c->gravity()) {
     c->mark(MHD_K_GRAVITY);
     launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_n, c->st);
   }
+  // predictor: first-order fluxes of U^n, half step into U* and its
+  // primitives
   c->mark(MHD_K_FLUX);
   launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
   c->mark(MHD_K_EMF);
@@ -444,7 +468,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   DtRef half = dt;
   half.factor = 0.5;
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, Us, W, F, E, c->grav<T>(), half, cnt, c->st);
+  launch_update<T>(g, c->ph, U, Us, W, Ws, F, E, c->grav<T>(), half, cnt, nullptr, c->st);
   if (ns) {
     c->mark(MHD_K_SCALARS);
     launch_scalar_update<T>(g, W.w[0], F, Xn, Xn, Xh, ns, first, half, c->st);
@@ -452,42 +476,45 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   }
   c->mark(MHD_K_GHOSTS);
   launch_ghosts<T>(g, c->ph, Us, c->st);
-  // corrector: MUSCL fluxes of U*, full step from U^n
   c->mark(MHD_K_PRIM);
-  launch_prim<T>(g, c->ph, Us, W, cnt, c->st);
+  launch_prim_shell<T>(g, c->ph, Us, Ws, cnt, c->st);
+  // corrector: MUSCL fluxes of U*, full step from U^n, the primitives of
+  // U^{n+1} and the candidates of the next step's dt
   if (c->gravity()) {
     c->mark(MHD_K_GRAVITY);
-    launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_half,
+    launch_self_gravity<T>(g, c->ph, Ws.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_half,
                            c->st);
   }
   if (c->mlp_params) {
     c->mark(MHD_K_SHOCK);
-    launch_shock<T>(g, W, c->shock(), c->mlp_jump, c->st);
+    launch_shock<T>(g, Ws, c->shock(), c->mlp_jump, c->st);
     // the caller may change the weights between steps: repack every step
     launch_mlp_pack(c->mlp_params, c->frags(), c->st);
     for (int a = 0; a < 3; ++a) {
       c->mark(MHD_K_FLUX_MLP);
-      launch_flux_mlp<T>(g, c->ph, a, W, Us.b[a], F, second, cnt, c->mlp_ref(), c->st);
+      launch_flux_mlp<T>(g, c->ph, a, Ws, Us.b[a], F, second, cnt, c->mlp_ref(), c->st);
     }
   } else {
     c->mark(MHD_K_FLUX);
-    launch_flux<T>(g, c->ph, W, Us, F, second, cnt, c->st);
+    launch_flux<T>(g, c->ph, Ws, Us, F, second, cnt, c->st);
   }
   if (c->flux_acc) {
     c->mark(MHD_K_OTHER);
     launch_fluxacc<T>(g, F, (T*)c->flux_acc, dt, c->st);
   }
   c->mark(MHD_K_EMF);
-  launch_emf<T>(g, W, F, E, c->st);
+  launch_emf<T>(g, Ws, F, E, c->st);
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, U, W, F, E, c->grav<T>(), dt, cnt, c->st);
+  launch_update<T>(g, c->ph, U, Un, Ws, W, F, E, c->grav<T>(), dt, cnt, c->cfl_part(), c->st);
   if (ns) {
     c->mark(MHD_K_SCALARS);
-    launch_scalar_update<T>(g, W.w[0], F, Xn, Xh, Xn, ns, second, dt, c->st);
+    launch_scalar_update<T>(g, Ws.w[0], F, Xn, Xh, Xn, ns, second, dt, c->st);
     launch_scalar_ghosts<T>(g, Xn, ns, c->st);
   }
   c->mark(MHD_K_GHOSTS);
-  launch_ghosts<T>(g, c->ph, U, c->st);
+  launch_ghosts<T>(g, c->ph, Un, c->st);
+  c->mark(MHD_K_PRIM);
+  launch_prim_shell<T>(g, c->ph, Un, W, cnt, c->st);
   if (Pp.n > 0) {
     c->mark(MHD_K_NBODY);
     launch_kick_drift<T>(g, Pp, c->grav<T>(), dt, c->st);
@@ -495,10 +522,14 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->mark(MHD_K_OTHER);
   launch_advance_time(c->misc() + M_T, (long long*)(c->misc() + M_STEP), dt, c->st);
   c->mark(-1);
+  c->fcur ^= 1;
+  c->w_valid = true;
+  c->cfl_valid = true;
 }
 
 template <class T>
 void enqueue_cfl(mhd_ctx* c) {
+  c->cfl_valid = false;  // the partials are this pass's now
   c->mark(MHD_K_CFL);
   launch_cfl<T>(c->g, c->ph, c->cons<T>(0), c->cfl_part(), c->misc() + M_DT, c->counters(),
                 c->parts<T>(), c->st);
@@ -788,9 +819,9 @@ int mhd_debug_array(mhd_ctx* c, int what, void* d_out, size_t* n_out) {
   else if (what < 24)
     q = 48 + (what - 21);  // edges
   else if (what < 27)
-    q = 24 + (what - 24);  // cell EMF
+    q = 59 + (what - 24);  // cell EMF of the corrector's input
   else
-    q = 16 + (what - 27);  // primitives
+    q = 51 + (what - 27);  // primitives of the corrector's input
   if (hipMemcpyAsync(d_out, c->arr(q), (size_t)c->g.np * es, hipMemcpyDeviceToDevice, c->st) !=
       hipSuccess)
     return MHD_E_HIP;
@@ -884,13 +915,13 @@ int mhd_mlp_samples(mhd_ctx* c, const void* d_acc, double dt_coarse, int64_t n,
 
   if (n == 0) return MHD_OK;
   if (c->cfg.precision == MHD_FP64) {
-    launch_shock<double>(c->g, c->prim<double>(), c->shock(), c->mlp_jump, c->st);
-    launch_mlp_samples<double>(c->g, c->prim<double>(), c->flux<double>(), c->shock(),
+    launch_shock<double>(c->g, c->prim<double>(1), c->shock(), c->mlp_jump, c->st);
+    launch_mlp_samples<double>(c->g, c->prim<double>(1), c->flux<double>(), c->shock(),
                                (const double*)d_acc, dt_coarse, c->ph.gamma, n, d_faces, d_x, d_t,
                                d_mask, c->st);
   } else {
-    launch_shock<float>(c->g, c->prim<float>(), c->shock(), c->mlp_jump, c->st);
-    launch_mlp_samples<float>(c->g, c->prim<float>(), c->flux<float>(), c->shock(),
+    launch_shock<float>(c->g, c->prim<float>(1), c->shock(), c->mlp_jump, c->st);
+    launch_mlp_samples<float>(c->g, c->prim<float>(1), c->flux<float>(), c->shock(),
                               (const float*)d_acc, dt_coarse, c->ph.gamma, n, d_faces, d_x, d_t,
                               d_mask, c->st);
   }

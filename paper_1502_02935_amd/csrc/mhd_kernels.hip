@@ -116,11 +116,18 @@ void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, hipStream_t st) {
 // E = -v x B (Eq. 9) on all cells that have both faces: [-NG, n+NG-1]^3.
 // FP32: cells that lose more than 6 bits in E - KE - ME (E/(E-KE-ME) > 64)
 // redo KE, ME and P in FP64 from the stored FP32 values.
+//
+// The primitives, the CT face update and the CFL candidates are computed in
+// more than one kernel (the primitive pass, the ghost-shell pass, the fused
+// stage update) and must agree bitwise there: their functions contract a*b+c
+// into an FMA only within one expression (fp contract(on)), so the result
+// does not depend on which subexpressions a kernel happens to share.
 // ------------------------------------------------------------------------
 
 template <class T>
 __device__ __forceinline__ T pressure(T gam, T rho, T mx, T my, T mz, T E, T b0x, T b1x, T b0y,
                                       T b1y, T b0z, T b1z, T& bcx, T& bcy, T& bcz, bool& rec) {
+#pragma clang fp contract(on)
   bcx = T(0.5) * (b0x + b1x);
   bcy = T(0.5) * (b0y + b1y);
   bcz = T(0.5) * (b0z + b1z);
@@ -171,6 +178,7 @@ template <class T>
 __device__ __forceinline__ double cfl_cell(const Geo& g, const Physics& ph, T rho_, T mx_, T my_,
                                            T mz_, T E_, T b0x, T b1x, T b0y, T b1y, T b0z, T b1z,
                                            unsigned* status) {
+#pragma clang fp contract(on)
   const double rho = rho_, mx = mx_, my = my_, mz = mz_, E = E_;
   const double bc[3] = {0.5 * ((double)b0x + (double)b1x), 0.5 * ((double)b0y + (double)b1y),
                         0.5 * ((double)b0z + (double)b1z)};
@@ -208,6 +216,31 @@ __device__ __forceinline__ void block_min_to(double r, double* part) {
   }
 }
 
+// Primitives and cell EMF of the cell at p from its conserved values and
+// its lower (b0*) and upper (b1*) faces.  One function for every pass that
+// writes primitives, so that they agree bitwise for the same inputs.
+template <class T>
+__device__ __forceinline__ void store_prim(T gam, const Prim<T>& w, int p, T rho, T mx, T my,
+                                           T mz, T E, T b0x, T b1x, T b0y, T b1y, T b0z, T b1z,
+                                           bool& rec) {
+#pragma clang fp contract(on)
+  T bcx, bcy, bcz;
+  const T P = pressure(gam, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, bcx, bcy, bcz, rec);
+  const T ir = rcp(rho);
+  const T vx = mx * ir, vy = my * ir, vz = mz * ir;
+  w.w[0][p] = rho;
+  w.w[1][p] = vx;
+  w.w[2][p] = vy;
+  w.w[3][p] = vz;
+  w.w[4][p] = P;
+  w.w[5][p] = bcx;
+  w.w[6][p] = bcy;
+  w.w[7][p] = bcz;
+  w.ec[0][p] = vz * bcy - vy * bcz;
+  w.ec[1][p] = vx * bcz - vz * bcx;
+  w.ec[2][p] = vy * bcx - vx * bcy;
+}
+
 // CFL = true: the interior cells also give their time-step candidates,
 // folded per block into part[] (the step's own dt, from the same loads).
 template <class T, bool CFL>
@@ -218,25 +251,10 @@ __global__ void __launch_bounds__(kSpanThreads) k_prim(Geo g, Physics ph, Span s
   double r = INFINITY;
   if (pt.valid) {
     const int p = pt.p;
-    const T gam = (T)ph.gamma;
     const T rho = s.u[0][p], mx = s.u[1][p], my = s.u[2][p], mz = s.u[3][p], E = s.u[4][p];
     const T b0x = s.b[0][p], b1x = s.b[0][p + 1], b0y = s.b[1][p], b1y = s.b[1][p + g.sy];
     const T b0z = s.b[2][p], b1z = s.b[2][p + g.sz];
-    T bcx, bcy, bcz;
-    const T P = pressure(gam, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, bcx, bcy, bcz, rec);
-    const T ir = rcp(rho);
-    const T vx = mx * ir, vy = my * ir, vz = mz * ir;
-    w.w[0][p] = rho;
-    w.w[1][p] = vx;
-    w.w[2][p] = vy;
-    w.w[3][p] = vz;
-    w.w[4][p] = P;
-    w.w[5][p] = bcx;
-    w.w[6][p] = bcy;
-    w.w[7][p] = bcz;
-    w.ec[0][p] = vz * bcy - vy * bcz;
-    w.ec[1][p] = vx * bcz - vz * bcx;
-    w.ec[2][p] = vy * bcx - vx * bcy;
+    store_prim((T)ph.gamma, w, p, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, rec);
     if constexpr (CFL) {
       if (pt.i >= 0 && pt.i < g.n[0] && pt.j >= 0 && pt.j < g.n[1] && pt.k >= 0 && pt.k < g.n[2])
         r = cfl_cell<T>(g, ph, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, cnt.status);
@@ -244,6 +262,71 @@ __global__ void __launch_bounds__(kSpanThreads) k_prim(Geo g, Physics ph, Span s
   }
   if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);
   if constexpr (CFL) block_min_to(r, part);
+}
+
+// Thread t -> cell c of the ghost shell, [-NG, n+NG-1]^3 without the
+// interior [0, n-1]^3: the 2 NG z-layers as whole planes, then the 2 NG
+// y-layers of the interior planes as whole rows, then the 2 NG x-cells at
+// the ends of each interior row; false past the last one.
+__device__ __forceinline__ bool shell_cell(const Geo& g, int t, int c[3]) {
+  const int w0 = g.n[0] + 2 * NG, w1 = g.n[1] + 2 * NG;
+  const int nzl = 2 * NG * w0 * w1, nyl = 2 * NG * w0 * g.n[2];
+  const int nxl = 2 * NG * g.n[1] * g.n[2];
+  int l;
+  if (t < nzl) {
+    l = t / (w0 * w1);
+    const int r = t - l * w0 * w1;
+    c[2] = l < NG ? l - NG : g.n[2] + (l - NG);
+    c[1] = r / w0 - NG;
+    c[0] = r % w0 - NG;
+  } else if (t < nzl + nyl) {
+    t -= nzl;
+    const int k = t / (2 * NG * w0);
+    const int r = t - k * (2 * NG * w0);
+    l = r / w0;
+    c[2] = k;
+    c[1] = l < NG ? l - NG : g.n[1] + (l - NG);
+    c[0] = r - l * w0 - NG;
+  } else if (t < nzl + nyl + nxl) {
+    t -= nzl + nyl;
+    l = t % (2 * NG);
+    const int r = t / (2 * NG);
+    c[2] = r / g.n[1];
+    c[1] = r - c[2] * g.n[1];
+    c[0] = l < NG ? l - NG : g.n[0] + (l - NG);
+  } else {
+    return false;
+  }
+  return true;
+}
+
+static int shell_cells(const Geo& g) {
+  const int w0 = g.n[0] + 2 * NG, w1 = g.n[1] + 2 * NG;
+  return 2 * NG * (w0 * w1 + w0 * g.n[2] + g.n[1] * g.n[2]);
+}
+
+// Primitives of the ghost shell (after the ghost fill; the interior cells'
+// come from the stage update).
+template <class T>
+__global__ void __launch_bounds__(256) k_prim_shell(Geo g, Physics ph, Cons<T> s, Prim<T> w,
+                                                    Counters cnt) {
+  int c[3];
+  bool rec = false;
+  if (shell_cell(g, (int)(blockIdx.x * 256u + threadIdx.x), c)) {
+    const int p = pidx(g, c[0], c[1], c[2]);
+    store_prim((T)ph.gamma, w, p, s.u[0][p], s.u[1][p], s.u[2][p], s.u[3][p], s.u[4][p],
+               s.b[0][p], s.b[0][p + 1], s.b[1][p], s.b[1][p + g.sy], s.b[2][p],
+               s.b[2][p + g.sz], rec);
+  }
+  if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);
+}
+
+template <class T>
+void launch_prim_shell(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
+                       hipStream_t st) {
+  const int n = shell_cells(g);
+  hipLaunchKernelGGL(k_prim_shell<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, ph,
+                     s, w, c);
 }
 
 static Span prim_span(const Geo& g) {
@@ -489,127 +572,150 @@ __device__ __forceinline__ void grad_phi(const Physics& ph, double x, double y, 
   }
 }
 
+// CT update of the A-face at index q: B_A - dt (dE_C/db - dE_B/dc) with
+// (A, B, C) cyclic, rb = dt/d_B, rc = dt/d_C.
+template <class T, int A>
+__device__ __forceinline__ T ct_face(const Geo& g, const Cons<T>& s0, const Edge<T>& e, int q,
+                                     T rb, T rc) {
+#pragma clang fp contract(on)
+  constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+  const T* Ec = e.e[C];
+  const T* Eb = e.e[B];
+  return s0.b[A][q] - rb * (Ec[q + stride_of(g, B)] - Ec[q]) +
+         rc * (Eb[q + stride_of(g, C)] - Eb[q]);
+}
+
+// One stage's update, fused with what follows it on every cell: the
+// density and pressure floors, then the primitive recovery of the updated
+// state into wo (and, CFL = true, the cell's FP64 time-step candidate for
+// the next step, folded per block into part[]).  The cell-centred B of the
+// updated faces needs the upper face of each axis, which another point
+// owns: it is recomputed here with the same arithmetic (ct_face), so it is
+// bitwise the value that point stores.  On a periodic axis (nf = n) the
+// last cell's upper face n is the ghost copy of face 0: its old value and
+// the EMFs of its edges (from fluxes whose stencils are ghost copies of
+// face 0's) equal face 0's, so the recomputed value is face 0's new value
+// and no wrap is needed.  s1's faces must not be s0's (the upper-face
+// recomputation reads s0's faces while other points write s1's); s1's
+// cells may be s0's.  w (the stage's primitives, read for the source) must
+// not be wo.
+//
 // Every load of a point is issued whether or not the point's cell or faces
 // are updated (the padded arrays hold every index the span reaches, and
 // values of points that are not updated are discarded): guarding the loads
-// per face family would split a wave's memory traffic into four dependent
-// round trips.
-template <class T>
+// per face family would split a wave's memory traffic into dependent round
+// trips.
+template <class T, bool CFL>
 __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span sp, Cons<T> s0,
-                                                         Cons<T> s1, Prim<T> w, Flux<T> f,
-                                                         Edge<T> e, Grav<T> gr, DtRef dtr) {
+                                                         Cons<T> s1, Prim<T> w, Prim<T> wo,
+                                                         Flux<T> f, Edge<T> e, Grav<T> gr,
+                                                         DtRef dtr, Counters cnt, double* part) {
   const Pt pt = span_point(g, sp);
-  if (!pt.valid) return;
-  const int i = pt.i, j = pt.j, k = pt.k;
-  const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
-  const int p = pt.p;
-  const int cc[3] = {i, j, k};
-  const int st[3] = {1, g.sy, g.sz};
-  T bnew[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int b = (a + 1) % 3, c = (a + 2) % 3;
-    const T rb = (T)(dt / g.d[b]), rc = (T)(dt / g.d[c]);
-    const T* Ec = e.e[c];
-    const T* Eb = e.e[b];
-    bnew[a] = s0.b[a][p] - rb * (Ec[p + st[b]] - Ec[p]) + rc * (Eb[p + st[c]] - Eb[p]);
-  }
-  T S[5] = {T(0), T(0), T(0), T(0), T(0)};
-  if (ph.source != 0) {
-    double gp[3];
-    if (ph.source == 4 && ph.src[1] == 1.0) {  // gas decoupled from gravity
-      gp[0] = gp[1] = gp[2] = 0.0;
-    } else if (ph.source == 4) {
-      gp[0] = gr.g[0][p];
-      gp[1] = gr.g[1][p];
-      gp[2] = gr.g[2][p];
-    } else {
-      grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
-               g.x0[2] + (k + 0.5) * g.d[2], gp);
-    }
-    const T rho = w.w[0][p];
-    const T gx = (T)gp[0], gy = (T)gp[1], gz = (T)gp[2];
-    S[1] = -rho * gx;
-    S[2] = -rho * gy;
-    S[3] = -rho * gz;
-    S[4] = -rho * (w.w[1][p] * gx + w.w[2][p] * gy + w.w[3][p] * gz);
-  }
-  const T rx = (T)(dt / g.d[0]), ry = (T)(dt / g.d[1]), rz = (T)(dt / g.d[2]);
-  const T dtT = (T)dt;
-  T u[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const T* fx = f.f[0][frame_comp(0, m)];
-    const T* fy = f.f[1][frame_comp(1, m)];
-    const T* fz = f.f[2][frame_comp(2, m)];
-    T v = s0.u[m][p];
-    v -= rx * (fx[p + 1] - fx[p]);
-    v -= ry * (fy[p + g.sy] - fy[p]);
-    v -= rz * (fz[p + g.sz] - fz[p]);
-    v += dtT * S[m];
-    u[m] = v;
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const int b = (a + 1) % 3, c = (a + 2) % 3;
-    if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) s1.b[a][p] = bnew[a];
-  }
-  if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) s1.u[m][p] = u[m];
-  }
-}
-
-// Density and pressure floors on the updated state: rho is raised to
-// rho_floor; then E is raised so that P >= p_floor, with the cell-centred B
-// of the updated faces.  A pass of its own, after every face of the stage
-// has been written.
-template <class T>
-__global__ void __launch_bounds__(kSpanThreads) k_floors(Geo g, Physics ph, Span sp, Cons<T> s,
-                                                         Counters cnt) {
-  const Pt pt = span_point(g, sp);
-  bool hit = false;
+  bool hit = false, rec = false;
+  double r = INFINITY;
   if (pt.valid) {
+    const int i = pt.i, j = pt.j, k = pt.k;
+    const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
     const int p = pt.p;
-    T rho = s.u[0][p];
-    if (rho < (T)ph.rho_floor) {
-      rho = (T)ph.rho_floor;
-      s.u[0][p] = rho;
-      hit = true;
+    const int cc[3] = {i, j, k};
+    const T rx = (T)(dt / g.d[0]), ry = (T)(dt / g.d[1]), rz = (T)(dt / g.d[2]);
+    const int up[3] = {p + 1, p + g.sy, p + g.sz};
+    const T bnew[3] = {ct_face<T, 0>(g, s0, e, p, ry, rz), ct_face<T, 1>(g, s0, e, p, rz, rx),
+                       ct_face<T, 2>(g, s0, e, p, rx, ry)};
+    const T bup[3] = {ct_face<T, 0>(g, s0, e, up[0], ry, rz),
+                      ct_face<T, 1>(g, s0, e, up[1], rz, rx),
+                      ct_face<T, 2>(g, s0, e, up[2], rx, ry)};
+    T S[5] = {T(0), T(0), T(0), T(0), T(0)};
+    if (ph.source != 0) {
+      double gp[3];
+      if (ph.source == 4 && ph.src[1] == 1.0) {  // gas decoupled from gravity
+        gp[0] = gp[1] = gp[2] = 0.0;
+      } else if (ph.source == 4) {
+        gp[0] = gr.g[0][p];
+        gp[1] = gr.g[1][p];
+        gp[2] = gr.g[2][p];
+      } else {
+        grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
+                 g.x0[2] + (k + 0.5) * g.d[2], gp);
+      }
+      const T rho = w.w[0][p];
+      const T gx = (T)gp[0], gy = (T)gp[1], gz = (T)gp[2];
+      S[1] = -rho * gx;
+      S[2] = -rho * gy;
+      S[3] = -rho * gz;
+      S[4] = -rho * (w.w[1][p] * gx + w.w[2][p] * gy + w.w[3][p] * gz);
     }
-    const T gam = (T)ph.gamma;
-    // Upper faces of the cell; on a periodic axis (nf = n) the last cell's
-    // upper face is the first face, whose ghost copy the next ghost fill
-    // writes.
-    const int cc[3] = {pt.i, pt.j, pt.k};
-    const int st[3] = {1, g.sy, g.sz};
-    int up[3];
+    const T dtT = (T)dt;
+    T u[5];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-      up[a] = (g.nf[a] == g.n[a] && cc[a] == g.n[a] - 1) ? p - (g.n[a] - 1) * st[a] : p + st[a];
-    T bcx, bcy, bcz;
-    bool rec;
-    const T E = s.u[4][p];
-    const T P = pressure(gam, rho, s.u[1][p], s.u[2][p], s.u[3][p], E, s.b[0][p], s.b[0][up[0]],
-                         s.b[1][p], s.b[1][up[1]], s.b[2][p], s.b[2][up[2]], bcx, bcy, bcz, rec);
-    if (P < (T)ph.p_floor) {
-      s.u[4][p] = E + ((T)ph.p_floor - P) / (gam - T(1));
-      hit = true;
+    for (int m = 0; m < 5; ++m) {
+      const T* fx = f.f[0][frame_comp(0, m)];
+      const T* fy = f.f[1][frame_comp(1, m)];
+      const T* fz = f.f[2][frame_comp(2, m)];
+      T v = s0.u[m][p];
+      v -= rx * (fx[p + 1] - fx[p]);
+      v -= ry * (fy[p + g.sy] - fy[p]);
+      v -= rz * (fz[p + g.sz] - fz[p]);
+      v += dtT * S[m];
+      u[m] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) s1.b[a][p] = bnew[a];
+    }
+    if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+      const T gam = (T)ph.gamma;
+      T rho = u[0], E = u[4];
+      if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
+        // floors: rho raised to rho_floor, then E so that P >= p_floor
+        if (rho < (T)ph.rho_floor) {
+          rho = (T)ph.rho_floor;
+          hit = true;
+        }
+        T bcx, bcy, bcz;
+        bool rq;
+        const T P = pressure(gam, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
+                             bnew[2], bup[2], bcx, bcy, bcz, rq);
+        if (P < (T)ph.p_floor) {
+          E = E + ((T)ph.p_floor - P) / (gam - T(1));
+          hit = true;
+        }
+      }
+      s1.u[0][p] = rho;
+      s1.u[1][p] = u[1];
+      s1.u[2][p] = u[2];
+      s1.u[3][p] = u[3];
+      s1.u[4][p] = E;
+      store_prim(gam, wo, p, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1], bnew[2],
+                 bup[2], rec);
+      if constexpr (CFL)
+        r = cfl_cell<T>(g, ph, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
+                        bnew[2], bup[2], cnt.status);
     }
   }
   wave_count(hit, cnt.floor_hits);
+  if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);
+  if constexpr (CFL) block_min_to(r, part);
 }
+
+static Span update_span(const Geo& g) {
+  return make_span(g, 0, g.n[0], 0, g.n[1], 0, g.n[2]);
+}
+
+int update_cfl_blocks(const Geo& g) { return update_span(g).nblk; }
 
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
-                   Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c, hipStream_t st) {
-  const Span sp = make_span(g, 0, g.n[0], 0, g.n[1], 0, g.n[2]);
-  hipLaunchKernelGGL(k_update<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s0, s1, w,
-                     f, e, gr, dt);
-  if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
-    const Span si = make_span(g, 0, g.n[0] - 1, 0, g.n[1] - 1, 0, g.n[2] - 1);
-    hipLaunchKernelGGL(k_floors<T>, span_grid(si), dim3(kSpanThreads), 0, st, g, ph, si, s1, c);
-  }
+                   Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
+                   double* cfl_part, hipStream_t st) {
+  const Span sp = update_span(g);
+  if (cfl_part)
+    hipLaunchKernelGGL((k_update<T, true>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp,
+                       s0, s1, w, wo, f, e, gr, dt, c, cfl_part);
+  else
+    hipLaunchKernelGGL((k_update<T, false>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp,
+                       s0, s1, w, wo, f, e, gr, dt, c, nullptr);
 }
 
 // ------------------------------------------------------------------------
@@ -660,38 +766,41 @@ static Span cfl_span(const Geo& g) {
 }
 
 int cfl_blocks(const Geo& g) {
-  const int nb = cfl_span(g).nblk, np = prim_span(g).nblk;
-  return (nb > np ? nb : np) + kPartCflBlocks + kCflReduce;
+  int nb = cfl_span(g).nblk;
+  nb = nb > prim_span(g).nblk ? nb : prim_span(g).nblk;
+  nb = nb > update_span(g).nblk ? nb : update_span(g).nblk;
+  return nb + kPartCflBlocks + kCflReduce;
+}
+
+// dt_out = cfl x the minimum of the nb cell partials in part[] and (if
+// pp.n) the particles' partials, which are written after them.
+template <class T>
+void launch_cfl_reduce(const Geo& g, const Physics& ph, double* part, int nb, double* dt_out,
+                       Parts<T> pp, hipStream_t st) {
+  static_assert(kCflReduce == 64, "k_cfl_final folds one wave");
+  if (pp.n > 0) {
+    launch_particle_cfl<T>(g, pp, part + nb, st);
+    nb += kPartCflBlocks;
+  }
+  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, nb, part + nb);
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + nb, ph.cfl, dt_out);
 }
 
 template <class T>
 void launch_prim_cfl(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, double* part,
                      double* dt_out, Counters c, Parts<T> pp, hipStream_t st) {
   const Span sp = prim_span(g);
-  int nb = sp.nblk;
-  if (pp.n > 0) {  // the particles' partials follow the cells'
-    launch_particle_cfl<T>(g, pp, part + nb, st);
-    nb += kPartCflBlocks;
-  }
   hipLaunchKernelGGL((k_prim<T, true>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s, w,
                      c, part);
-  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, nb, part + nb);
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + nb, ph.cfl, dt_out);
+  launch_cfl_reduce<T>(g, ph, part, sp.nblk, dt_out, pp, st);
 }
 
 template <class T>
 void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
                 Counters c, Parts<T> pp, hipStream_t st) {
-  static_assert(kCflReduce == 64, "k_cfl_final folds one wave");
   const Span sp = cfl_span(g);
-  int nb = sp.nblk;
-  if (pp.n > 0) {
-    launch_particle_cfl<T>(g, pp, part + nb, st);
-    nb += kPartCflBlocks;
-  }
   hipLaunchKernelGGL(k_cfl<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp, s, part, c);
-  hipLaunchKernelGGL(k_cfl_reduce, dim3(kCflReduce), dim3(256), 0, st, part, nb, part + nb);
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, st, part + nb, ph.cfl, dt_out);
+  launch_cfl_reduce<T>(g, ph, part, sp.nblk, dt_out, pp, st);
 }
 
 __global__ void k_advance_time(double* t, long long* step, DtRef dtr) {
@@ -1075,8 +1184,13 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_flux_mlp<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>,        \
                                    Muscl<T>, Counters, MlpRef, hipStream_t);                     \
   template void launch_shock<T>(const Geo&, Prim<T>, uint8_t*, double, hipStream_t);           \
-  template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Flux<T>, \
-                                 Edge<T>, Grav<T>, DtRef, Counters, hipStream_t);                \
+  template void launch_prim_shell<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,     \
+                                     hipStream_t);                                               \
+  template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Prim<T>, \
+                                 Flux<T>, Edge<T>, Grav<T>, DtRef, Counters, double*,            \
+                                 hipStream_t);                                                   \
+  template void launch_cfl_reduce<T>(const Geo&, const Physics&, double*, int, double*, Parts<T>, \
+                                     hipStream_t);                                               \
   template void launch_cfl<T>(const Geo&, const Physics&, Cons<T>, double*, double*, Counters,   \
                               Parts<T>, hipStream_t);                                            \
   template void launch_diag<T>(const Geo&, const Physics&, Cons<T>, double*, double*,           \

@@ -181,9 +181,21 @@ template <class T>
 void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, hipStream_t st);
 template <class T>
 void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
+// One stage's update of s0 into s1 (s1's faces must be other arrays than
+// s0's; its cells may be s0's) with the floors and the primitives of the
+// updated interior cells into wo (w: the stage's primitives, for the
+// source; wo must be other arrays).  cfl_part != nullptr: the cells' FP64
+// time-step candidates as update_cfl_blocks(g) per-block minima.
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
-                   Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c, hipStream_t st);
+                   Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
+                   double* cfl_part, hipStream_t st);
+int update_cfl_blocks(const Geo& g);
+// Primitives of the ghost shell [-NG, n+NG-1]^3 minus the interior (after
+// the ghost fill).
+template <class T>
+void launch_prim_shell(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
+                       hipStream_t st);
 // Passive scalars of one stage: x1 = x0 - dt div F_X, with F_X the mass flux
 // of f times X = xs / rho (rho: the stage's primitive density) reconstructed
 // by m on the upwind side; interior cells.  x1 may be x0.
@@ -207,6 +219,10 @@ int cfl_blocks(const Geo& g);
 template <class T>
 void launch_cfl(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* dt_out,
                 Counters c, Parts<T> pp, hipStream_t st);
+// dt_out from nb cell partials already in part (and the particles').
+template <class T>
+void launch_cfl_reduce(const Geo& g, const Physics& ph, double* part, int nb, double* dt_out,
+                       Parts<T> pp, hipStream_t st);
 // Particles (mhd_nbody.hip).  Per-block minima over the particles of
 // d_a / |v_a| into part[0 .. kPartCflBlocks).
 template <class T>

@@ -82,6 +82,7 @@ __device__ __forceinline__ void muscl_lr(const Muscl<T>& m, T w0, T w1, T w2, T 
 // (a^2 - b^2)^2 + 4 a^2 bt^2 so it never goes negative by cancellation.
 template <class T>
 __device__ __forceinline__ T fast_speed(T d, T p, T bn, T bt1, T bt2, T gam) {
+#pragma clang fp contract(on)
   const T id = rcp(d);
   const T a2 = gam * p * id;
   const T bt2s = (bt1 * bt1 + bt2 * bt2) * id;
