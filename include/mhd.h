@@ -220,6 +220,15 @@ int mhd_get_scalars(mhd_ctx *ctx, void *d_rho_x);
 int mhd_set_particles(mhd_ctx *ctx, const void *d_x, const void *d_v, const void *d_m);
 int mhd_get_particles(mhd_ctx *ctx, void *d_x, void *d_v);
 
+/* enable != 0: the steps from now on keep every component of every face's
+   flux of each stage in the workspace, as mhd_mlp_samples and the flux
+   entries of mhd_debug_array read them (the learned correction's sampling,
+   checks); enable == 0 (the default): the fused flux sweep keeps only what
+   the EMFs, passive scalars and tile seams need, and those entries read
+   stale values.  Takes effect at the next mhd_step.  Steps with a learned
+   correction or a flux accumulator keep every flux either way. */
+int mhd_set_full_fluxes(mhd_ctx *ctx, int enable);
+
 /* Copies one internal padded array of the last corrector stage to d_out
    (element type of the context precision, [nz+5][ny+5][nx+5], x fastest,
    interior cell (i,j,k) at ((k+2)(ny+5) + j+2)(nx+5) + i+2):
@@ -312,7 +321,8 @@ int mhd_flux_accumulate(mhd_ctx *ctx, void *d_acc);
    mhd_flux_accumulate.  Synchronises. */
 int mhd_coarsen(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_bz);
 
-/* Training samples from the last step of a (coarse) context:
+/* Training samples from the last step of a (coarse) context, which must
+   have been taken with mhd_set_full_fluxes on:
    for n faces d_faces [n][4] = (axis, i, j, k) with 0 <= i,j,k < n_axis,
    d_x [n][32] = features of the corrector state, d_t [n][8] = the MLP
    output that would turn its corrector flux into d_acc/dt_coarse (d_acc

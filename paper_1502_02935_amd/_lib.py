@@ -127,6 +127,8 @@ def load() -> C.CDLL:
     L.mhd_flux_accumulate.argtypes = [vp, vp]
     L.mhd_coarsen.restype = C.c_int
     L.mhd_coarsen.argtypes = [vp, vp, vp, vp, vp]
+    L.mhd_set_full_fluxes.restype = C.c_int
+    L.mhd_set_full_fluxes.argtypes = [vp, C.c_int]
     L.mhd_mlp_samples.restype = C.c_int
     L.mhd_mlp_samples.argtypes = [vp, vp, C.c_double, i64, vp, vp, vp, vp]
     L.mhd_mlp_forward.restype = C.c_int

@@ -243,6 +243,8 @@ struct mhd_ctx {
   // shell), as the last step left them; cfl_valid: cfl_part() holds that
   // step's update_cfl_blocks() partials of U's time-step candidates.
   bool w_valid = false, cfl_valid = false;
+  // keep every component of every face's flux in memory (mhd_set_full_fluxes)
+  bool full_fluxes = false;
   template <class T>
   Cons<T> cons(int set) const {  // set 0: U (t^n), 1: U* (half step)
     Cons<T> s;
@@ -459,16 +461,23 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     c->mark(MHD_K_GRAVITY);
     launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_n, c->st);
   }
+  // the fused flux sweep unless the learned correction or the flux
+  // accumulation needs every face's full flux in memory
+  const bool swept = !c->mlp_params && !c->flux_acc;
+  const int store = c->full_fluxes ? 2 : (ns > 0 ? 1 : 0);
+  DtRef half = dt;
+  half.factor = 0.5;
   // predictor: first-order fluxes of U^n, half step into U* and its
   // primitives
   c->mark(MHD_K_FLUX);
-  launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
+  if (swept)
+    launch_sweep<T>(g, c->ph, W, U, Us, F, first, c->grav<T>(), half, cnt, store, c->st);
+  else
+    launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, W, F, E, c->st);
-  DtRef half = dt;
-  half.factor = 0.5;
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, Us, W, Ws, F, E, c->grav<T>(), half, cnt, nullptr, c->st);
+  launch_update<T>(g, c->ph, U, Us, W, Ws, F, E, c->grav<T>(), half, cnt, nullptr, swept, c->st);
   if (ns) {
     c->mark(MHD_K_SCALARS);
     launch_scalar_update<T>(g, W.w[0], F, Xn, Xn, Xh, ns, first, half, c->st);
@@ -494,6 +503,9 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
       c->mark(MHD_K_FLUX_MLP);
       launch_flux_mlp<T>(g, c->ph, a, Ws, Us.b[a], F, second, cnt, c->mlp_ref(), c->st);
     }
+  } else if (swept) {
+    c->mark(MHD_K_FLUX);
+    launch_sweep<T>(g, c->ph, Ws, Un, Un, F, second, c->grav<T>(), dt, cnt, store, c->st);
   } else {
     c->mark(MHD_K_FLUX);
     launch_flux<T>(g, c->ph, Ws, Us, F, second, cnt, c->st);
@@ -505,7 +517,8 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, Ws, F, E, c->st);
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, Un, Ws, W, F, E, c->grav<T>(), dt, cnt, c->cfl_part(), c->st);
+  launch_update<T>(g, c->ph, U, Un, Ws, W, F, E, c->grav<T>(), dt, cnt, c->cfl_part(), swept,
+                   c->st);
   if (ns) {
     c->mark(MHD_K_SCALARS);
     launch_scalar_update<T>(g, Ws.w[0], F, Xn, Xh, Xn, ns, second, dt, c->st);
@@ -906,6 +919,12 @@ int mhd_coarsen(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz) {
                           (float*)d_bz, c->st);
   if (hip_status() != MHD_OK) return MHD_E_HIP;
   return hipStreamSynchronize(c->st) == hipSuccess ? MHD_OK : MHD_E_HIP;
+}
+
+int mhd_set_full_fluxes(mhd_ctx* c, int enable) {
+  if (!c) return MHD_E_ARG;
+  c->full_fluxes = enable != 0;
+  return MHD_OK;
 }
 
 int mhd_mlp_samples(mhd_ctx* c, const void* d_acc, double dt_coarse, int64_t n,

@@ -8,6 +8,7 @@
 
 #include "mhd_kernels.hpp"
 #include "mhd_mlp.hpp"
+#include "mhd_source.hpp"
 #include "mhd_span.hpp"
 
 namespace mhd {
@@ -553,25 +554,6 @@ void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st) {
 // update (Eq. 8: dB_a/dt = -(dE_c/db - dE_b/dc), (a,b,c) cyclic).
 // ------------------------------------------------------------------------
 
-__device__ __forceinline__ void grad_phi(const Physics& ph, double x, double y, double z,
-                                         double gp[3]) {
-  gp[0] = gp[1] = gp[2] = 0.0;
-  if (ph.source == 1) {
-    const double v0 = ph.src[0], rc = ph.src[1], q = ph.src[2];
-    const double den = rc * rc + x * x + y * y + z * z / (q * q);
-    gp[0] = v0 * v0 * x / den;
-    gp[1] = v0 * v0 * y / den;
-    gp[2] = v0 * v0 * (z / (q * q)) / den;
-  } else if (ph.source == 2) {
-    gp[0] = ph.src[0];
-    gp[1] = ph.src[1];
-    gp[2] = ph.src[2];
-  } else if (ph.source == 3) {
-    const double A = ph.src[0], wd = ph.src[1];
-    gp[0] = 2.0 * A * x / (wd * wd) * exp(-(x / wd) * (x / wd));
-  }
-}
-
 // CT update of the A-face at index q: B_A - dt (dE_C/db - dE_B/dc) with
 // (A, B, C) cyclic, rb = dt/d_B, rc = dt/d_C.
 template <class T, int A>
@@ -605,7 +587,7 @@ __device__ __forceinline__ T ct_face(const Geo& g, const Cons<T>& s0, const Edge
 // values of points that are not updated are discarded): guarding the loads
 // per face family would split a wave's memory traffic into dependent round
 // trips.
-template <class T, bool CFL>
+template <class T, bool CFL, bool SWEPT>
 __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span sp, Cons<T> s0,
                                                          Cons<T> s1, Prim<T> w, Prim<T> wo,
                                                          Flux<T> f, Edge<T> e, Grav<T> gr,
@@ -625,39 +607,42 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
     const T bup[3] = {ct_face<T, 0>(g, s0, e, up[0], ry, rz),
                       ct_face<T, 1>(g, s0, e, up[1], rz, rx),
                       ct_face<T, 2>(g, s0, e, up[2], rx, ry)};
-    T S[5] = {T(0), T(0), T(0), T(0), T(0)};
-    if (ph.source != 0) {
-      double gp[3];
-      if (ph.source == 4 && ph.src[1] == 1.0) {  // gas decoupled from gravity
-        gp[0] = gp[1] = gp[2] = 0.0;
-      } else if (ph.source == 4) {
-        gp[0] = gr.g[0][p];
-        gp[1] = gr.g[1][p];
-        gp[2] = gr.g[2][p];
-      } else {
-        grad_phi(ph, g.x0[0] + (i + 0.5) * g.d[0], g.x0[1] + (j + 0.5) * g.d[1],
-                 g.x0[2] + (k + 0.5) * g.d[2], gp);
-      }
-      const T rho = w.w[0][p];
-      const T gx = (T)gp[0], gy = (T)gp[1], gz = (T)gp[2];
-      S[1] = -rho * gx;
-      S[2] = -rho * gy;
-      S[3] = -rho * gz;
-      S[4] = -rho * (w.w[1][p] * gx + w.w[2][p] * gy + w.w[3][p] * gz);
-    }
-    const T dtT = (T)dt;
     T u[5];
+    if constexpr (SWEPT) {
+      // the sweep left the update of every cell, without the fluxes of the
+      // upper faces on its tile seams (last column, row or plane of a tile)
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const T* fx = f.f[0][frame_comp(0, m)];
-      const T* fy = f.f[1][frame_comp(1, m)];
-      const T* fz = f.f[2][frame_comp(2, m)];
-      T v = s0.u[m][p];
-      v -= rx * (fx[p + 1] - fx[p]);
-      v -= ry * (fy[p + g.sy] - fy[p]);
-      v -= rz * (fz[p + g.sz] - fz[p]);
-      v += dtT * S[m];
-      u[m] = v;
+      for (int m = 0; m < 5; ++m) u[m] = s1.u[m][p];
+      if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+        if (i % kSwX == kSwX - 1 || i == g.n[0] - 1) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) u[m] -= rx * f.f[0][frame_comp(0, m)][p + 1];
+        }
+        if (j % kSwY == kSwY - 1 || j == g.n[1] - 1) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) u[m] -= ry * f.f[1][frame_comp(1, m)][p + g.sy];
+        }
+        if (k % kSwZ == kSwZ - 1 || k == g.n[2] - 1) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) u[m] -= rz * f.f[2][frame_comp(2, m)][p + g.sz];
+        }
+      }
+    } else {
+      T S[5];
+      cell_source<T>(g, ph, gr, i, j, k, p, w.w[0][p], w.w[1][p], w.w[2][p], w.w[3][p], S);
+      const T dtT = (T)dt;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const T* fx = f.f[0][frame_comp(0, m)];
+        const T* fy = f.f[1][frame_comp(1, m)];
+        const T* fz = f.f[2][frame_comp(2, m)];
+        T v = s0.u[m][p];
+        v -= rx * (fx[p + 1] - fx[p]);
+        v -= ry * (fy[p + g.sy] - fy[p]);
+        v -= rz * (fz[p + g.sz] - fz[p]);
+        v += dtT * S[m];
+        u[m] = v;
+      }
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -705,17 +690,27 @@ static Span update_span(const Geo& g) {
 
 int update_cfl_blocks(const Geo& g) { return update_span(g).nblk; }
 
+template <class T, bool SWEPT>
+static void launch_update_sw(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
+                             Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
+                             double* cfl_part, hipStream_t st) {
+  const Span sp = update_span(g);
+  if (cfl_part)
+    hipLaunchKernelGGL((k_update<T, true, SWEPT>), span_grid(sp), dim3(kSpanThreads), 0, st, g,
+                       ph, sp, s0, s1, w, wo, f, e, gr, dt, c, cfl_part);
+  else
+    hipLaunchKernelGGL((k_update<T, false, SWEPT>), span_grid(sp), dim3(kSpanThreads), 0, st, g,
+                       ph, sp, s0, s1, w, wo, f, e, gr, dt, c, nullptr);
+}
+
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
-                   double* cfl_part, hipStream_t st) {
-  const Span sp = update_span(g);
-  if (cfl_part)
-    hipLaunchKernelGGL((k_update<T, true>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp,
-                       s0, s1, w, wo, f, e, gr, dt, c, cfl_part);
+                   double* cfl_part, bool swept, hipStream_t st) {
+  if (swept)
+    launch_update_sw<T, true>(g, ph, s0, s1, w, wo, f, e, gr, dt, c, cfl_part, st);
   else
-    hipLaunchKernelGGL((k_update<T, false>), span_grid(sp), dim3(kSpanThreads), 0, st, g, ph, sp,
-                       s0, s1, w, wo, f, e, gr, dt, c, nullptr);
+    launch_update_sw<T, false>(g, ph, s0, s1, w, wo, f, e, gr, dt, c, cfl_part, st);
 }
 
 // ------------------------------------------------------------------------
@@ -1187,7 +1182,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_prim_shell<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,     \
                                      hipStream_t);                                               \
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Prim<T>, \
-                                 Flux<T>, Edge<T>, Grav<T>, DtRef, Counters, double*,            \
+                                 Flux<T>, Edge<T>, Grav<T>, DtRef, Counters, double*, bool,      \
                                  hipStream_t);                                                   \
   template void launch_cfl_reduce<T>(const Geo&, const Physics&, double*, int, double*, Parts<T>, \
                                      hipStream_t);                                               \

@@ -185,11 +185,29 @@ void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
 // s0's; its cells may be s0's) with the floors and the primitives of the
 // updated interior cells into wo (w: the stage's primitives, for the
 // source; wo must be other arrays).  cfl_part != nullptr: the cells' FP64
-// time-step candidates as update_cfl_blocks(g) per-block minima.
+// time-step candidates as update_cfl_blocks(g) per-block minima.  swept:
+// s1's cells already hold the update of launch_sweep (seam fluxes still to
+// add) instead of f holding every face's flux.
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
-                   double* cfl_part, hipStream_t st);
+                   double* cfl_part, bool swept, hipStream_t st);
+// Tiles of the fused flux sweep: kSwX x kSwY cells a block (one wave per
+// x-row), walking kSwZ planes in z.
+constexpr int kSwX = 64, kSwY = 4, kSwZ = 16;
+// Fused flux sweep and conservative update of one stage (mhd_flux.hip):
+// the fluxes of every face of the interior cells with the Riemann solver
+// of ph and the reconstruction of m; into s1's cells the update of s0's
+// cells with those fluxes and dt S, except the fluxes of the upper faces of
+// tile seams, which go to f for launch_update(swept); the field
+// components of the fluxes and the mass-flux signs of every face to f for
+// the EMFs; store 1: also the mass fluxes (passive scalars), 2: every
+// component.  The faces of the outer layer of the flux range [-1, n]^3 are
+// computed by a second, small kernel into f.  s1's cells may be s0's.
+template <class T>
+void launch_sweep(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s0, Cons<T> s1,
+                  Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c, int store,
+                  hipStream_t st);
 int update_cfl_blocks(const Geo& g);
 // Primitives of the ghost shell [-NG, n+NG-1]^3 minus the interior (after
 // the ghost fill).

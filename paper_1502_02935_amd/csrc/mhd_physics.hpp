@@ -11,7 +11,11 @@
 //
 // Divisions are grouped so that each denominator is inverted once.  In FP32
 // the reciprocal and the square root are the hardware v_rcp_f32 and
-// v_sqrt_f32 (1 ulp each); in FP64 both are correctly rounded.
+// v_sqrt_f32 (1 ulp each); in FP64 both are correctly rounded.  a*b+c is
+// contracted to an FMA only within one expression (fp contract(on)), so a
+// face gives bitwise the same flux in every kernel that computes it (the
+// faces at index n of a periodic axis, computed by the outer-layer pass,
+// must equal the faces at 0 from the sweep).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -66,6 +70,7 @@ struct Muscl {
 template <class T>
 __device__ __forceinline__ void muscl_lr(const Muscl<T>& m, T w0, T w1, T w2, T w3, T& wl,
                                          T& wr) {
+#pragma clang fp contract(on)
   if (m.first_order) {
     wl = w1;
     wr = w2;
@@ -95,6 +100,7 @@ __device__ __forceinline__ T fast_speed(T d, T p, T bn, T bt1, T bt2, T gam) {
 // 1/(gamma - 1).
 template <class T>
 __device__ __forceinline__ void cons_flux(const Face<T>& s, T bn, T igm1, T u[7], T f[7]) {
+#pragma clang fp contract(on)
   const T v2 = s.vn * s.vn + s.vt1 * s.vt1 + s.vt2 * s.vt2;
   const T b2 = bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2;
   const T pt = s.p + T(0.5) * b2;
@@ -124,6 +130,7 @@ struct Star {
 template <class T>
 __device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T SM, T pts,
                                              int& degenerate) {
+#pragma clang fp contract(on)
   Star<T> r;
   const T sv = S - s.vn;
   const T ism = rcp(S - SM);
@@ -157,6 +164,7 @@ __device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T
 template <class T>
 __device__ __forceinline__ int hll(const Face<T>& L, const Face<T>& R, T bn, T gam, T igm1,
                                    T f[7]) {
+#pragma clang fp contract(on)
   T ul[7], fl[7], ur[7], fr[7];
   cons_flux(L, bn, igm1, ul, fl);
   cons_flux(R, bn, igm1, ur, fr);
@@ -185,6 +193,7 @@ __device__ __forceinline__ int hll(const Face<T>& L, const Face<T>& R, T bn, T g
 // conditions, star states of equal pressure and normal velocity.
 template <class T>
 __device__ __forceinline__ int hllc(const Face<T>& L0, const Face<T>& R0, T gam, T igm1, T f[7]) {
+#pragma clang fp contract(on)
   const Face<T> L{L0.d, L0.vn, L0.vt1, L0.vt2, L0.p, T(0), T(0)};
   const Face<T> R{R0.d, R0.vn, R0.vt1, R0.vt2, R0.p, T(0), T(0)};
   T ul[7], fl[7], ur[7], fr[7];
@@ -226,6 +235,7 @@ __device__ __forceinline__ int hllc(const Face<T>& L0, const Face<T>& R0, T gam,
 template <class T>
 __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T gam, T igm1,
                                     T f[7]) {
+#pragma clang fp contract(on)
   T ul[7], fl[7], ur[7], fr[7];
   cons_flux(L, bn, igm1, ul, fl);
   cons_flux(R, bn, igm1, ur, fr);

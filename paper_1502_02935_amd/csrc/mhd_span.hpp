@@ -128,6 +128,17 @@ __device__ __forceinline__ void wave_count(bool flag, unsigned long long* ctr) {
   }
 }
 
+// Add every lane's n into the counter's slot of this block, with one
+// atomic per wave.  Must be reached by every lane of the wave.
+__device__ __forceinline__ void wave_add(int n, unsigned long long* ctr) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+  if (n != 0 && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(1)) - 1)) {
+    const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    atomicAdd(ctr + (size_t)(b % kCounterSlots) * kCounterStride, (unsigned long long)n);
+  }
+}
+
 // Buffer access with a 32-bit byte offset (one per stencil point, shared by
 // all arrays; no 64-bit address arithmetic per access); each resource is
 // bounded by its array's size, so an offset outside it reads 0.
@@ -145,6 +156,36 @@ __device__ __forceinline__ void bst(float v, __amdgpu_buffer_rsrc_t r, unsigned 
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// Runs of consecutive elements at a 4-byte-aligned byte offset in one
+// wide load: 2 floats / 4 floats / 2 doubles (the vector memory unit takes
+// about as long per instruction for 4 bytes a lane as for 16).  Elements
+// are copied out of the vector before the bit cast: a bit cast of a vector
+// element expression reads element 0.
+__device__ __forceinline__ void bld2(float* v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  const unsigned e0 = q[0], e1 = q[1];
+  v[0] = __builtin_bit_cast(float, e0);
+  v[1] = __builtin_bit_cast(float, e1);
+}
+__device__ __forceinline__ void bld4(float* v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  const unsigned e0 = q[0], e1 = q[1], e2 = q[2], e3 = q[3];
+  v[0] = __builtin_bit_cast(float, e0);
+  v[1] = __builtin_bit_cast(float, e1);
+  v[2] = __builtin_bit_cast(float, e2);
+  v[3] = __builtin_bit_cast(float, e3);
+}
+__device__ __forceinline__ void bld2(double* v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  const u32x2 lo = {q[0], q[1]}, hi = {q[2], q[3]};
+  v[0] = __builtin_bit_cast(double, lo);
+  v[1] = __builtin_bit_cast(double, hi);
+}
+__device__ __forceinline__ void bld4(double* v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  bld2(v, r, off);
+  bld2(v + 2, r, off + 16);
+}
 __device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }

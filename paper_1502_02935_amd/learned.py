@@ -66,6 +66,7 @@ def generate(problem, pairs: int, faces_per_pair: int, seed: int = 0, precision=
         fine.step(1, dt=dt2)
         fine.flux_accumulator(False)
         coarse = Sim(ccfg, *cstate, device=device)
+        coarse.set_full_fluxes(True)
         coarse.step(1, dt=dt1 + dt2)
         faces = random_faces(ccfg, faces_per_pair, gen, device)
         x, t, m = coarse.mlp_samples(acc, dt1 + dt2, faces)

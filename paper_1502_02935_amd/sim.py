@@ -207,9 +207,14 @@ class Sim:
                 "mhd_coarsen")
         return c5, b[0], b[1], b[2]
 
+    def set_full_fluxes(self, enable: bool = True):
+        """Keep every face's full flux of each stage in memory from the next
+        step on (for mlp_samples and the flux entries of debug_array)."""
+        L.check(self.L.mhd_set_full_fluxes(self.ctx, 1 if enable else 0), "mhd_set_full_fluxes")
+
     def mlp_samples(self, acc: torch.Tensor, dt_coarse: float, faces: torch.Tensor):
         """Features, targets and masks of faces [n][4] (axis, i, j, k) from
-        this context's last step."""
+        this context's last step (taken with set_full_fluxes on)."""
         n = faces.shape[0]
         assert faces.dtype == torch.int32 and faces.is_contiguous() and faces.shape == (n, 4)
         assert acc.dtype == self.cfg.dtype and acc.is_contiguous()

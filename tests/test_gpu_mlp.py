@@ -164,6 +164,7 @@ def test_samples_match_oracle_features_and_targets(bc):
     pb = P.random_smooth((16, 12, 10), seed=11, bc=bc)
     o = oracle_of(pb)
     s = gpu_sim(pb)
+    s.set_full_fluxes(True)
     dt = o.dt()
     o.step(dt)
     s.step(1, dt=dt)
