@@ -106,31 +106,32 @@ def error_run(pb, nsteps):
                  "fp64_recovery_cell_evals": d32["n_fp64_recovery"]}
 
 
-# Algorithmic work of one launch of the flux kernel (all three face
-# families).  Points per launch: (n+2)^3 (cells -1..n on each axis); faces:
-# n+1 along each family's normal, n+2 across (one ghost row each side for
-# the corner EMFs), three families.  Bytes: the 8 primitive arrays read once
-# per point; per face the face-normal B read, 7 flux components and the
-# mass-flux sign byte written.  Flops per face, counted on the FP64 oracle
-# over the turbulent-box face states (oracle/count_flops.py): HLLD 400.6,
-# MUSCL of 7 variables 154.0.
-FLUX_BYTES_PER_POINT_FP32 = 8 * 4
-FLUX_BYTES_PER_FACE_FP32 = 4 + 7 * 4 + 1
+# Algorithmic work of one launch of the fused flux sweep (the dominant
+# kernel: fluxes of the three lower faces of every interior cell and the
+# stage's conservative update).  Bytes per cell, FP32: read the 8 primitive
+# arrays, the 3 face-normal B and the 5 conserved cell values once (64 B);
+# write the 5 updated cell values, the 6 field components of the 3 fluxes
+# and the 3 mass-flux sign bytes (47 B), and the 5 hydrodynamic components
+# of the faces on tile seams, which the stage update adds (1/64 of the x,
+# 1/4 of the y and 1/16 of the z faces: 6.56 B).  Flops per face, counted on
+# the FP64 oracle over the turbulent-box face states (oracle/count_flops.py):
+# HLLD 400.6, MUSCL of 7 variables 154.0; the update adds 30 per cell.
+SWEEP_BYTES_PER_CELL_FP32 = 8 * 4 + 3 * 4 + 5 * 4 + 5 * 4 + 6 * 4 + 3 + 5 * 4 * (1 / 64 + 1 / 4 + 1 / 16)
 HLLD_FLOPS_PER_FACE = 400.6
 MUSCL_FLOPS_PER_FACE = 154.0
+UPDATE_FLOPS_PER_CELL = 30.0
 # Whole step per cell-update (both stages, every part), same count.
 STEP_FLOPS_PER_CELL_UPDATE = 3162.0
 STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
-# Measured HBM traffic of one flux-kernel launch at n = 256 (2 x TCC
-# FETCH_SIZE + WRITE_SIZE: a plain 1 GiB copy reads as 512 MiB of
-# FETCH_SIZE and 1 GiB of WRITE_SIZE), valid only for the kernel sources
-# with this hash.
-PROFILED_FLUX = {"sources_sha256_16": "7056ce5c3cdc88d9", "n": 256,
-                 "bytes_per_launch": 2.335e9}
-# The sources that define the flux kernel's code (sweep, geometry, solver).
+# Measured HBM traffic of one sweep launch at n = 256 (2 x TCC FETCH_SIZE +
+# WRITE_SIZE: a plain 1 GiB copy reads as 512 MiB of FETCH_SIZE and 1 GiB of
+# WRITE_SIZE), valid only for the kernel sources with this hash.
+PROFILED_SWEEP = {"sources_sha256_16": None, "n": 256, "bytes_per_launch": None}
+# The sources that define the sweep's code (kernel, geometry, solver, source).
 KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_flux.hip",
                   "paper_1502_02935_amd/csrc/mhd_span.hpp",
-                  "paper_1502_02935_amd/csrc/mhd_physics.hpp")
+                  "paper_1502_02935_amd/csrc/mhd_physics.hpp",
+                  "paper_1502_02935_amd/csrc/mhd_source.hpp")
 
 
 def kernel_sources_hash():
@@ -142,23 +143,24 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def flux_roofline(n, prof):
-    """Roofline of the flux kernel (the dominant kernel): its mean launch time
-    from HIP events over the timed region, algorithmic bytes and flops per
-    launch.  Arithmetic intensity about 9.1 (first order) to 12.6 (MUSCL)
-    flop/byte, below the FP32 ridge of 157.3/8 = 19.7: HBM bound by the
-    published peaks."""
+def sweep_roofline(n, prof):
+    """Roofline of the fused flux sweep (the dominant kernel): its mean
+    launch time from HIP events over the timed region, algorithmic bytes and
+    flops per launch.  Arithmetic intensity about 10.5 (first order) to 14.4
+    (MUSCL) flop/byte, below the FP32 ridge of 157.3/8 = 19.7: HBM bound by
+    the published peaks (the measured limiter is the vector ALUs' issue)."""
     ms_tot, nl = prof["flux"]
     ms = ms_tot / nl
-    points = (n + 2) ** 3
-    faces = 3 * (n + 1) * (n + 2) * (n + 2)
-    byts = points * FLUX_BYTES_PER_POINT_FP32 + faces * FLUX_BYTES_PER_FACE_FP32
-    flops = faces * (HLLD_FLOPS_PER_FACE + 0.5 * MUSCL_FLOPS_PER_FACE)  # mean of both stages
+    cells = n ** 3
+    faces = 3 * cells
+    byts = cells * SWEEP_BYTES_PER_CELL_FP32
+    flops = faces * (HLLD_FLOPS_PER_FACE + 0.5 * MUSCL_FLOPS_PER_FACE) + cells * UPDATE_FLOPS_PER_CELL
     ach = byts / (ms * 1e-3) / 1e9
     traffic = None
-    if kernel_sources_hash() == PROFILED_FLUX["sources_sha256_16"] and n == PROFILED_FLUX["n"]:
-        traffic = PROFILED_FLUX["bytes_per_launch"]
-    return {"kernel": "k_flux (x, y and z faces in one launch; first-order and MUSCL + HLLD)",
+    if kernel_sources_hash() == PROFILED_SWEEP["sources_sha256_16"] and n == PROFILED_SWEEP["n"]:
+        traffic = PROFILED_SWEEP["bytes_per_launch"]
+    return {"kernel": "k_sweep (fused flux sweep and stage update: three face families, "
+                      "first-order and MUSCL + HLLD)",
             "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "ms_per_launch": ms,
             "bytes_per_launch": byts, "faces_per_launch": faces,
@@ -255,7 +257,7 @@ def main():
     kern = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1], "share": v[0] / sum(
         x[0] for x in prof32.values())} for k, v in prof32.items() if v[1]}
     result["kernel_profile_fp32"] = kern
-    result["roofline"] = flux_roofline(n, prof32)
+    result["roofline"] = sweep_roofline(n, prof32)
     # the whole path: arithmetic intensity 3162 flop / 64 B = 49 flop/byte
     result["path_roofline"] = {
         "bound": "alu", "flops_per_cell_update": STEP_FLOPS_PER_CELL_UPDATE,

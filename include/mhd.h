@@ -246,7 +246,9 @@ enum {
   MHD_K_PRIM = 1,     /* primitives; in a step that computes its own dt also the
                          CFL candidates of the start-of-step state and their
                          reduction to dt */
-  MHD_K_FLUX = 2,     /* fluxes of all three face families, one launch */
+  MHD_K_FLUX = 2,     /* fluxes of all three face families, one launch: the fused
+                         flux sweep with the stage's conservative update, or (with
+                         a flux accumulator) the plain flux kernel */
   MHD_K_FLUX_MLP = 3, /* corrector flux sweeps with the learned correction,
                          one launch per axis */
   MHD_K_SHOCK = 4,    /* shock cells of the corrector state (learned runs) */
@@ -257,7 +259,9 @@ enum {
   MHD_K_GRAVITY = 9,  /* self-gravity Poisson solve (FFTs, k-space division, gradient) */
   MHD_K_SCALARS = 10, /* passive-scalar face fluxes and update, and their ghost fill */
   MHD_K_NBODY = 11,   /* particle kick and drift (their deposit is part of MHD_K_GRAVITY) */
-  MHD_K_COUNT = 12
+  MHD_K_FLUX_OUTER = 12, /* fluxes of the outer layer of the flux range after the fused
+                            sweep (copied from periodic images or solved) */
+  MHD_K_COUNT = 13
 };
 
 typedef struct mhd_profile_t {

@@ -68,7 +68,7 @@ class mhd_profile_t(C.Structure):
 
 
 KERNEL_KINDS = ("ghosts", "prim", "flux", "flux_mlp", "shock", "emf", "update", "cfl", "other",
-                "gravity", "scalars", "nbody")
+                "gravity", "scalars", "nbody", "flux_outer")
 MAX_SCALARS = 8
 
 

@@ -470,10 +470,13 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   // predictor: first-order fluxes of U^n, half step into U* and its
   // primitives
   c->mark(MHD_K_FLUX);
-  if (swept)
+  if (swept) {
     launch_sweep<T>(g, c->ph, W, U, Us, F, first, c->grav<T>(), half, cnt, store, c->st);
-  else
+    c->mark(MHD_K_FLUX_OUTER);
+    launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, c->st);
+  } else {
     launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
+  }
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, W, F, E, c->st);
   c->mark(MHD_K_UPDATE);
@@ -506,6 +509,8 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   } else if (swept) {
     c->mark(MHD_K_FLUX);
     launch_sweep<T>(g, c->ph, Ws, Un, Un, F, second, c->grav<T>(), dt, cnt, store, c->st);
+    c->mark(MHD_K_FLUX_OUTER);
+    launch_flux_outer<T>(g, c->ph, Ws, Us, F, second, cnt, c->st);
   } else {
     c->mark(MHD_K_FLUX);
     launch_flux<T>(g, c->ph, Ws, Us, F, second, cnt, c->st);

@@ -199,6 +199,12 @@ static int flux_shell_points(const Geo& g) {
   return 2 * (w0 * w1 + w0 * g.n[2] + g.n[1] * g.n[2]);
 }
 
+// A point of the outer layer whose out-of-range coordinates all lie on
+// periodic axes is the periodic image of an interior point, whose faces the
+// sweep has solved from the same stencil values: its faces are copied from
+// there (bitwise what solving them would give; the sweep counted their
+// solver events, face_copies).  Elsewhere (an outflow or inflow side) they
+// are solved.  Runs after the sweep.
 template <class T, int RS, bool FO>
 __global__ void __launch_bounds__(256) k_flux_shell(Geo g, Physics ph, Prim<T> w,
                                                     const T* __restrict__ bx,
@@ -207,9 +213,33 @@ __global__ void __launch_bounds__(256) k_flux_shell(Geo g, Physics ph, Prim<T> w
                                                     Muscl<T> mu, Counters cnt) {
   int c[3];
   int cx = 0, cy = 0, cz = 0;
-  if (flux_shell_point(g, (int)(blockIdx.x * 256u + threadIdx.x), c))
-    flux_point<T, RS, FO>(g, ph, c[0], c[1], c[2], pidx(g, c[0], c[1], c[2]), w, bx, by, bz, f,
-                          mu, cx, cy, cz);
+  if (flux_shell_point(g, (int)(blockIdx.x * 256u + threadIdx.x), c)) {
+    const int p = pidx(g, c[0], c[1], c[2]);
+    int m[3];
+    bool image = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      m[a] = c[a];
+      if (c[a] < 0 || c[a] >= g.n[a]) {
+        if (g.nf[a] == g.n[a])
+          m[a] = c[a] < 0 ? c[a] + g.n[a] : c[a] - g.n[a];
+        else
+          image = false;
+      }
+    }
+    if (image) {
+      const int q = pidx(g, m[0], m[1], m[2]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (c[a] < 0) continue;  // no A-face at index -1
+#pragma unroll
+        for (int k = 0; k < 7; ++k) f.f[a][k][p] = f.f[a][k][q];
+        f.sg[a][p] = f.sg[a][q];
+      }
+    } else {
+      flux_point<T, RS, FO>(g, ph, c[0], c[1], c[2], p, w, bx, by, bz, f, mu, cx, cy, cz);
+    }
+  }
   count_codes(cnt, cx, cy, cz);
 }
 
@@ -294,6 +324,24 @@ __device__ __forceinline__ void store_face(const Flux<T>& f, const T F[7], unsig
   for (int c = 0; c < cn; ++c) gst(f.f[A][c], o, F[c]);
 }
 
+// How many times the outer layer copies the A-face of interior cell c (its
+// periodic images: along a periodic axis a cell at index 0 reappears at n,
+// one at n-1 at -1, where an A-face exists only if that index is not -1 on
+// A itself), plus one for the face itself: the sweep counts a solver event
+// on that face this many times, as solving the outer layer would.
+__device__ __forceinline__ int face_copies(const Geo& g, const int c[3], int A) {
+  int m = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (g.nf[a] != g.n[a]) continue;  // not periodic
+    int k = 1;
+    if (c[a] == 0) ++k;
+    if (c[a] == g.n[a] - 1 && a != A) ++k;
+    m *= k;
+  }
+  return m;
+}
+
 struct SweepGrid {
   int ntx, nty, nch, nblk;
 };
@@ -368,23 +416,35 @@ __global__ void __launch_bounds__(kSwX* kSwY) k_sweep(Geo g, Physics ph, SweepGr
       {
         const Stencil<T> sx = sweep_stencil<T, 0, FO>(es, w, s0.b[0], o);
         const int cx = face_solve<T, RS, FO>(ph, sx, mu, Fx);
-        hll += cx & 1;
-        deg += (cx >> 1) & 1;
+        const int cc[3] = {i, j, k};
+        if (cx) {
+          const int mult = face_copies(g, cc, 0);
+          hll += (cx & 1) * mult;
+          deg += ((cx >> 1) & 1) * mult;
+        }
         store_face<T, 0>(f, Fx, o, p, store, lx == 0);
       }
       __builtin_amdgcn_sched_barrier(0);
       {
         const Stencil<T> sy = sweep_stencil<T, 1, FO>((unsigned)g.sy * es, w, s0.b[1], o);
         const int cy = face_solve<T, RS, FO>(ph, sy, mu, Fy);
-        hll += cy & 1;
-        deg += (cy >> 1) & 1;
+        const int cc[3] = {i, j, k};
+        if (cy) {
+          const int mult = face_copies(g, cc, 1);
+          hll += (cy & 1) * mult;
+          deg += ((cy >> 1) & 1) * mult;
+        }
         store_face<T, 1>(f, Fy, o, p, store, ly == 0);
       }
       __builtin_amdgcn_sched_barrier(0);
       {
         const int cz = face_solve<T, RS, FO>(ph, zs, mu, Fz);
-        hll += cz & 1;
-        deg += (cz >> 1) & 1;
+        const int cc[3] = {i, j, k};
+        if (cz) {
+          const int mult = face_copies(g, cc, 2);
+          hll += (cz & 1) * mult;
+          deg += ((cz >> 1) & 1) * mult;
+        }
         store_face<T, 2>(f, Fz, o, p, store, k == k0);
       }
 #pragma unroll
@@ -451,9 +511,29 @@ static void launch_sweep_rs(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> 
   sg.nblk = sg.ntx * sg.nty * sg.nch;
   hipLaunchKernelGGL((k_sweep<T, RS, FO>), dim3((unsigned)sg.nblk), dim3(kSwX * kSwY), 0, st, g,
                      ph, sg, w, s0, s1, f, m, gr, dt, c, store);
-  const int ns = flux_shell_points(g);
-  hipLaunchKernelGGL((k_flux_shell<T, RS, FO>), dim3((unsigned)((ns + 255) / 256)), dim3(256), 0,
-                     st, g, ph, w, s0.b[0], s0.b[1], s0.b[2], f, m, c);
+}
+
+template <class T, int RS>
+static void launch_outer_rs(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f,
+                            Muscl<T> m, Counters c, hipStream_t st) {
+  const dim3 gr((unsigned)((flux_shell_points(g) + 255) / 256)), bl(256);
+  if (m.first_order)
+    hipLaunchKernelGGL((k_flux_shell<T, RS, true>), gr, bl, 0, st, g, ph, w, s.b[0], s.b[1],
+                       s.b[2], f, m, c);
+  else
+    hipLaunchKernelGGL((k_flux_shell<T, RS, false>), gr, bl, 0, st, g, ph, w, s.b[0], s.b[1],
+                       s.b[2], f, m, c);
+}
+
+template <class T>
+void launch_flux_outer(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f,
+                       Muscl<T> m, Counters c, hipStream_t st) {
+  if (ph.riemann == kRiemannHLL)
+    launch_outer_rs<T, kRiemannHLL>(g, ph, w, s, f, m, c, st);
+  else if (ph.riemann == kRiemannHLLC)
+    launch_outer_rs<T, kRiemannHLLC>(g, ph, w, s, f, m, c, st);
+  else
+    launch_outer_rs<T, kRiemannHLLD>(g, ph, w, s, f, m, c, st);
 }
 
 template <class T, int RS>
@@ -507,6 +587,10 @@ template void launch_flux<double>(const Geo&, const Physics&, Prim<double>, Cons
                                   Flux<double>, Muscl<double>, Counters, hipStream_t);
 template void launch_flux<float>(const Geo&, const Physics&, Prim<float>, Cons<float>,
                                  Flux<float>, Muscl<float>, Counters, hipStream_t);
+template void launch_flux_outer<double>(const Geo&, const Physics&, Prim<double>, Cons<double>,
+                                        Flux<double>, Muscl<double>, Counters, hipStream_t);
+template void launch_flux_outer<float>(const Geo&, const Physics&, Prim<float>, Cons<float>,
+                                       Flux<float>, Muscl<float>, Counters, hipStream_t);
 template void launch_sweep<double>(const Geo&, const Physics&, Prim<double>, Cons<double>,
                                    Cons<double>, Flux<double>, Muscl<double>, Grav<double>,
                                    DtRef, Counters, int, hipStream_t);

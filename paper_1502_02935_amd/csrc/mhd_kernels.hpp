@@ -202,12 +202,19 @@ constexpr int kSwX = 64, kSwY = 4, kSwZ = 16;
 // tile seams, which go to f for launch_update(swept); the field
 // components of the fluxes and the mass-flux signs of every face to f for
 // the EMFs; store 1: also the mass fluxes (passive scalars), 2: every
-// component.  The faces of the outer layer of the flux range [-1, n]^3 are
-// computed by a second, small kernel into f.  s1's cells may be s0's.
+// component.  s1's cells may be s0's.  launch_flux_outer completes f.
 template <class T>
 void launch_sweep(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s0, Cons<T> s1,
                   Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c, int store,
                   hipStream_t st);
+// After launch_sweep: every component of the faces of the points in the
+// outer layer of the flux range, [-1, n]^3 without [0, n-1]^3 (the faces
+// at index n and the ghost rows the EMFs need), copied from their periodic
+// images (which the sweep solved) or, on outflow and inflow sides, solved
+// with normal B from s's faces.
+template <class T>
+void launch_flux_outer(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f,
+                       Muscl<T> m, Counters c, hipStream_t st);
 int update_cfl_blocks(const Geo& g);
 // Primitives of the ghost shell [-NG, n+NG-1]^3 minus the interior (after
 // the ghost fill).
