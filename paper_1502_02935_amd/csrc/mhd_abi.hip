@@ -473,7 +473,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   if (swept) {
     launch_sweep<T>(g, c->ph, W, U, Us, F, first, c->grav<T>(), half, cnt, store, c->st);
     c->mark(MHD_K_FLUX_OUTER);
-    launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, c->st);
+    launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, store, c->st);
   } else {
     launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
   }
@@ -510,7 +510,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     c->mark(MHD_K_FLUX);
     launch_sweep<T>(g, c->ph, Ws, Un, Un, F, second, c->grav<T>(), dt, cnt, store, c->st);
     c->mark(MHD_K_FLUX_OUTER);
-    launch_flux_outer<T>(g, c->ph, Ws, Us, F, second, cnt, c->st);
+    launch_flux_outer<T>(g, c->ph, Ws, Us, F, second, cnt, store, c->st);
   } else {
     c->mark(MHD_K_FLUX);
     launch_flux<T>(g, c->ph, Ws, Us, F, second, cnt, c->st);

@@ -515,8 +515,14 @@ static void launch_sweep_rs(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> 
 
 template <class T, int RS>
 static void launch_outer_rs(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f,
-                            Muscl<T> m, Counters c, hipStream_t st) {
-  const dim3 gr((unsigned)((flux_shell_points(g) + 255) / 256)), bl(256);
+                            Muscl<T> m, Counters c, int store, hipStream_t st) {
+  // the x-layer (the last 2 n_y n_z points) of a periodic x axis is left out
+  // unless every flux is kept: its readers take the images at x-index n-1
+  // and 0 instead, which lie in the cache lines they already read (the
+  // layer itself costs a line per row and array at both ends of the rows)
+  int npt = flux_shell_points(g);
+  if (g.nf[0] == g.n[0] && store < 2) npt -= 2 * g.n[1] * g.n[2];
+  const dim3 gr((unsigned)((npt + 255) / 256)), bl(256);
   if (m.first_order)
     hipLaunchKernelGGL((k_flux_shell<T, RS, true>), gr, bl, 0, st, g, ph, w, s.b[0], s.b[1],
                        s.b[2], f, m, c);
@@ -527,13 +533,13 @@ static void launch_outer_rs(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> 
 
 template <class T>
 void launch_flux_outer(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f,
-                       Muscl<T> m, Counters c, hipStream_t st) {
+                       Muscl<T> m, Counters c, int store, hipStream_t st) {
   if (ph.riemann == kRiemannHLL)
-    launch_outer_rs<T, kRiemannHLL>(g, ph, w, s, f, m, c, st);
+    launch_outer_rs<T, kRiemannHLL>(g, ph, w, s, f, m, c, store, st);
   else if (ph.riemann == kRiemannHLLC)
-    launch_outer_rs<T, kRiemannHLLC>(g, ph, w, s, f, m, c, st);
+    launch_outer_rs<T, kRiemannHLLC>(g, ph, w, s, f, m, c, store, st);
   else
-    launch_outer_rs<T, kRiemannHLLD>(g, ph, w, s, f, m, c, st);
+    launch_outer_rs<T, kRiemannHLLD>(g, ph, w, s, f, m, c, store, st);
 }
 
 template <class T, int RS>
@@ -588,9 +594,9 @@ template void launch_flux<double>(const Geo&, const Physics&, Prim<double>, Cons
 template void launch_flux<float>(const Geo&, const Physics&, Prim<float>, Cons<float>,
                                  Flux<float>, Muscl<float>, Counters, hipStream_t);
 template void launch_flux_outer<double>(const Geo&, const Physics&, Prim<double>, Cons<double>,
-                                        Flux<double>, Muscl<double>, Counters, hipStream_t);
+                                        Flux<double>, Muscl<double>, Counters, int, hipStream_t);
 template void launch_flux_outer<float>(const Geo&, const Physics&, Prim<float>, Cons<float>,
-                                       Flux<float>, Muscl<float>, Counters, hipStream_t);
+                                       Flux<float>, Muscl<float>, Counters, int, hipStream_t);
 template void launch_sweep<double>(const Geo&, const Physics&, Prim<double>, Cons<double>,
                                    Cons<double>, Flux<double>, Muscl<double>, Grav<double>,
                                    DtRef, Counters, int, hipStream_t);

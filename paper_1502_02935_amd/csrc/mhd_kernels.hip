@@ -507,22 +507,30 @@ __device__ __forceinline__ T upwind(int8_t sgn, T from_low, T from_high) {
   return sgn > 0 ? from_low : (sgn < 0 ? from_high : T(0.5) * (from_low + from_high));
 }
 
+// Faces at x-index -1 and n of a periodic x axis are read at their images
+// n-1 and 0 (the fused flux sweep does not store that layer; elsewhere the
+// two hold the same values): i is the point's x-index.
 template <class T, int C>
-__device__ __forceinline__ T corner(const Geo& g, const Prim<T>& w, const Flux<T>& f, int p) {
+__device__ __forceinline__ T corner(const Geo& g, const Prim<T>& w, const Flux<T>& f, int p,
+                                    int i) {
   constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
   const int sa = stride_of(g, A), sb = stride_of(g, B);
+  const bool xper = g.nf[0] == g.n[0];
+  const int pw = xper && i == g.n[0] ? p - g.n[0] : p;        // the point itself
+  const int xm = xper && i == 0 ? p + g.n[0] - 1 : p - 1;     // one step down x
+  const int pa = A == 0 ? xm : pw - sa, pb = B == 0 ? xm : pw - sb;
   const T* __restrict__ fa = f.f[A][5];  // B_b flux at a-faces (t1 of the a-frame)
   const T* __restrict__ fb = f.f[B][6];  // B_a flux at b-faces (t2 of the b-frame)
   const int8_t* __restrict__ ga = f.sg[A];
   const int8_t* __restrict__ gb = f.sg[B];
   const T* __restrict__ cc = w.ec[C];
-  const T X0 = -fa[p], X1 = -fa[p - sb];
-  const T Y0 = fb[p], Y1 = fb[p - sa];
+  const T X0 = -fa[pw], X1 = -fa[pb];
+  const T Y0 = fb[pw], Y1 = fb[pa];
   const T c00 = cc[p - sa - sb], c10 = cc[p - sb], c01 = cc[p - sa], c11 = cc[p];
-  const T db1 = upwind(ga[p], c01 - Y1, c11 - Y0);
-  const T db3 = upwind(ga[p - sb], Y1 - c00, Y0 - c10);
-  const T da1 = upwind(gb[p], c10 - X1, c11 - X0);
-  const T da3 = upwind(gb[p - sa], X1 - c00, X0 - c01);
+  const T db1 = upwind(ga[pw], c01 - Y1, c11 - Y0);
+  const T db3 = upwind(ga[pb], Y1 - c00, Y0 - c10);
+  const T da1 = upwind(gb[pw], c10 - X1, c11 - X0);
+  const T da3 = upwind(gb[pa], X1 - c00, X0 - c01);
   return T(0.25) * (X0 + X1 + Y0 + Y1) + T(0.25) * (db3 - db1) + T(0.25) * (da3 - da1);
 }
 
@@ -535,9 +543,9 @@ __global__ void __launch_bounds__(kSpanThreads) k_emf(Geo g, Span sp, Prim<T> w,
   const Pt pt = span_point(g, sp);
   if (!pt.valid) return;
   const int p = pt.p;
-  const T ex = corner<T, 0>(g, w, f, p);
-  const T ey = corner<T, 1>(g, w, f, p);
-  const T ez = corner<T, 2>(g, w, f, p);
+  const T ex = corner<T, 0>(g, w, f, p, pt.i);
+  const T ey = corner<T, 1>(g, w, f, p, pt.i);
+  const T ez = corner<T, 2>(g, w, f, p, pt.i);
   if (pt.i < g.n[0]) e.e[0][p] = ex;
   if (pt.j < g.n[1]) e.e[1][p] = ey;
   if (pt.k < g.n[2]) e.e[2][p] = ez;
@@ -615,8 +623,10 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
       for (int m = 0; m < 5; ++m) u[m] = s1.u[m][p];
       if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
         if (i % kSwX == kSwX - 1 || i == g.n[0] - 1) {
+          // face n of a periodic x axis is read at its image, face 0
+          const int q = g.nf[0] == g.n[0] && i == g.n[0] - 1 ? p + 1 - g.n[0] : p + 1;
 #pragma unroll
-          for (int m = 0; m < 5; ++m) u[m] -= rx * f.f[0][frame_comp(0, m)][p + 1];
+          for (int m = 0; m < 5; ++m) u[m] -= rx * f.f[0][frame_comp(0, m)][q];
         }
         if (j % kSwY == kSwY - 1 || j == g.n[1] - 1) {
 #pragma unroll
@@ -1021,7 +1031,9 @@ __global__ void __launch_bounds__(kSpanThreads) k_scalar_update(Geo g, Span sp,
 #pragma unroll
     for (int o = 0; o < 5; ++o) ir[a][o] = o == 2 ? ic : rcp(rho[p + (o - 2) * st[a]]);
     flo[a] = f.f[a][0][p];
-    fhi[a] = f.f[a][0][p + st[a]];
+    // face n of a periodic x axis is read at its image, face 0
+    const int up = a == 0 && g.nf[0] == g.n[0] && pt.i == g.n[0] - 1 ? p + 1 - g.n[0] : p + st[a];
+    fhi[a] = f.f[a][0][up];
     r[a] = (T)(dt / g.d[a]);
   }
   T out[NS];

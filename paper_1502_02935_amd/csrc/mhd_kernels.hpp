@@ -211,10 +211,12 @@ void launch_sweep(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s0, Cons<T
 // outer layer of the flux range, [-1, n]^3 without [0, n-1]^3 (the faces
 // at index n and the ghost rows the EMFs need), copied from their periodic
 // images (which the sweep solved) or, on outflow and inflow sides, solved
-// with normal B from s's faces.
+// with normal B from s's faces.  On a periodic x axis the points at x-index
+// -1 and n are left out unless store is 2 (their readers -- the EMFs, the
+// swept update's seams, the passive scalars -- wrap the x-index).
 template <class T>
 void launch_flux_outer(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f,
-                       Muscl<T> m, Counters c, hipStream_t st);
+                       Muscl<T> m, Counters c, int store, hipStream_t st);
 int update_cfl_blocks(const Geo& g);
 // Primitives of the ghost shell [-NG, n+NG-1]^3 minus the interior (after
 // the ghost fill).
