@@ -127,38 +127,6 @@ struct Star {
   T d, v1, v2, b1, b2, e, vb;
 };
 
-template <class T>
-__device__ __forceinline__ Star<T> star_side(const Face<T>& s, T e, T bn, T S, T SM, T pts,
-                                             int& degenerate) {
-#pragma clang fp contract(on)
-  Star<T> r;
-  const T sv = S - s.vn;
-  const T ism = rcp(S - SM);
-  const T pt = s.p + T(0.5) * (bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2);
-  const T dsv = s.d * sv;
-  r.d = dsv * ism;
-  const T den = dsv * (S - SM) - bn * bn;
-  if (fabs(den) > T(kDegenerate) * pts) {
-    const T iden = rcp(den);
-    const T kv = bn * (SM - s.vn) * iden;
-    const T kb = (dsv * sv - bn * bn) * iden;
-    r.v1 = s.vt1 - s.bt1 * kv;
-    r.v2 = s.vt2 - s.bt2 * kv;
-    r.b1 = s.bt1 * kb;
-    r.b2 = s.bt2 * kb;
-  } else {
-    r.v1 = s.vt1;
-    r.v2 = s.vt2;
-    r.b1 = s.bt1;
-    r.b2 = s.bt2;
-    degenerate = 1;
-  }
-  const T vb = s.vn * bn + s.vt1 * s.bt1 + s.vt2 * s.bt2;
-  r.vb = SM * bn + r.v1 * r.b1 + r.v2 * r.b2;
-  r.e = (sv * e - pt * s.vn + pts * SM + bn * (vb - r.vb)) * ism;
-  return r;
-}
-
 // HLL flux (Harten, Lax & van Leer): one intermediate state between the
 // outer waves, with the outer speeds of the HLLD solver.
 template <class T>
@@ -230,30 +198,53 @@ __device__ __forceinline__ int hllc(const Face<T>& L0, const Face<T>& R0, T gam,
   return 0;
 }
 
+// Star state of one side without its energy: density, transverse v and B
+// (the energy is needed for the side whose flux is returned only).
+template <class T>
+__device__ __forceinline__ Star<T> star_base(const Face<T>& s, T bn, T S, T SM, T pts,
+                                             int& degenerate) {
+#pragma clang fp contract(on)
+  Star<T> r;
+  const T sv = S - s.vn;
+  const T ism = rcp(S - SM);
+  const T dsv = s.d * sv;
+  r.d = dsv * ism;
+  const T den = dsv * (S - SM) - bn * bn;
+  if (fabs(den) > T(kDegenerate) * pts) {
+    const T iden = rcp(den);
+    const T kv = bn * (SM - s.vn) * iden;
+    const T kb = (dsv * sv - bn * bn) * iden;
+    r.v1 = s.vt1 - s.bt1 * kv;
+    r.v2 = s.vt2 - s.bt2 * kv;
+    r.b1 = s.bt1 * kb;
+    r.b2 = s.bt2 * kb;
+  } else {
+    r.v1 = s.vt1;
+    r.v2 = s.vt2;
+    r.b1 = s.bt1;
+    r.b2 = s.bt2;
+    degenerate = 1;
+  }
+  r.e = T(0);
+  r.vb = T(0);
+  return r;
+}
+
 // HLLD flux (igm1 = 1/(gamma - 1)).  Returns bit0 if the HLL flux was used
-// (S_M outside (S_L, S_R)), bit1 if a star state was degenerate.
+// (S_M outside (S_L, S_R)), bit1 if a star state was degenerate.  The side
+// whose conserved state and flux enter the result -- the upwind side of a
+// supersonic face, else the side of the contact the face lies on -- is
+// picked before any flux is formed, so each face forms one physical flux
+// (both only when it falls back to HLL).
 template <class T>
 __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T gam, T igm1,
                                     T f[7]) {
 #pragma clang fp contract(on)
-  T ul[7], fl[7], ur[7], fr[7];
-  cons_flux(L, bn, igm1, ul, fl);
-  cons_flux(R, bn, igm1, ur, fr);
   const T cfl = fast_speed(L.d, L.p, bn, L.bt1, L.bt2, gam);
   const T cfr = fast_speed(R.d, R.p, bn, R.bt1, R.bt2, gam);
   const T cmax = cfl > cfr ? cfl : cfr;
   const T SL = (L.vn < R.vn ? L.vn : R.vn) - cmax;
   const T SR = (L.vn > R.vn ? L.vn : R.vn) + cmax;
-  if (SL > T(0)) {
-#pragma unroll
-    for (int m = 0; m < 7; ++m) f[m] = fl[m];
-    return 0;
-  }
-  if (SR < T(0)) {
-#pragma unroll
-    for (int m = 0; m < 7; ++m) f[m] = fr[m];
-    return 0;
-  }
   const T ptl = L.p + T(0.5) * (bn * bn + L.bt1 * L.bt1 + L.bt2 * L.bt2);
   const T ptr = R.p + T(0.5) * (bn * bn + R.bt1 * R.bt1 + R.bt2 * R.bt2);
   const T al = L.d * (SL - L.vn);
@@ -261,32 +252,51 @@ __device__ __forceinline__ int hlld(const Face<T>& L, const Face<T>& R, T bn, T 
   const T ia = rcp(ar - al);
   const T SM = (ar * R.vn - al * L.vn - ptr + ptl) * ia;
   const T pts = (ar * ptl - al * ptr + al * ar * (R.vn - L.vn)) * ia;
+  const bool sup = SL > T(0) || SR < T(0);
+  const bool left = sup ? SL > T(0) : SM >= T(0);
+  const Face<T> w = left ? L : R;
+  T u0[7], f0[7];
+  cons_flux(w, bn, igm1, u0, f0);
+  if (sup) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) f[m] = f0[m];
+    return 0;
+  }
   if (!(SL < SM && SM < SR)) {
+    T uo[7], fo[7];
+    cons_flux(left ? R : L, bn, igm1, uo, fo);
     const T inv = rcp(SR - SL);
 #pragma unroll
-    for (int m = 0; m < 7; ++m) f[m] = (SR * fl[m] - SL * fr[m] + SL * SR * (ur[m] - ul[m])) * inv;
+    for (int m = 0; m < 7; ++m) {
+      const T ul = left ? u0[m] : uo[m], ur = left ? uo[m] : u0[m];
+      const T fl = left ? f0[m] : fo[m], fr = left ? fo[m] : f0[m];
+      f[m] = (SR * fl - SL * fr + SL * SR * (ur - ul)) * inv;
+    }
     return 1;
   }
   int deg = 0;
-  const Star<T> sl = star_side(L, ul[4], bn, SL, SM, pts, deg);
-  const Star<T> sr = star_side(R, ur[4], bn, SR, SM, pts, deg);
+  const Star<T> sl = star_base(L, bn, SL, SM, pts, deg);
+  const Star<T> sr = star_base(R, bn, SR, SM, pts, deg);
   T ql, qr, iql, iqr;
   root_pair(sl.d, ql, iql);
   root_pair(sr.d, qr, iqr);
   const T abn = fabs(bn);
   const T SsL = SM - abn * iql;
   const T SsR = SM + abn * iqr;
-  const bool left = SM >= T(0);
-  const Star<T> s = left ? sl : sr;
   const T S = left ? SL : SR;
+  Star<T> s = left ? sl : sr;
+  {  // the chosen side's star energy and v*.B*
+    const T sv = S - w.vn;
+    const T ism = rcp(S - SM);
+    const T pt = w.p + T(0.5) * (bn * bn + w.bt1 * w.bt1 + w.bt2 * w.bt2);
+    const T vb = w.vn * bn + w.vt1 * w.bt1 + w.vt2 * w.bt2;
+    s.vb = SM * bn + s.v1 * s.b1 + s.v2 * s.b2;
+    s.e = (sv * u0[4] - pt * w.vn + pts * SM + bn * (vb - s.vb)) * ism;
+  }
   // F*_a = F_a + S_a (U*_a - U_a)
   const T us[7] = {s.d, s.d * SM, s.d * s.v1, s.d * s.v2, s.e, s.b1, s.b2};
 #pragma unroll
-  for (int m = 0; m < 7; ++m) {
-    const T u0 = left ? ul[m] : ur[m];
-    const T f0 = left ? fl[m] : fr[m];
-    f[m] = f0 + S * (us[m] - u0);
-  }
+  for (int m = 0; m < 7; ++m) f[m] = f0[m] + S * (us[m] - u0[m]);
   const bool inner = left ? (SsL < T(0)) : (SsR < T(0) ? false : true);
   if (inner) {
     // double-star state across the rotational discontinuity on this side
