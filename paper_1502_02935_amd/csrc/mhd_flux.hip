@@ -396,10 +396,11 @@ __global__ void __launch_bounds__(kSwX* kSwY) k_sweep(Geo g, Physics ph, SweepGr
     const int p = pidx(g, i, j, k);
     const unsigned o = (unsigned)p * es;
     T Fx[7], Fy[7], Fz[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) Fx[c] = Fy[c] = Fz[c] = T(0);
     T un[5], S[5];
-    if (act) {
+    if (!act) {  // lanes outside the box still feed the exchanges
+#pragma unroll
+      for (int c = 0; c < 5; ++c) Fx[c] = Fy[c] = T(0);
+    } else {
       {  // the plane the z-stencil gains: k+1 (first order: k)
         T v[7];
         load_point<T, 2>(w, FO ? o : o + (unsigned)g.sz * es, v);

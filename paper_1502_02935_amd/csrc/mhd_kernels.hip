@@ -616,12 +616,15 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
                       ct_face<T, 1>(g, s0, e, up[1], rz, rx),
                       ct_face<T, 2>(g, s0, e, up[2], rx, ry)};
     T u[5];
+    bool store_u = !SWEPT;  // the sweep's value stands unless a seam or a floor changes it
     if constexpr (SWEPT) {
       // the sweep left the update of every cell, without the fluxes of the
       // upper faces on its tile seams (last column, row or plane of a tile)
 #pragma unroll
       for (int m = 0; m < 5; ++m) u[m] = s1.u[m][p];
       if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+        store_u = i % kSwX == kSwX - 1 || i == g.n[0] - 1 || j % kSwY == kSwY - 1 ||
+                  j == g.n[1] - 1 || k % kSwZ == kSwZ - 1 || k == g.n[2] - 1;
         if (i % kSwX == kSwX - 1 || i == g.n[0] - 1) {
           // face n of a periodic x axis is read at its image, face 0
           const int q = g.nf[0] == g.n[0] && i == g.n[0] - 1 ? p + 1 - g.n[0] : p + 1;
@@ -677,11 +680,13 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
           hit = true;
         }
       }
-      s1.u[0][p] = rho;
-      s1.u[1][p] = u[1];
-      s1.u[2][p] = u[2];
-      s1.u[3][p] = u[3];
-      s1.u[4][p] = E;
+      if (store_u || hit) {
+        s1.u[0][p] = rho;
+        s1.u[1][p] = u[1];
+        s1.u[2][p] = u[2];
+        s1.u[3][p] = u[3];
+        s1.u[4][p] = E;
+      }
       store_prim(gam, wo, p, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1], bnew[2],
                  bup[2], rec);
       if constexpr (CFL)
