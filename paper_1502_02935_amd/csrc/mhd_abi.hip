@@ -243,6 +243,11 @@ struct mhd_ctx {
   // shell), as the last step left them; cfl_valid: cfl_part() holds that
   // step's update_cfl_blocks() partials of U's time-step candidates.
   bool w_valid = false, cfl_valid = false;
+  // xg_stale: the last ghost fill of U and of prim<T>(0) ran with x_lite (on
+  // a fully periodic box the fused path reads x ghosts at their interior
+  // images, so its stages skip those layers); any other path refills them
+  // first.
+  bool xg_stale = false;
   // keep every component of every face's flux in memory (mhd_set_full_fluxes)
   bool full_fluxes = false;
   template <class T>
@@ -442,6 +447,25 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   DtRef at_n = dt, at_half = dt;  // particle positions of the two potentials
   at_n.factor = 0.0;
   at_half.factor = 0.5;
+  // the fused flux sweep unless the learned correction or the flux
+  // accumulation needs every face's full flux in memory
+  const bool swept = !c->mlp_params && !c->flux_acc;
+  const int store = c->full_fluxes ? 2 : (ns > 0 ? 1 : 0);
+  // x ghost layers left out of the stages' ghost fills: only where nothing
+  // of this step reads them (fully periodic box, fused path, no passive
+  // scalar, no full fluxes kept for samples)
+  bool per = true;
+  for (int a = 0; a < 6; ++a) per = per && g.bc[a] == 0;
+  const bool x_lite = per && swept && ns == 0 && !c->full_fluxes;
+  if (c->xg_stale && !x_lite) {
+    c->mark(MHD_K_GHOSTS);
+    launch_ghosts<T>(g, c->ph, U, false, c->st);
+    if (c->w_valid) {
+      c->mark(MHD_K_PRIM);
+      launch_prim_shell<T>(g, c->ph, U, W, cnt, false, c->st);
+    }
+  }
+  c->xg_stale = x_lite;
   // primitives of U^n (and the step's own dt): left by the previous step's
   // corrector, else one pass over U
   c->mark(MHD_K_PRIM);
@@ -461,10 +485,6 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     c->mark(MHD_K_GRAVITY);
     launch_self_gravity<T>(g, c->ph, W.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_n, c->st);
   }
-  // the fused flux sweep unless the learned correction or the flux
-  // accumulation needs every face's full flux in memory
-  const bool swept = !c->mlp_params && !c->flux_acc;
-  const int store = c->full_fluxes ? 2 : (ns > 0 ? 1 : 0);
   DtRef half = dt;
   half.factor = 0.5;
   // predictor: first-order fluxes of U^n, half step into U* and its
@@ -487,9 +507,9 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     launch_scalar_ghosts<T>(g, Xh, ns, c->st);
   }
   c->mark(MHD_K_GHOSTS);
-  launch_ghosts<T>(g, c->ph, Us, c->st);
+  launch_ghosts<T>(g, c->ph, Us, x_lite, c->st);
   c->mark(MHD_K_PRIM);
-  launch_prim_shell<T>(g, c->ph, Us, Ws, cnt, c->st);
+  launch_prim_shell<T>(g, c->ph, Us, Ws, cnt, x_lite, c->st);
   // corrector: MUSCL fluxes of U*, full step from U^n, the primitives of
   // U^{n+1} and the candidates of the next step's dt
   if (c->gravity()) {
@@ -530,9 +550,9 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     launch_scalar_ghosts<T>(g, Xn, ns, c->st);
   }
   c->mark(MHD_K_GHOSTS);
-  launch_ghosts<T>(g, c->ph, Un, c->st);
+  launch_ghosts<T>(g, c->ph, Un, x_lite, c->st);
   c->mark(MHD_K_PRIM);
-  launch_prim_shell<T>(g, c->ph, Un, W, cnt, c->st);
+  launch_prim_shell<T>(g, c->ph, Un, W, cnt, x_lite, c->st);
   if (Pp.n > 0) {
     c->mark(MHD_K_NBODY);
     launch_kick_drift<T>(g, Pp, c->grav<T>(), dt, c->st);
@@ -653,12 +673,12 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
   if (cfg->precision == MHD_FP64) {
     launch_scatter<double>(c->g, (const double*)d_cell5, (const double*)d_bx,
                            (const double*)d_by, (const double*)d_bz, c->cons<double>(0), c->st);
-    launch_ghosts<double>(c->g, c->ph, c->cons<double>(0), c->st);
+    launch_ghosts<double>(c->g, c->ph, c->cons<double>(0), false, c->st);
     enqueue_cfl<double>(c);
   } else {
     launch_scatter<float>(c->g, (const float*)d_cell5, (const float*)d_bx, (const float*)d_by,
                           (const float*)d_bz, c->cons<float>(0), c->st);
-    launch_ghosts<float>(c->g, c->ph, c->cons<float>(0), c->st);
+    launch_ghosts<float>(c->g, c->ph, c->cons<float>(0), false, c->st);
     enqueue_cfl<float>(c);
   }
   int rc = hip_status();

@@ -283,25 +283,27 @@ __device__ __forceinline__ void load_point(const Prim<T>& w, unsigned o, T v[7])
   for (int q = 0; q < 7; ++q) v[q] = gld(src[q], o);
 }
 
-// The A-face stencil of the cell at byte offset o (stride s bytes along A)
-// and its face-normal field, as load_stencil.
+// The A-face stencil of the cell at byte offset o and its face-normal
+// field, as load_stencil; the points two below, one below and one above the
+// cell lie at o + dm2, o + dm1, o + dp1 (modulo 2^32).
 template <class T, int A, bool FO>
-__device__ __forceinline__ Stencil<T> sweep_stencil(unsigned s, const Prim<T>& w,
-                                                    const T* __restrict__ bn, unsigned o) {
+__device__ __forceinline__ Stencil<T> sweep_stencil(unsigned dm2, unsigned dm1, unsigned dp1,
+                                                    const Prim<T>& w, const T* __restrict__ bn,
+                                                    unsigned o) {
   Stencil<T> st;
   T v[7];
   if constexpr (!FO) {
-    load_point<T, A>(w, o - 2 * s, v);
+    load_point<T, A>(w, o + dm2, v);
 #pragma unroll
     for (int c = 0; c < 7; ++c) st.v[c][0] = v[c];
-    load_point<T, A>(w, o + s, v);
+    load_point<T, A>(w, o + dp1, v);
 #pragma unroll
     for (int c = 0; c < 7; ++c) st.v[c][3] = v[c];
   } else {
 #pragma unroll
     for (int c = 0; c < 7; ++c) st.v[c][0] = st.v[c][3] = T(0);
   }
-  load_point<T, A>(w, o - s, v);
+  load_point<T, A>(w, o + dm1, v);
 #pragma unroll
   for (int c = 0; c < 7; ++c) st.v[c][1] = v[c];
   load_point<T, A>(w, o, v);
@@ -342,6 +344,17 @@ __device__ __forceinline__ int face_copies(const Geo& g, const int c[3], int A) 
   return m;
 }
 
+// Index step from x-index i to the cell d away along x (|d| <= 2), wrapped
+// into [0, n) on a periodic x axis, as an unsigned (two's complement) count.
+__device__ __forceinline__ unsigned x_step(const Geo& g, int i, int d) {
+  int t = i + d;
+  if (g.nf[0] == g.n[0]) {
+    t %= g.n[0];
+    if (t < 0) t += g.n[0];
+  }
+  return (unsigned)(t - i);
+}
+
 struct SweepGrid {
   int ntx, nty, nch, nblk;
 };
@@ -368,6 +381,11 @@ __global__ void __launch_bounds__(kSwX* kSwY) k_sweep(Geo g, Physics ph, SweepGr
   const bool x_up = lx < kSwX - 1 && i + 1 < g.n[0];
   const bool y_up = ly < kSwY - 1 && j + 1 < g.n[1];
   const unsigned es = (unsigned)sizeof(T);
+  // byte offsets of the x-stencil's points from the cell: on a periodic x
+  // axis they wrap onto the interior images, so the x ghost layer of the
+  // primitives is never read
+  const unsigned xm2 = x_step(g, i, -2) * es, xm1 = x_step(g, i, -1) * es,
+                 xp1 = x_step(g, i, 1) * es;
   const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
   const T rx = (T)(dt / g.d[0]), ry = (T)(dt / g.d[1]), rz = (T)(dt / g.d[2]), dtT = (T)dt;
   // z-stencil of the z-face at plane k: planes k-2..k+1 in zs.v[.][0..3]
@@ -415,7 +433,7 @@ __global__ void __launch_bounds__(kSwX* kSwY) k_sweep(Geo g, Physics ph, SweepGr
       // flux if asked, the hydrodynamic components of the faces that other
       // tiles need (first column, row and plane of the tile).
       {
-        const Stencil<T> sx = sweep_stencil<T, 0, FO>(es, w, s0.b[0], o);
+        const Stencil<T> sx = sweep_stencil<T, 0, FO>(xm2, xm1, xp1, w, s0.b[0], o);
         const int cx = face_solve<T, RS, FO>(ph, sx, mu, Fx);
         const int cc[3] = {i, j, k};
         if (cx) {
@@ -427,8 +445,10 @@ __global__ void __launch_bounds__(kSwX* kSwY) k_sweep(Geo g, Physics ph, SweepGr
       }
       __builtin_amdgcn_sched_barrier(0);
       {
-        const Stencil<T> sy = sweep_stencil<T, 1, FO>((unsigned)g.sy * es, w, s0.b[1], o);
-        const int cy = face_solve<T, RS, FO>(ph, sy, mu, Fy);
+        const unsigned sy = (unsigned)g.sy * es;
+        const Stencil<T> sy_st =
+            sweep_stencil<T, 1, FO>(0u - 2u * sy, 0u - sy, sy, w, s0.b[1], o);
+        const int cy = face_solve<T, RS, FO>(ph, sy_st, mu, Fy);
         const int cc[3] = {i, j, k};
         if (cy) {
           const int mult = face_copies(g, cc, 1);

@@ -34,49 +34,56 @@ __device__ __forceinline__ int map_axis(int c, int m, int n, int bclo, int bchi,
 
 // Thread t -> ghost point c (the 5 ghost layers of x, then of y, then of z,
 // over the full extent of the other two axes); false past the last one.
-__device__ __forceinline__ bool ghost_point(const Geo& g, long long t, int c[3]) {
+// xl = 1 keeps of the x layers only the points at x-index n, whose only
+// value filled is the x-face n (*bx_only): on a fully periodic box the
+// fused stage path reads every other x ghost at its interior image.
+__device__ __forceinline__ bool ghost_point(const Geo& g, long long t, int xl, int c[3],
+                                           bool& bx_only) {
   const long long E0 = g.ext[0], E1 = g.ext[1], E2 = g.ext[2];
-  const long long nx5 = 5 * E1 * E2, ny5 = 5 * E0 * E2, nz5 = 5 * E0 * E1;
+  const long long nxl = xl * E1 * E2, ny5 = 5 * E0 * E2, nz5 = 5 * E0 * E1;
   long long r;
-  if (t < nx5) {
-    const int l = (int)(t % 5);
-    r = t / 5;
+  bx_only = false;
+  if (t < nxl) {
+    const int l = xl == 5 ? (int)(t % 5) : 2;
+    r = t / xl;
     c[0] = l < 2 ? l - 2 : g.n[0] + (l - 2);
     c[1] = (int)(r % E1) - NG;
     c[2] = (int)(r / E1) - NG;
-  } else if (t < nx5 + ny5) {
-    r = t - nx5;
+    bx_only = xl != 5;
+  } else if (t < nxl + ny5) {  // x fastest: a wave covers a run of one row
+    r = t - nxl;
+    c[0] = (int)(r % E0) - NG;
+    r /= E0;
     const int l = (int)(r % 5);
-    r /= 5;
     c[1] = l < 2 ? l - 2 : g.n[1] + (l - 2);
+    c[2] = (int)(r / 5) - NG;
+  } else if (t < nxl + ny5 + nz5) {
+    r = t - nxl - ny5;
     c[0] = (int)(r % E0) - NG;
-    c[2] = (int)(r / E0) - NG;
-  } else if (t < nx5 + ny5 + nz5) {
-    r = t - nx5 - ny5;
-    const int l = (int)(r % 5);
-    r /= 5;
+    r /= E0;
+    c[1] = (int)(r % E1) - NG;
+    const int l = (int)(r / E1);
     c[2] = l < 2 ? l - 2 : g.n[2] + (l - 2);
-    c[0] = (int)(r % E0) - NG;
-    c[1] = (int)(r / E0) - NG;
   } else {
     return false;
   }
   return true;
 }
 
-static unsigned ghost_blocks(const Geo& g, int bs) {
-  const long long tot = 5ll * ((long long)g.ext[1] * g.ext[2] + (long long)g.ext[0] * g.ext[2] +
-                               (long long)g.ext[0] * g.ext[1]);
+static unsigned ghost_blocks(const Geo& g, int bs, int xl) {
+  const long long tot = (long long)xl * g.ext[1] * g.ext[2] +
+                        5ll * ((long long)g.ext[0] * g.ext[2] + (long long)g.ext[0] * g.ext[1]);
   return (unsigned)((tot + bs - 1) / bs);
 }
 
 template <class T>
-__global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
+__global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
   int c[3];
-  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, c)) return;
+  bool bx_only;
+  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, xl, c, bx_only)) return;
   const int p = pidx(g, c[0], c[1], c[2]);
   // cell arrays
-  {
+  if (!bx_only) {
     bool inflow = false;
     int m[3];
 #pragma unroll
@@ -94,6 +101,7 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
   // face arrays: the normal axis has nf interior entries
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
+    if (bx_only && f != 0) continue;
     bool inflow = false;
     int m[3];
 #pragma unroll
@@ -108,8 +116,10 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s) {
 }
 
 template <class T>
-void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, hipStream_t st) {
-  hipLaunchKernelGGL(k_ghosts<T>, dim3(ghost_blocks(g, 256)), dim3(256), 0, st, g, ph, s);
+void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, bool x_lite, hipStream_t st) {
+  const int xl = x_lite ? 1 : 5;
+  hipLaunchKernelGGL(k_ghosts<T>, dim3(ghost_blocks(g, 256, xl)), dim3(256), 0, st, g, ph, s,
+                     xl);
 }
 
 // ------------------------------------------------------------------------
@@ -301,13 +311,19 @@ __device__ __forceinline__ bool shell_cell(const Geo& g, int t, int c[3]) {
   return true;
 }
 
-static int shell_cells(const Geo& g) {
+// x_lite: without the x-cells at the ends of the interior rows (the last
+// part of the enumeration).
+static int shell_cells(const Geo& g, bool x_lite) {
   const int w0 = g.n[0] + 2 * NG, w1 = g.n[1] + 2 * NG;
-  return 2 * NG * (w0 * w1 + w0 * g.n[2] + g.n[1] * g.n[2]);
+  return 2 * NG * (w0 * w1 + w0 * g.n[2] + (x_lite ? 0 : g.n[1] * g.n[2]));
 }
 
 // Primitives of the ghost shell (after the ghost fill; the interior cells'
-// come from the stage update).
+// come from the stage update).  After a ghost fill with x_lite the x-end
+// cells are left out; so are, in effect, the ghost planes' and rows' cells
+// at x-indices outside [0, n) (computed from x-ghost faces of the interior
+// rows that such a fill does not refresh, and read by nothing that runs
+// after it).
 template <class T>
 __global__ void __launch_bounds__(256) k_prim_shell(Geo g, Physics ph, Cons<T> s, Prim<T> w,
                                                     Counters cnt) {
@@ -324,8 +340,8 @@ __global__ void __launch_bounds__(256) k_prim_shell(Geo g, Physics ph, Cons<T> s
 
 template <class T>
 void launch_prim_shell(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
-                       hipStream_t st) {
-  const int n = shell_cells(g);
+                       bool x_lite, hipStream_t st) {
+  const int n = shell_cells(g, x_lite);
   hipLaunchKernelGGL(k_prim_shell<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, ph,
                      s, w, c);
 }
@@ -507,9 +523,10 @@ __device__ __forceinline__ T upwind(int8_t sgn, T from_low, T from_high) {
   return sgn > 0 ? from_low : (sgn < 0 ? from_high : T(0.5) * (from_low + from_high));
 }
 
-// Faces at x-index -1 and n of a periodic x axis are read at their images
-// n-1 and 0 (the fused flux sweep does not store that layer; elsewhere the
-// two hold the same values): i is the point's x-index.
+// Faces and cells at x-index -1 and n of a periodic x axis are read at
+// their images n-1 and 0 (the fused flux sweep does not store that face
+// layer and the stage's ghost fill may leave that cell layer out; where
+// both are filled they hold the same values): i is the point's x-index.
 template <class T, int C>
 __device__ __forceinline__ T corner(const Geo& g, const Prim<T>& w, const Flux<T>& f, int p,
                                     int i) {
@@ -526,7 +543,10 @@ __device__ __forceinline__ T corner(const Geo& g, const Prim<T>& w, const Flux<T
   const T* __restrict__ cc = w.ec[C];
   const T X0 = -fa[pw], X1 = -fa[pb];
   const T Y0 = fb[pw], Y1 = fb[pa];
-  const T c00 = cc[p - sa - sb], c10 = cc[p - sb], c01 = cc[p - sa], c11 = cc[p];
+  // the four cells around the edge: pw, pw - e_a (pa), pw - e_b (pb), and
+  // one step down both (a step down x is xm)
+  const int pab = A == 0 ? xm - sb : (B == 0 ? xm - sa : pw - sa - sb);
+  const T c00 = cc[pab], c10 = cc[pb], c01 = cc[pa], c11 = cc[pw];
   const T db1 = upwind(ga[pw], c01 - Y1, c11 - Y0);
   const T db3 = upwind(ga[pb], Y1 - c00, Y0 - c10);
   const T da1 = upwind(gb[pw], c10 - X1, c11 - X0);
@@ -1090,7 +1110,8 @@ void launch_scalar_update(const Geo& g, const T* rho, Flux<T> f, Scal<T> x0, Sca
 template <class T>
 __global__ void k_scalar_ghosts(Geo g, Scal<T> x, int ns) {
   int c[3];
-  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, c)) return;
+  bool bx_only;
+  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, 5, c, bx_only)) return;
   const int p = pidx(g, c[0], c[1], c[2]);
   bool inflow = false;
   int m[3];
@@ -1108,7 +1129,8 @@ __global__ void k_scalar_ghosts(Geo g, Scal<T> x, int ns) {
 template <class T>
 void launch_scalar_ghosts(const Geo& g, Scal<T> x, int ns, hipStream_t st) {
   if (ns <= 0) return;
-  hipLaunchKernelGGL(k_scalar_ghosts<T>, dim3(ghost_blocks(g, 256)), dim3(256), 0, st, g, x, ns);
+  hipLaunchKernelGGL(k_scalar_ghosts<T>, dim3(ghost_blocks(g, 256, 5)), dim3(256), 0, st, g, x,
+                     ns);
 }
 
 template <class T, bool IN>
@@ -1187,7 +1209,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
 // ------------------------------------------------------------------------
 
 #define MHD_INST(T)                                                                              \
-  template void launch_ghosts<T>(const Geo&, const Physics&, Cons<T>, hipStream_t);              \
+  template void launch_ghosts<T>(const Geo&, const Physics&, Cons<T>, bool, hipStream_t);        \
   template void launch_prim<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,           \
                                hipStream_t);                                                     \
   template void launch_prim_cfl<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, double*,        \
@@ -1197,7 +1219,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
                                    Muscl<T>, Counters, MlpRef, hipStream_t);                     \
   template void launch_shock<T>(const Geo&, Prim<T>, uint8_t*, double, hipStream_t);           \
   template void launch_prim_shell<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,     \
-                                     hipStream_t);                                               \
+                                     bool, hipStream_t);                                         \
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Prim<T>, \
                                  Flux<T>, Edge<T>, Grav<T>, DtRef, Counters, double*, bool,      \
                                  hipStream_t);                                                   \

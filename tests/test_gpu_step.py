@@ -238,6 +238,33 @@ def test_determinism_and_checkpoint_resume():
     assert d3["step"] == 3
 
 
+def test_ghost_fill_modes_agree():
+    """On a fully periodic box the fused path's stage ghost fills leave out
+    the x ghost layers (every reader takes the interior images instead);
+    a step on another path (here: all fluxes kept) refills them first.
+    Switching between the two mid-run gives bitwise the runs that never
+    switch, and both match the oracle."""
+    pb = P.random_smooth((9, 7, 70), seed=38)
+    runs = []
+    for plan in ((False,) * 6, (True,) * 6, (False, False, True, True, False, False)):
+        s = gpu_sim(pb)
+        for full in plan:
+            s.set_full_fluxes(full)
+            s.step(1)
+        runs.append(host_state(s))
+    for a, b, c in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(a, c)
+    o = oracle_of(pb)
+    s = gpu_sim(pb)
+    for _ in range(6):
+        dt = o.dt()
+        o.step(dt)
+        s.step(1, dt=dt)
+    err = field_errors(host_state(s), o.get_state())
+    assert max(err.values()) <= TOL, err
+
+
 def test_bad_state_rejected():
     from paper_1502_02935_amd import MHDError
     pb = P.random_smooth((8, 8, 8), seed=37)
