@@ -108,15 +108,18 @@ def error_run(pb, nsteps):
 
 # Algorithmic work of one launch of the fused flux sweep (the dominant
 # kernel: fluxes of the three lower faces of every interior cell and the
-# stage's conservative update).  Bytes per cell, FP32: read the 8 primitive
-# arrays, the 3 face-normal B and the 5 conserved cell values once (64 B);
-# write the 5 updated cell values, the 6 field components of the 3 fluxes
+# stage's conservative update).  Bytes per cell, FP32: read the primitive
+# arrays, the 3 face-normal B and the 5 conserved cell values once (64 B in
+# the corrector; 60 B in the predictor, whose primitive density is the
+# conserved density array it also reads; 62 B as the mean of the two
+# launches); write the 5 updated cell values, the 6 field components of the 3 fluxes
 # and the 3 mass-flux sign bytes (47 B), and the 5 hydrodynamic components
 # of the faces on tile seams, which the stage update adds (1/64 of the x,
 # 1/4 of the y and 1/16 of the z faces: 6.56 B).  Flops per face, counted on
 # the FP64 oracle over the turbulent-box face states (oracle/count_flops.py):
 # HLLD 400.6, MUSCL of 7 variables 154.0; the update adds 30 per cell.
-SWEEP_BYTES_PER_CELL_FP32 = 8 * 4 + 3 * 4 + 5 * 4 + 5 * 4 + 6 * 4 + 3 + 5 * 4 * (1 / 64 + 1 / 4 + 1 / 16)
+SWEEP_BYTES_PER_CELL_FP32 = (7.5 * 4 + 3 * 4 + 5 * 4 + 5 * 4 + 6 * 4 + 3
+                             + 5 * 4 * (1 / 64 + 1 / 4 + 1 / 16))
 HLLD_FLOPS_PER_FACE = 400.6
 MUSCL_FLOPS_PER_FACE = 154.0
 UPDATE_FLOPS_PER_CELL = 30.0

@@ -22,9 +22,10 @@ namespace {
 
 constexpr size_t kAlign = 256;
 // T arrays: two state sets (5 cells + 3 faces each), the primitives and cell
-// EMF of the current state (8 + 3), fluxes 21, edges 3, the primitives and
-// cell EMF of the half step (8 + 3).
-constexpr int kNumT = 62;
+// EMF of the current state (7 + 3: the primitive density is the state's own
+// density array), fluxes 21, edges 3, the primitives and cell EMF of the
+// half step (7 + 3).
+constexpr int kNumT = 60;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -259,17 +260,18 @@ struct mhd_ctx {
   }
   template <class T>
   Prim<T> prim(int set) const {  // set 0: of U, 1: of U* (the corrector's input)
-    const int q = set ? 51 : 16;
+    const int q = set ? 50 : 16;
     Prim<T> w;
-    for (int m = 0; m < 8; ++m) w.w[m] = (T*)arr(q + m);
-    for (int a = 0; a < 3; ++a) w.ec[a] = (T*)arr(q + 8 + a);
+    w.w[0] = (T*)arr(8 * set);  // rho of the primitives: the set's own cell density
+    for (int m = 1; m < 8; ++m) w.w[m] = (T*)arr(q + m - 1);
+    for (int a = 0; a < 3; ++a) w.ec[a] = (T*)arr(q + 7 + a);
     return w;
   }
   template <class T>
   Flux<T> flux() const {
     Flux<T> f;
     for (int a = 0; a < 3; ++a) {
-      for (int m = 0; m < 7; ++m) f.f[a][m] = (T*)arr(27 + 7 * a + m);
+      for (int m = 0; m < 7; ++m) f.f[a][m] = (T*)arr(26 + 7 * a + m);
       f.sg[a] = sg(a);
     }
     return f;
@@ -277,7 +279,7 @@ struct mhd_ctx {
   template <class T>
   Edge<T> edge() const {
     Edge<T> e;
-    for (int a = 0; a < 3; ++a) e.e[a] = (T*)arr(48 + a);
+    for (int a = 0; a < 3; ++a) e.e[a] = (T*)arr(47 + a);
     return e;
   }
   int nscalar() const { return cfg.nscalar; }
@@ -853,13 +855,15 @@ int mhd_debug_array(mhd_ctx* c, int what, void* d_out, size_t* n_out) {
   }
   int q;
   if (what < 21)
-    q = 27 + what;  // fluxes
+    q = 26 + what;  // fluxes
   else if (what < 24)
-    q = 48 + (what - 21);  // edges
+    q = 47 + (what - 21);  // edges
   else if (what < 27)
-    q = 59 + (what - 24);  // cell EMF of the corrector's input
+    q = 57 + (what - 24);  // cell EMF of the corrector's input
+  else if (what == 27)
+    q = 8;  // primitive density of the corrector's input: U*'s own density
   else
-    q = 51 + (what - 27);  // primitives of the corrector's input
+    q = 50 + (what - 28);  // other primitives of the corrector's input
   if (hipMemcpyAsync(d_out, c->arr(q), (size_t)c->g.np * es, hipMemcpyDeviceToDevice, c->st) !=
       hipSuccess)
     return MHD_E_HIP;

@@ -82,37 +82,45 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
   bool bx_only;
   if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, xl, c, bx_only)) return;
   const int p = pidx(g, c[0], c[1], c[2]);
+  // every source value is loaded before the first store (a store through
+  // one array pointer would otherwise order the next array's load after it)
+  T v[8];
+  bool put[8];
   // cell arrays
-  if (!bx_only) {
+  {
     bool inflow = false;
     int m[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       m[a] = map_axis(c[a], g.n[a], g.n[a], g.bc[2 * a], g.bc[2 * a + 1], inflow);
-    if (inflow) {
+    const bool moved = m[0] != c[0] || m[1] != c[1] || m[2] != c[2];
+    const int q0 = pidx(g, m[0], m[1], m[2]);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) s.u[q][p] = (T)ph.inflow_u[q];
-    } else if (m[0] != c[0] || m[1] != c[1] || m[2] != c[2]) {
-      const int q0 = pidx(g, m[0], m[1], m[2]);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) s.u[q][p] = s.u[q][q0];
+    for (int q = 0; q < 5; ++q) {
+      put[q] = !bx_only && (inflow || moved);
+      v[q] = !put[q] ? T(0) : (inflow ? (T)ph.inflow_u[q] : s.u[q][q0]);
     }
   }
   // face arrays: the normal axis has nf interior entries
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
-    if (bx_only && f != 0) continue;
     bool inflow = false;
     int m[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       m[a] = map_axis(c[a], a == f ? g.nf[a] : g.n[a], g.n[a], g.bc[2 * a], g.bc[2 * a + 1],
                       inflow);
-    if (inflow)
-      s.b[f][p] = (T)ph.inflow_b[f];
-    else if (m[0] != c[0] || m[1] != c[1] || m[2] != c[2])
-      s.b[f][p] = s.b[f][pidx(g, m[0], m[1], m[2])];
+    const bool moved = m[0] != c[0] || m[1] != c[1] || m[2] != c[2];
+    put[5 + f] = (!bx_only || f == 0) && (inflow || moved);
+    v[5 + f] = !put[5 + f] ? T(0)
+                           : (inflow ? (T)ph.inflow_b[f] : s.b[f][pidx(g, m[0], m[1], m[2])]);
   }
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+    if (put[q]) s.u[q][p] = v[q];
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+    if (put[5 + f]) s.b[f][p] = v[5 + f];
 }
 
 template <class T>
@@ -229,7 +237,9 @@ __device__ __forceinline__ void block_min_to(double r, double* part) {
 
 // Primitives and cell EMF of the cell at p from its conserved values and
 // its lower (b0*) and upper (b1*) faces.  One function for every pass that
-// writes primitives, so that they agree bitwise for the same inputs.
+// writes primitives, so that they agree bitwise for the same inputs.  The
+// primitive density is the state's own density array (w.w[0] is the cell
+// array of the conserved set the primitives belong to), not written here.
 template <class T>
 __device__ __forceinline__ void store_prim(T gam, const Prim<T>& w, int p, T rho, T mx, T my,
                                            T mz, T E, T b0x, T b1x, T b0y, T b1y, T b0z, T b1z,
@@ -239,7 +249,6 @@ __device__ __forceinline__ void store_prim(T gam, const Prim<T>& w, int p, T rho
   const T P = pressure(gam, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, bcx, bcy, bcz, rec);
   const T ir = rcp(rho);
   const T vx = mx * ir, vy = my * ir, vz = mz * ir;
-  w.w[0][p] = rho;
   w.w[1][p] = vx;
   w.w[2][p] = vy;
   w.w[3][p] = vz;

@@ -31,8 +31,8 @@ def test_workspace_bytes_valid():
     n32 = workspace_bytes(_cfg(precision=1))
     assert n64 > n32 > 0
     assert n64 % 256 == 0
-    # 62 padded arrays of 21 x 13 x 9 points at least
-    assert n64 >= 62 * 21 * 13 * 9 * 8
+    # 60 padded arrays of 21 x 13 x 9 points at least
+    assert n64 >= 60 * 21 * 13 * 9 * 8
 
 
 @pytest.mark.parametrize("bad", [
