@@ -359,8 +359,13 @@ struct SweepGrid {
   int ntx, nty, nch, nblk;
 };
 
+// FP32: compiled for at least 4 waves per SIMD (at most 128 VGPRs).  The
+// MUSCL variant then spills a few registers to scratch, which costs less
+// than the fourth wave gains; the FP64 variants would spill heavily and keep
+// the compiler's choice.
 template <class T, int RS, bool FO>
-__global__ void __launch_bounds__(kSwX* kSwY) k_sweep(Geo g, Physics ph, SweepGrid sgd,
+__global__ void __launch_bounds__(kSwX* kSwY)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_sweep(Geo g, Physics ph, SweepGrid sgd,
                                                       Prim<T> w, Cons<T> s0, Cons<T> s1,
                                                       Flux<T> f, Muscl<T> mu, Grav<T> gr,
                                                       DtRef dtr, Counters cnt, int store) {
