@@ -129,10 +129,12 @@ STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
 # Measured HBM traffic of one sweep launch at n = 256 (2 x TCC FETCH_SIZE +
 # WRITE_SIZE: a plain 1 GiB copy reads as 512 MiB of FETCH_SIZE and 1 GiB of
 # WRITE_SIZE), valid only for the kernel sources with this hash.
-PROFILED_SWEEP = {"sources_sha256_16": "a555ecc4052afd25", "n": 256,
+PROFILED_SWEEP = {"sources_sha256_16": "185d474cc6acd07b", "n": 256,
                   "bytes_per_launch": 2.442e9}
-# The sources that define the sweep's code (kernel, geometry, solver, source).
+# The sources that define the sweep's code (kernel, tile sizes and interfaces,
+# geometry, solver, source).
 KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_flux.hip",
+                  "paper_1502_02935_amd/csrc/mhd_kernels.hpp",
                   "paper_1502_02935_amd/csrc/mhd_span.hpp",
                   "paper_1502_02935_amd/csrc/mhd_physics.hpp",
                   "paper_1502_02935_amd/csrc/mhd_source.hpp")

@@ -33,8 +33,11 @@ struct Cons {  // conserved state: 5 cell arrays + 3 face arrays
   T* b[3];
 };
 
+// Primitives rho, vx, vy, vz, P, Bcx, Bcy, Bcz and cell EMF.  w[0] is the
+// density array of the conserved state the primitives belong to: the
+// primitive passes read it there and never write it.
 template <class T>
-struct Prim {  // primitives rho, vx, vy, vz, P, Bcx, Bcy, Bcz and cell EMF
+struct Prim {
   T* w[8];
   T* ec[3];
 };
