@@ -236,8 +236,11 @@ int mhd_set_full_fluxes(mhd_ctx *ctx, int enable);
    (x,y,z)), 7..13 y-face flux (frame (y,z,x)), 14..20 z-face flux (frame
    (z,x,y)), 21..23 edge EMF Ex, Ey, Ez, 24..26 cell EMF, 27..34 primitives
    rho, vx, vy, vz, P, Bcx, Bcy, Bcz, and with self-gravity 35 Psi and
-   36..38 its gradient at the cells.  *n_out gets the element count.
-   Synchronises. */
+   36..38 its gradient at the cells.  *n_out gets the element count.  On a
+   box periodic on all sides, steps without full fluxes, passive scalars,
+   learned correction or flux accumulation leave the x ghost layers of the
+   cell arrays unrefreshed (their readers take the interior images): read
+   the interior entries.  Synchronises. */
 int mhd_debug_array(mhd_ctx *ctx, int what, void *d_out, size_t *n_out);
 
 /* Kernel classes timed by the profiling hook. */
