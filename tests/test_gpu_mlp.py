@@ -230,6 +230,26 @@ def test_fused_correction_matches_oracle(precision):
     assert dg["n_mlp_gated"] == do["n_mlp_gated"]
 
 
+def test_mlp_after_plain_steps_refills_ghosts():
+    """Plain fused steps on a fully periodic box leave the x ghost layers
+    unrefreshed; the first step with the learned correction refills them,
+    so it equals the same step after plain steps that kept every ghost
+    layer (all fluxes kept)."""
+    pb = P.random_smooth((9, 7, 70), seed=15)
+    params = _t(_params(14, 0.05).astype(np.float32))
+    out = []
+    for full in (False, True):
+        s = gpu_sim(pb, precision=1)
+        s.set_full_fluxes(full)
+        s.step(2)
+        s.set_mlp(params, tau=0.5, jump=0.5, tau_flux=0.1)
+        s.step(1)
+        assert s.diag()["n_mlp_faces"] > 0
+        out.append(host_state(s))
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_trained_network_beats_plain_coarse():
     """What the trained network gains: on a held-out turbulent box (seed 205,
     not used in training), 40 fine 256^3 steps against 20 coarse 128^3 steps
