@@ -129,7 +129,7 @@ STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
 # Measured HBM traffic of one sweep launch at n = 256 (2 x TCC FETCH_SIZE +
 # WRITE_SIZE: a plain 1 GiB copy reads as 512 MiB of FETCH_SIZE and 1 GiB of
 # WRITE_SIZE), valid only for the kernel sources with this hash.
-PROFILED_SWEEP = {"sources_sha256_16": "185d474cc6acd07b", "n": 256,
+PROFILED_SWEEP = {"sources_sha256_16": "1b0a8b55cdc452f9", "n": 256,
                   "bytes_per_launch": 2.442e9}
 # The sources that define the sweep's code (kernel, tile sizes and interfaces,
 # geometry, solver, source).

@@ -365,10 +365,9 @@ struct SweepGrid {
 // the compiler's choice.
 template <class T, int RS, bool FO>
 __global__ void __launch_bounds__(kSwX* kSwY)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8))) k_sweep(Geo g, Physics ph, SweepGrid sgd,
-                                                      Prim<T> w, Cons<T> s0, Cons<T> s1,
-                                                      Flux<T> f, Muscl<T> mu, Grav<T> gr,
-                                                      DtRef dtr, Counters cnt, int store) {
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
+    k_sweep(Geo g, Physics ph, SweepGrid sgd, Prim<T> w, Cons<T> s0, Cons<T> s1, Flux<T> f,
+            Muscl<T> mu, Grav<T> gr, DtRef dtr, Counters cnt, int store) {
   static_assert(kSwX == 64, "a wave is one x-row of the tile");
   __shared__ T fy_up[2][5][kSwY][kSwX];
   // blocks -> (tile x, tile y, z-chunk), each XCD a contiguous range (the
