@@ -115,11 +115,11 @@ def error_run(pb, nsteps):
 # launches); write the 5 updated cell values, the 6 field components of the 3 fluxes
 # and the 3 mass-flux sign bytes (47 B), and the 5 hydrodynamic components
 # of the faces on tile seams, which the stage update adds (1/64 of the x,
-# 1/4 of the y and 1/16 of the z faces: 6.56 B).  Flops per face, counted on
+# 1/8 of the y and 1/16 of the z faces: 4.06 B).  Flops per face, counted on
 # the FP64 oracle over the turbulent-box face states (oracle/count_flops.py):
 # HLLD 400.6, MUSCL of 7 variables 154.0; the update adds 30 per cell.
 SWEEP_BYTES_PER_CELL_FP32 = (7.5 * 4 + 3 * 4 + 5 * 4 + 5 * 4 + 6 * 4 + 3
-                             + 5 * 4 * (1 / 64 + 1 / 4 + 1 / 16))
+                             + 5 * 4 * (1 / 64 + 1 / 8 + 1 / 16))
 HLLD_FLOPS_PER_FACE = 400.6
 MUSCL_FLOPS_PER_FACE = 154.0
 UPDATE_FLOPS_PER_CELL = 30.0
@@ -129,8 +129,8 @@ STEP_BYTES_PER_CELL_UPDATE_FP32 = 64.0  # read and write the 8 state fields
 # Measured HBM traffic of one sweep launch at n = 256 (2 x TCC FETCH_SIZE +
 # WRITE_SIZE: a plain 1 GiB copy reads as 512 MiB of FETCH_SIZE and 1 GiB of
 # WRITE_SIZE), valid only for the kernel sources with this hash.
-PROFILED_SWEEP = {"sources_sha256_16": "1b0a8b55cdc452f9", "n": 256,
-                  "bytes_per_launch": 2.442e9}
+PROFILED_SWEEP = {"sources_sha256_16": "22087e2bbb30120c", "n": 256,
+                  "bytes_per_launch": 2.331e9}
 # The sources that define the sweep's code (kernel, tile sizes and interfaces,
 # geometry, solver, source).
 KERNEL_SOURCES = ("paper_1502_02935_amd/csrc/mhd_flux.hip",

@@ -199,7 +199,7 @@ void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim
                    double* cfl_part, bool swept, hipStream_t st);
 // Tiles of the fused flux sweep: kSwX x kSwY cells a block (one wave per
 // x-row), walking kSwZ planes in z.
-constexpr int kSwX = 64, kSwY = 4, kSwZ = 16;
+constexpr int kSwX = 64, kSwY = 8, kSwZ = 16;
 // Fused flux sweep and conservative update of one stage (mhd_flux.hip):
 // the fluxes of every face of the interior cells with the Riemann solver
 // of ph and the reconstruction of m; into s1's cells the update of s0's
