@@ -33,7 +33,10 @@
  * Pins (the tests check this code against closed forms, textbook solutions,
  * independent formulations and invariants, not against itself): every part
  * above has at least one (the density and pressure floors, which the paper
- * leaves open, through the closed forms they give on uniform states).
+ * leaves open, through the closed forms they give on uniform states; the
+ * CFL step through hand-worked values for oblique states on unequal cells;
+ * the fixed potentials through the momentum a short step gives gas at rest,
+ * against central differences of the potentials as printed).
  * Parity unpinned: the exact value of the HLLD degenerate-state threshold
  * (pinned only to keep the flux bounded near it).
  *
