@@ -59,6 +59,7 @@ typedef enum mhd_status {
 } mhd_status;
 
 enum { MHD_FP64 = 0, MHD_FP32 = 1 };
+enum { MHD_RECOVERY_FP64 = 0, MHD_RECOVERY_OFF = 1 };
 enum { MHD_BC_PERIODIC = 0, MHD_BC_OUTFLOW = 1, MHD_BC_INFLOW = 2 };
 enum { MHD_RECON_PAPER = 0, MHD_RECON_KAPPA = 1, MHD_RECON_FIRST = 2 };
 enum {
@@ -104,7 +105,11 @@ typedef struct mhd_config {
                              rho, vx, vy, vz, P, Bx, By, Bz */
   int32_t riemann;        /* MHD_RIEMANN_*: HLLD (0, default), or the gas-dynamic HLL or HLLC */
   int32_t nscalar;        /* passive scalars, 0..MHD_MAX_SCALARS (see mhd_set_scalars) */
-  int32_t reserved[2];    /* must be 0 */
+  int32_t recovery;       /* MHD_FP32: MHD_RECOVERY_FP64 (0, default) redoes the pressure
+                             in FP64 in cells where E / (E - rho v^2/2 - B^2/2) > 64;
+                             MHD_RECOVERY_OFF (1) keeps every pressure in FP32 (to
+                             measure what the recovery gives).  Must be 0 in MHD_FP64 */
+  int32_t reserved;       /* must be 0 */
   int64_t npart;          /* N-body particles, >= 0; > 0 needs MHD_SRC_SELF_GRAVITY (see
                              mhd_set_particles) */
 } mhd_config;
@@ -329,7 +334,9 @@ int mhd_flux_accumulate(mhd_ctx *ctx, void *d_acc);
 int mhd_coarsen(mhd_ctx *ctx, void *d_cell5, void *d_bx, void *d_by, void *d_bz);
 
 /* Training samples from the last step of a (coarse) context, which must
-   have been taken with mhd_set_full_fluxes on:
+   have been taken with mhd_set_full_fluxes on (or with the learned
+   correction or a flux accumulator active); MHD_E_ARG otherwise, also
+   before the first step:
    for n faces d_faces [n][4] = (axis, i, j, k) with 0 <= i,j,k < n_axis,
    d_x [n][32] = features of the corrector state, d_t [n][8] = the MLP
    output that would turn its corrector flux into d_acc/dt_coarse (d_acc

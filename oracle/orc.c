@@ -96,6 +96,14 @@ int orc_threads(void) {
 #endif
 }
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Single-face physics in the face-normal frame (n, t1, t2).               */
 /* A frame state is w = rho, vn, vt1, vt2, P, Bt1, Bt2 plus the normal Bn. */

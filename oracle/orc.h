@@ -153,6 +153,8 @@ double orc_step(orc_grid *g, double dt);
 void orc_diag_get(orc_grid *g, orc_diag *out);
 /* Number of OpenMP threads the oracle loops use (1 if built without OpenMP). */
 int orc_threads(void);
+/* Sets the OpenMP thread count of the following calls (n >= 1). */
+void orc_set_threads(int n);
 
 /* Internal arrays left by the last corrector stage, interior-extended ranges,
    in the padded layout [nz+2g+1][ny+2g+1][nx+2g+1] with g = 2 (x fastest):

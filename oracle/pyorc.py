@@ -168,6 +168,7 @@ def load_oracle():
     L.orc_step.argtypes = [C.c_void_p, C.c_double]
     L.orc_diag_get.argtypes = [C.c_void_p, C.POINTER(_Diag)]
     L.orc_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
     L.orc_debug_array.restype = C.c_long
     L.orc_debug_array.argtypes = [C.c_void_p, C.c_int, dp]
     L.orc_padded_size.restype = C.c_long

@@ -16,6 +16,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "mhd.h")
 
 MHD_OK, MHD_E_ARG, MHD_E_HIP, MHD_E_STATE, MHD_E_UNSUPPORTED, MHD_E_WS = 0, -1, -2, -3, -4, -5
 MHD_FP64, MHD_FP32 = 0, 1
+RECOVERY_FP64, RECOVERY_OFF = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_PAPER, RECON_KAPPA, RECON_FIRST = 0, 1, 2
 RIEMANN_HLLD, RIEMANN_HLL, RIEMANN_HLLC = 0, 1, 2
@@ -37,7 +38,8 @@ class mhd_config(C.Structure):
         ("inflow", C.c_double * 8),
         ("riemann", C.c_int32),
         ("nscalar", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("recovery", C.c_int32),
+        ("reserved", C.c_int32),
         ("npart", C.c_int64),
     ]
 

@@ -101,8 +101,9 @@ bool config_ok(const mhd_config* c) {
   if (c->nscalar < 0 || c->nscalar > MHD_MAX_SCALARS) return false;
   if (c->npart < 0 || c->npart > 0x7fffffffll) return false;
   if (c->npart > 0 && c->source != MHD_SRC_SELF_GRAVITY) return false;
-  for (int q = 0; q < 2; ++q)
-    if (c->reserved[q] != 0) return false;
+  if (c->reserved != 0) return false;
+  if (c->recovery != MHD_RECOVERY_FP64 && c->recovery != MHD_RECOVERY_OFF) return false;
+  if (c->precision == MHD_FP64 && c->recovery != MHD_RECOVERY_FP64) return false;
   Geo g;
   if (!geo_of(c, &g)) return false;
   // the flux kernel addresses every padded array with 32-bit byte offsets
@@ -251,6 +252,10 @@ struct mhd_ctx {
   bool xg_stale = false;
   // keep every component of every face's flux in memory (mhd_set_full_fluxes)
   bool full_fluxes = false;
+  // the last step kept every component of its corrector fluxes (full
+  // fluxes, the learned correction or the flux accumulation was on):
+  // mhd_mlp_samples reads them
+  bool fluxes_kept = false;
   template <class T>
   Cons<T> cons(int set) const {  // set 0: U (t^n), 1: U* (half step)
     Cons<T> s;
@@ -409,6 +414,7 @@ Physics physics_of(const mhd_config* c) {
   for (int q = 0; q < 4; ++q) ph.src[q] = c->src[q];
   ph.rho_floor = c->rho_floor;
   ph.p_floor = c->p_floor;
+  ph.recover = c->recovery == MHD_RECOVERY_FP64;
   const double* q = c->inflow;
   ph.inflow_u[0] = q[0];
   ph.inflow_u[1] = q[0] * q[1];
@@ -424,6 +430,7 @@ int hip_status() {
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? MHD_OK : MHD_E_HIP;
 }
+
 
 template <class T>
 void enqueue_step(mhd_ctx* c, DtRef dt) {
@@ -453,6 +460,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   // accumulation needs every face's full flux in memory
   const bool swept = !c->mlp_params && !c->flux_acc;
   const int store = c->full_fluxes ? 2 : (ns > 0 ? 1 : 0);
+  c->fluxes_kept = !swept || c->full_fluxes;
   // x ghost layers left out of the stages' ghost fills: only where nothing
   // of this step reads them (fully periodic box, fused path, no passive
   // scalar, no full fluxes kept for samples)
@@ -960,6 +968,8 @@ int mhd_mlp_samples(mhd_ctx* c, const void* d_acc, double dt_coarse, int64_t n,
                     const int32_t* d_faces, float* d_x, float* d_t, uint8_t* d_mask) {
   if (!c || n < 0 || !(dt_coarse > 0.0)) return MHD_E_ARG;
   if (n > 0 && (!d_acc || !d_faces || !d_x || !d_t || !d_mask)) return MHD_E_ARG;
+  // the last step must have left every component of its corrector fluxes
+  if (!c->fluxes_kept) return MHD_E_ARG;
 
   if (n == 0) return MHD_OK;
   if (c->cfg.precision == MHD_FP64) {

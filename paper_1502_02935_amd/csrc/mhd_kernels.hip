@@ -145,7 +145,8 @@ void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, bool x_lite, hipS
 
 template <class T>
 __device__ __forceinline__ T pressure(T gam, T rho, T mx, T my, T mz, T E, T b0x, T b1x, T b0y,
-                                      T b1y, T b0z, T b1z, T& bcx, T& bcy, T& bcz, bool& rec) {
+                                      T b1y, T b0z, T b1z, T& bcx, T& bcy, T& bcz, bool& rec,
+                                      bool recover) {
 #pragma clang fp contract(on)
   bcx = T(0.5) * (b0x + b1x);
   bcy = T(0.5) * (b0y + b1y);
@@ -155,7 +156,7 @@ __device__ __forceinline__ T pressure(T gam, T rho, T mx, T my, T mz, T E, T b0x
   const T eint = E - ke - me;
   rec = false;
   if constexpr (sizeof(T) == 4) {
-    if (!(T(64) * eint > E)) {
+    if (recover && !(T(64) * eint > E)) {
       const double bx = 0.5 * ((double)b0x + (double)b1x);
       const double by = 0.5 * ((double)b0y + (double)b1y);
       const double bz = 0.5 * ((double)b0z + (double)b1z);
@@ -243,10 +244,11 @@ __device__ __forceinline__ void block_min_to(double r, double* part) {
 template <class T>
 __device__ __forceinline__ void store_prim(T gam, const Prim<T>& w, int p, T rho, T mx, T my,
                                            T mz, T E, T b0x, T b1x, T b0y, T b1y, T b0z, T b1z,
-                                           bool& rec) {
+                                           bool& rec, bool recover) {
 #pragma clang fp contract(on)
   T bcx, bcy, bcz;
-  const T P = pressure(gam, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, bcx, bcy, bcz, rec);
+  const T P = pressure(gam, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, bcx, bcy, bcz, rec,
+                       recover);
   const T ir = rcp(rho);
   const T vx = mx * ir, vy = my * ir, vz = mz * ir;
   w.w[1][p] = vx;
@@ -274,7 +276,8 @@ __global__ void __launch_bounds__(kSpanThreads) k_prim(Geo g, Physics ph, Span s
     const T rho = s.u[0][p], mx = s.u[1][p], my = s.u[2][p], mz = s.u[3][p], E = s.u[4][p];
     const T b0x = s.b[0][p], b1x = s.b[0][p + 1], b0y = s.b[1][p], b1y = s.b[1][p + g.sy];
     const T b0z = s.b[2][p], b1z = s.b[2][p + g.sz];
-    store_prim((T)ph.gamma, w, p, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, rec);
+    store_prim((T)ph.gamma, w, p, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, rec,
+               ph.recover);
     if constexpr (CFL) {
       if (pt.i >= 0 && pt.i < g.n[0] && pt.j >= 0 && pt.j < g.n[1] && pt.k >= 0 && pt.k < g.n[2])
         r = cfl_cell<T>(g, ph, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, cnt.status);
@@ -342,7 +345,7 @@ __global__ void __launch_bounds__(256) k_prim_shell(Geo g, Physics ph, Cons<T> s
     const int p = pidx(g, c[0], c[1], c[2]);
     store_prim((T)ph.gamma, w, p, s.u[0][p], s.u[1][p], s.u[2][p], s.u[3][p], s.u[4][p],
                s.b[0][p], s.b[0][p + 1], s.b[1][p], s.b[1][p + g.sy], s.b[2][p],
-               s.b[2][p + g.sz], rec);
+               s.b[2][p + g.sz], rec, ph.recover);
   }
   if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);
 }
@@ -703,7 +706,7 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
         T bcx, bcy, bcz;
         bool rq;
         const T P = pressure(gam, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
-                             bnew[2], bup[2], bcx, bcy, bcz, rq);
+                             bnew[2], bup[2], bcx, bcy, bcz, rq, ph.recover);
         if (P < (T)ph.p_floor) {
           E = E + ((T)ph.p_floor - P) / (gam - T(1));
           hit = true;
@@ -717,7 +720,7 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
         s1.u[4][p] = E;
       }
       store_prim(gam, wo, p, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1], bnew[2],
-                 bup[2], rec);
+                 bup[2], rec, ph.recover);
       if constexpr (CFL)
         r = cfl_cell<T>(g, ph, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
                         bnew[2], bup[2], cnt.status);

@@ -92,6 +92,7 @@ struct Physics {
   int source;
   double src[4];
   double rho_floor, p_floor;
+  bool recover;        // FP32: redo cancelling pressures in FP64
   double inflow_u[5];  // conserved ghost state of inflow sides
   double inflow_b[3];
 };

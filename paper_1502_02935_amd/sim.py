@@ -37,6 +37,7 @@ class MHDConfig:
     riemann: int = L.RIEMANN_HLLD
     nscalar: int = 0
     npart: int = 0
+    recovery: int = L.RECOVERY_FP64
 
     def to_c(self) -> L.mhd_config:
         c = L.mhd_config()
@@ -56,6 +57,7 @@ class MHDConfig:
         c.riemann = int(self.riemann)
         c.nscalar = int(self.nscalar)
         c.npart = int(self.npart)
+        c.recovery = int(self.recovery)
         return c
 
     @property

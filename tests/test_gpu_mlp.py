@@ -203,6 +203,29 @@ def test_samples_match_oracle_features_and_targets(bc):
     assert list(mb.cpu().numpy()) == [2, 2, 2]
 
 
+def test_samples_refused_without_kept_fluxes():
+    """mhd_mlp_samples reads every component of the last corrector fluxes:
+    refused (MHD_E_ARG) before the first step and after a fused step that
+    kept only what the EMFs need; accepted once a step kept them all."""
+    import torch
+    from paper_1502_02935_amd import MHDError
+    pb = P.random_smooth((16, 12, 10), seed=13)
+    s = gpu_sim(pb)
+    acc = torch.zeros((3, 7, 5, 6, 8), dtype=torch.float64, device="cuda")
+    faces = _t(np.array([[0, 1, 2, 3], [2, 4, 5, 6]], dtype=np.int32), torch.int32)
+    with pytest.raises(MHDError) as e:
+        s.mlp_samples(acc, 1e-3, faces)
+    assert e.value.code == -1
+    s.step(1)
+    with pytest.raises(MHDError) as e:
+        s.mlp_samples(acc, 1e-3, faces)
+    assert e.value.code == -1
+    s.set_full_fluxes(True)
+    s.step(1)
+    x, t, m = s.mlp_samples(acc, 1e-3, faces)
+    assert torch.isfinite(x).all() and torch.isfinite(t).all()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fused_correction_matches_oracle(precision):
     """A step with the gated, clipped MLP correction in the corrector sweep

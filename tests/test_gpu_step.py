@@ -6,7 +6,8 @@ import pytest
 
 from mhd_inputs import problems as P
 from oracle import pyorc as O
-from tests.gpu_util import field_errors, gpu_sim, host_state, needs_gpu, rel_err
+from tests.gpu_util import (field_errors, field_errors_group, gpu_sim, host_state, needs_gpu,
+                             rel_err)
 from tests.helpers import oracle_of
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -15,7 +16,7 @@ TOL = 1e-11
 
 
 def _parity(pb, nsteps, recon=O.RECON_PAPER, tol=TOL, check_dt=True, kappa=1.0 / 3.0,
-            riemann=O.RIEMANN_HLLD):
+            riemann=O.RIEMANN_HLLD, zero=()):
     o = oracle_of(pb, recon=recon, kappa=kappa, riemann=riemann)
     s = gpu_sim(pb, precision=0, recon=recon, kappa=kappa, riemann=riemann)
     if check_dt:
@@ -27,9 +28,10 @@ def _parity(pb, nsteps, recon=O.RECON_PAPER, tol=TOL, check_dt=True, kappa=1.0 /
         dts.append(dt)
         o.step(dt)
     s.step(nsteps, dt=dts)
-    err = field_errors(host_state(s), o.get_state())
+    got, ref = host_state(s), o.get_state()
+    err = field_errors(got, ref, zero=zero)
     bad = {k: v for k, v in err.items() if v > tol}
-    assert not bad, err
+    assert not bad, (err, field_errors_group(got, ref))
     dg, do = s.diag(), o.diag()
     assert dg["n_hll_fallback"] == do["n_hll_fallback"]
     assert dg["t"] == pytest.approx(do["t"], rel=1e-14)
@@ -120,7 +122,10 @@ def test_brio_wu_each_axis(axis):
     """1-D MHD Riemann problem (shocks, HLLD branches, minmod clipping) laid
     along each axis; the transverse axes have one cell."""
     pb = P.brio_wu(96, axis=axis)
-    _parity(pb, 25)
+    # v and B have no component along the frame's second transverse axis:
+    # those two fields are zero in exact arithmetic (rounding noise here)
+    t2 = "xyz"[(axis + 2) % 3]
+    _parity(pb, 25, zero=("M" + t2, "B" + t2))
 
 
 def test_ryu_jones():
