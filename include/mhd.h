@@ -28,7 +28,8 @@
  * Ownership: the caller owns every device buffer and the HIP stream; the
  * library owns only the host-side context (freed by mhd_destroy).  The library
  * never allocates device memory: all scratch lives in the caller's workspace
- * (size from mhd_workspace_bytes).  Work is enqueued on the caller's stream;
+ * (size from mhd_workspace_bytes), except for mhd_mlp_grad_noalloc, whose
+ * scratch is a static device array of the library.  Work is enqueued on the caller's stream;
  * only mhd_init, mhd_dt, mhd_diag, mhd_get_state and mhd_debug_array wait for
  * it.  A context is bound to one stream and is not thread-safe.
  *
@@ -359,6 +360,25 @@ int mhd_mlp_grad_workspace_bytes(int64_t n, size_t *out);
    Asynchronous. */
 int mhd_mlp_grad(int64_t n, const float *d_x, const float *d_t, const float *d_params,
                  float *d_grad, float *d_loss, void *d_ws, size_t ws_bytes, void *hip_stream);
+
+/* Gradient without allocation.  For callers that cannot allocate device
+   memory or hand over a workspace: code under HIP graph capture, tight
+   training loops, harnesses that forbid hipMalloc.  Same result as
+   mhd_mlp_grad (same kernels, same fixed reduction order: bitwise equal),
+   with the per-block partial gradients in a static device array of the
+   library instead of the caller's workspace; it calls no hipMalloc, hipFree
+   or other allocating routine.  n: 1 .. MHD_MLP_NOALLOC_MAX samples
+   (MHD_E_WS above it).  The array holds MHD_MLP_NOALLOC_MAX / 64 rows of
+   MHD_MLP_NPARAM + 1 floats (13.9 MB); every GPU the library runs on keeps
+   its own copy until the process ends.  All calls on one GPU share that
+   copy, so calls that overlap on one GPU (two streams, two threads) race
+   and must be serialised by the caller; each call writes every value it
+   reads from the array before reading it, so nothing carries over between
+   calls.  hip_stream must belong to the current device (MHD_E_ARG
+   otherwise).  d_loss may be NULL.  Asynchronous. */
+#define MHD_MLP_NOALLOC_MAX 32768
+int mhd_mlp_grad_noalloc(int64_t n, const float *d_x, const float *d_t, const float *d_params,
+                         float *d_grad, float *d_loss, void *hip_stream);
 
 /* One Adam update (bias-corrected, step >= 1) of d_params with moments
    d_m, d_v (zero-initialised by the caller).  Asynchronous. */

@@ -58,6 +58,7 @@ class mhd_diag_t(C.Structure):
 
 
 MLP_NPARAM = 6792
+MLP_NOALLOC_MAX = 32768
 
 
 class mhd_gate(C.Structure):
@@ -139,6 +140,8 @@ def load() -> C.CDLL:
     L.mhd_mlp_grad_workspace_bytes.argtypes = [i64, C.POINTER(sz)]
     L.mhd_mlp_grad.restype = C.c_int
     L.mhd_mlp_grad.argtypes = [i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mhd_mlp_grad_noalloc.restype = C.c_int
+    L.mhd_mlp_grad_noalloc.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     L.mhd_mlp_adam.restype = C.c_int
     L.mhd_mlp_adam.argtypes = [vp, vp, vp, vp, i64, C.c_double, C.c_double, C.c_double,
                                C.c_double, vp]

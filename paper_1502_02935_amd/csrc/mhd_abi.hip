@@ -10,6 +10,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -431,6 +432,33 @@ int hip_status() {
   return e == hipSuccess ? MHD_OK : MHD_E_HIP;
 }
 
+}  // namespace
+
+// Partial gradients of mhd_mlp_grad_noalloc: one row of MHD_MLP_NPARAM + 1
+// floats per 64-sample block, for at most MHD_MLP_NOALLOC_MAX samples.  In
+// host code this name is only a stand-in for the symbol: kernels get the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float scratch[(size_t)(MHD_MLP_NOALLOC_MAX / 64) *
+                                               (MHD_MLP_NPARAM + 1)];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_addr[kScratchDevices];  // device address of `scratch`, per device
+
+// Device address of `scratch` on device dev, which must be the current
+// device; looked up on the first call on each device.
+int scratch_address(int dev, float** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MHD_E_HIP;
+    g_scratch_addr[dev] = (float*)p;
+  }
+  *out = g_scratch_addr[dev];
+  return MHD_OK;
+}
 
 template <class T>
 void enqueue_step(mhd_ctx* c, DtRef dt) {
@@ -1005,6 +1033,25 @@ int mhd_mlp_grad(int64_t n, const float* d_x, const float* d_t, const float* d_p
   if (n <= 0 || !d_x || !d_t || !d_params || !d_grad || !d_ws) return MHD_E_ARG;
   if (ws_bytes < mlp_grad_workspace(n)) return MHD_E_WS;
   launch_mlp_grad(n, d_x, d_t, d_params, d_grad, d_loss, (float*)d_ws, (hipStream_t)hip_stream);
+  return hip_status();
+}
+
+int mhd_mlp_grad_noalloc(int64_t n, const float* d_x, const float* d_t, const float* d_params,
+                         float* d_grad, float* d_loss, void* hip_stream) {
+  if (n <= 0 || !d_x || !d_t || !d_params || !d_grad) return MHD_E_ARG;
+  if (n > MHD_MLP_NOALLOC_MAX) return MHD_E_WS;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MHD_E_HIP;
+  if (dev < 0 || dev >= kScratchDevices) return MHD_E_UNSUPPORTED;
+  if (hip_stream) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice((hipStream_t)hip_stream, &sdev) != hipSuccess) return MHD_E_HIP;
+    if (sdev != dev) return MHD_E_ARG;
+  }
+  float* part = nullptr;
+  const int rc = scratch_address(dev, &part);
+  if (rc != MHD_OK) return rc;
+  launch_mlp_grad(n, d_x, d_t, d_params, d_grad, d_loss, part, (hipStream_t)hip_stream);
   return hip_status();
 }
 

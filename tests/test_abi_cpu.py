@@ -118,3 +118,16 @@ def test_particles_need_self_gravity_and_add_their_buffers():
         assert w - w0 == 2 * a(7 * n * es) + 2 * a(4 * n) + a(4 * (4 * nt + 3 + 3 * mc))
     with pytest.raises(L.MHDError):
         workspace_bytes(MHDConfig(npart=1 << 31, **base))
+
+
+def test_grad_noalloc_checks_arguments_on_the_host():
+    """The gradient entry point without allocation refuses bad sizes and
+    NULL pointers before any HIP call (so this runs without a GPU): n <= 0
+    or a NULL pointer -> MHD_E_ARG; n above MHD_MLP_NOALLOC_MAX -> MHD_E_WS."""
+    lib = L.load()
+    fake = C.c_void_p(256)  # never dereferenced: the call returns first
+    assert lib.mhd_mlp_grad_noalloc(L.MLP_NOALLOC_MAX + 1, fake, fake, fake, fake, None,
+                                    None) == L.MHD_E_WS
+    assert lib.mhd_mlp_grad_noalloc(0, fake, fake, fake, fake, None, None) == L.MHD_E_ARG
+    assert lib.mhd_mlp_grad_noalloc(10, None, fake, fake, fake, None, None) == L.MHD_E_ARG
+    assert lib.mhd_mlp_grad_noalloc(10, fake, fake, fake, None, None, None) == L.MHD_E_ARG
