@@ -82,7 +82,7 @@ __device__ __forceinline__ int face_solve(const Physics& ph, const Stencil<T>& s
       l[v] = st.v[v][1];
       r[v] = st.v[v][2];
     } else {
-      muscl_lr(mu, st.v[v][0], st.v[v][1], st.v[v][2], st.v[v][3], l[v], r[v]);
+      muscl_lr_limited(mu, st.v[v][0], st.v[v][1], st.v[v][2], st.v[v][3], l[v], r[v]);
     }
   }
   const Face<T> L{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};

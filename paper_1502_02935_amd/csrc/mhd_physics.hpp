@@ -66,7 +66,21 @@ struct Muscl {
 };
 
 // Left/right interface values at the face between cells 1 and 2 of the
-// stencil w0..w3 (Eq. 12-14).
+// stencil w0..w3 (Eq. 12-14), limited (the caller knows the stage is not
+// first order).
+template <class T>
+__device__ __forceinline__ void muscl_lr_limited(const Muscl<T>& m, T w0, T w1, T w2, T w3,
+                                                 T& wl, T& wr) {
+#pragma clang fp contract(on)
+  const T back = w1 - w0, mid = w2 - w1, fwd = w3 - w2;
+  const T dl = m.cA * minmod(back, m.bA * mid) + m.cB * minmod(mid, m.bB * back);
+  const T dr = m.cA * minmod(fwd, m.bA * mid) + m.cB * minmod(mid, m.bB * fwd);
+  wl = w1 + dl;
+  wr = w2 - dr;
+}
+
+// The same with the run-time choice of first order (m.first_order: the
+// interface values are the two cell values).
 template <class T>
 __device__ __forceinline__ void muscl_lr(const Muscl<T>& m, T w0, T w1, T w2, T w3, T& wl,
                                          T& wr) {

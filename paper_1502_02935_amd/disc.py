@@ -4,13 +4,20 @@ potential, toroidal field, outflow sides).
 
     python -m paper_1502_02935_amd.disc precision [--nx 512 --ny 512 --nz 128 --steps 200]
     python -m paper_1502_02935_amd.disc large     [--nx 1024 --ny 1024 --nz 256 --steps 100]
+    python -m paper_1502_02935_amd.disc attribution [--nx 512 --ny 512 --nz 128 --steps 200]
 
 precision: FP32 bulk against the FP64 path from one FP32-rounded state with
 the FP64 run's time steps (L1 and Linf per field), plus the throughput of
 both precisions with their own device CFL steps.  large: throughput of the
 FP32 path on the largest one-GPU machine (same profiles on a 48 x 48 x 12 kpc
-box, so the cell size is that of the 512 x 512 x 128 slab).
-Prints one JSON line.
+box, so the cell size is that of the 512 x 512 x 128 slab).  attribution:
+where the FP32 error comes from -- the FP64 path with chosen conserved
+fields rounded to FP32 after every step (storage alone, per field), the
+FP32 path, and the FP64 path from a state whose E is perturbed by 1e-12
+(how much the flow amplifies a small difference), each against the plain
+FP64 run with the same steps, with the share of the density error in
+bands of density.
+Prints one JSON line (attribution: one per run).
 """
 from __future__ import annotations
 
@@ -117,6 +124,82 @@ def precision(nx, ny, nz, steps, seed=1):
     return res
 
 
+def _banded(a, b, tag):
+    """L1 per field of state b against a, plus the density error by density
+    band (share of the summed |d rho| and mean relative error per band)."""
+    out = {"run": tag, "L1": {k: v["L1_rel"] for k, v in _errors(a, b).items()}}
+    rho = a[0][0]
+    e = (b[0][0].double() - rho).abs()
+    tot = float(e.sum())
+    bands = {}
+    for lo, hi in ((0.1, 1e30), (1e-2, 0.1), (1e-3, 1e-2), (0.0, 1e-3)):
+        m = (rho >= lo) & (rho < hi)
+        n = int(m.sum())
+        bands["rho>=%g" % lo] = {"cells": n, "share": float(e[m].sum()) / tot if tot > 0 else 0.0,
+                                 "rel": float((e[m] / rho[m]).mean()) if n else 0.0}
+    out["rho_bands"] = bands
+    return out
+
+
+def _fp64_run(pb, dts, round_fields=(), perturb=0.0):
+    """FP64 run with the given steps; round_fields: conserved fields (0-4
+    cells rho, Mx, My, Mz, E; 5-7 faces) rounded to FP32 after every step
+    (a restart from the rounded state, bitwise what continuing would give);
+    perturb: relative Gaussian perturbation of E at the start."""
+    c5 = torch.as_tensor(pb.cell5, device="cuda")
+    b = [torch.as_tensor(x, device="cuda") for x in (pb.bx, pb.by, pb.bz)]
+    if perturb:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        c5 = c5.clone()
+        c5[4] *= 1.0 + perturb * torch.randn(c5[4].shape, device="cuda", generator=g,
+                                             dtype=torch.float64)
+    cfg = config_from_problem(pb, precision=L.MHD_FP64)
+    s = Sim(cfg, c5, *b)
+    if not round_fields:
+        s.step(len(dts), dt=dts)
+    else:
+        for dt in dts:
+            s.step(1, dt=dt)
+            c5, bx, by, bz = s.get_state()
+            s.close()
+            del s
+            for m in round_fields:
+                t = c5[m] if m < 5 else (bx, by, bz)[m - 5]
+                t.copy_(t.float().double())
+            s = Sim(cfg, c5, bx, by, bz)
+    out = s.get_state()
+    s.close()
+    return out
+
+
+def attribution(nx, ny, nz, steps, seed=1):
+    pb = _problem(nx, ny, nz, seed)
+    s64 = Sim(config_from_problem(pb, precision=L.MHD_FP64), pb.cell5, pb.bx, pb.by, pb.bz)
+    dts = []
+    for _ in range(steps):
+        dts.append(s64.dt())
+        s64.step(1, dt=dts[-1])
+    ref = s64.get_state()
+    s64.close()
+    del s64
+    rows = []
+    s32 = Sim(config_from_problem(pb, precision=L.MHD_FP32), pb.cell5, pb.bx, pb.by, pb.bz)
+    s32.step(steps, dt=dts)
+    rows.append(_banded(ref, s32.get_state(), "fp32"))
+    s32.close()
+    del s32
+    for tag, rf in (("fp64_rounded_all", (0, 1, 2, 3, 4, 5, 6, 7)), ("fp64_rounded_E", (4,)),
+                    ("fp64_rounded_M", (1, 2, 3)), ("fp64_rounded_rho", (0,)),
+                    ("fp64_rounded_B", (5, 6, 7))):
+        _log(tag)
+        rows.append(_banded(ref, _fp64_run(pb, dts, rf), tag))
+    rows.append(_banded(ref, _fp64_run(pb, dts, perturb=1e-12), "fp64_E_perturbed_1e-12"))
+    for r in rows:
+        r.update({"cells": pb.ncell, "steps": steps})
+    return rows
+
+
 def large(nx, ny, nz, steps, seed=1):
     pb = _problem(nx, ny, nz, seed)
     res = {"workload": "disc slab %dx%dx%d, %g x %g x %g kpc, FP32" % (
@@ -129,7 +212,7 @@ def large(nx, ny, nz, steps, seed=1):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("mode", choices=("precision", "large"))
+    ap.add_argument("mode", choices=("precision", "large", "attribution"))
     ap.add_argument("--nx", type=int, default=None)
     ap.add_argument("--ny", type=int, default=None)
     ap.add_argument("--nz", type=int, default=None)
@@ -138,6 +221,10 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.mode == "precision":
         r = precision(a.nx or 512, a.ny or 512, a.nz or 128, a.steps or 200, a.seed)
+    elif a.mode == "attribution":
+        for row in attribution(a.nx or 512, a.ny or 512, a.nz or 128, a.steps or 200, a.seed):
+            print(json.dumps(row), flush=True)
+        return
     else:
         r = large(a.nx or 1024, a.ny or 1024, a.nz or 256, a.steps or 100, a.seed)
     print(json.dumps(r), flush=True)

@@ -14,8 +14,14 @@ Beside each run two references:
   FP32 after every step, i.e. the error any path that keeps the state in
   FP32 has even with exact arithmetic;
 * the same FP32 path with the recovery switched off (every pressure in FP32).
-The bars are stated per field against the storage floor (L1) and as absolute
-maxima."""
+Bars: per field, L1 within 6x the storage floor (measured 1.6-3.5x: the
+FP32 fluxes add about as much as the storage), and the largest error of
+rho, M and E within 2e-5 of the field's largest value.  The face-B maxima
+are not bounded: a floor or limiter decision taken on the other side of its
+threshold moves B by up to 4e-3 of its scale in a cell of the Mach-25 box.
+With the recovery off the L1 errors move by a few per cent only: the FP32
+representation of E and the FP32 fluxes, not the cancellation in the
+pressure, set the error at these sizes."""
 import json
 
 import numpy as np
@@ -93,4 +99,6 @@ def test_fp32_in_recovery_regime(name):
     # the ghost shell): at least one of them takes the recovery on average
     assert rep["fp64_recovery_per_cell_step"] >= 1.0, rep
     for k, v in rep["L1_on"].items():
-        assert np.isfinite(v), (k, rep)
+        assert v <= 6.0 * rep["L1_floor"][k] + 1e-12, (k, rep)
+    for k in ("rho", "Mx", "My", "Mz", "E"):
+        assert rep["max_on"][k] <= 2e-5, (k, rep)

@@ -226,13 +226,22 @@ def test_samples_refused_without_kept_fluxes():
     assert torch.isfinite(x).all() and torch.isfinite(t).all()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_fused_correction_matches_oracle(precision):
+@pytest.mark.parametrize("case,precision", [("brio_wu", 0), ("box3d", 0), ("box3d", 1),
+                                            ("blast3d", 0)])
+def test_fused_correction_matches_oracle(case, precision):
     """A step with the gated, clipped MLP correction in the corrector sweep
-    against the oracle's (FP64, bf16-rounded MLP)."""
+    against the oracle's (FP64, bf16-rounded MLP): a shock tube (the gate
+    acts), a smooth 3-D box (all three face families corrected, FP64 and
+    FP32) and a 3-D box with an over-pressured sphere (gated faces in 3-D)."""
     import torch
-    # FP64: a shock tube exercises the gate; FP32: a 3-D box
-    pb = P.brio_wu(64) if precision == 0 else P.random_smooth((24, 20, 16), seed=13)
+    if case == "brio_wu":
+        pb = P.brio_wu(64)
+    else:
+        pb = P.random_smooth((24, 20, 16), seed=13)
+        if case == "blast3d":
+            X, Y, Z = P.cell_centres(pb)
+            hot = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2 < 0.2 ** 2
+            pb.cell5[4][hot] += 10.0  # P raised by 6.7 inside the sphere
     params = _params(14, 0.05).astype(np.float32).astype(np.float64)
     o = oracle_of(pb)
     o.set_mlp(params, tau=0.5, jump=0.5, tau_flux=0.1)
@@ -251,6 +260,8 @@ def test_fused_correction_matches_oracle(precision):
     assert dg["n_mlp_faces"] > 0
     assert abs(dg["n_mlp_faces"] - do["n_mlp_faces"]) <= 0.001 * do["n_mlp_faces"]
     assert dg["n_mlp_gated"] == do["n_mlp_gated"]
+    if case != "box3d":
+        assert do["n_mlp_gated"] > 0
 
 
 def test_mlp_after_plain_steps_refills_ghosts():
