@@ -9,8 +9,9 @@ CFL dt).
 
 Prints one JSON line: FP32-bulk throughput (the headline value), the FP64
 throughput, the FP32-vs-FP64 L1/Linf error per field after 100 steps from the
-same FP32-rounded state with the same time steps, the disc slab's (512 x 512
-x 128, 200 steps) FP32 error and throughput, the roofline position of the
+same FP32-rounded state with the same time steps (plain and compensated
+FP32), the disc slab's (512 x 512 x 128, 200 steps) FP32 errors and
+throughput, the compensated FP32 throughput, the roofline position of the
 dominant kernel (HIP events around each launch inside the timed region) and
 of the whole path, and the FP64 CPU oracle timed on a bounded sample of the
 same workload (all host threads, and one).
@@ -125,7 +126,7 @@ def error_run(pb, nsteps, precisions=(1,)):
         d = s.diag(check=False)
         s.close()
         del s
-        key = {1: "fp32"}.get(prec, "precision_%d" % prec)
+        key = {1: "fp32", 2: "fp32_comp"}.get(prec, "precision_%d" % prec)
         errs[key] = _field_errors(a, b)
         info[key] = {"fp64_recovery_cell_evals": d["n_fp64_recovery"], "status": d["status"],
                      "floor_hits": d["n_floor"], "n_degenerate": d["n_degenerate"],
@@ -288,7 +289,7 @@ def disc_leg(steps):
            "cells": pb.ncell, "fp32_cell_updates_per_s": pb.ncell * 20 / el,
            "fp32_ms_per_step": 1e3 * el / 20}
     log("  FP32 %.3f ms/step" % out["fp32_ms_per_step"])
-    errs, info = error_run(pb, steps)
+    errs, info = error_run(pb, steps, precisions=(1, 2))
     out["error_vs_fp64"] = errs
     out["error_run"] = info
     return out
@@ -353,6 +354,11 @@ def main():
     result["roofline"] = sweep_roofline(n, prof32)
     result["path_roofline"] = path_roofline(n, rate32)
 
+    log("compensated FP32 timed run")
+    elc, profc, _ = timed_run(pb, 2, args.steps, args.warmup)
+    result["fp32_comp"] = {"value": cells * args.steps / elc, "ms_per_step": 1e3 * elc / args.steps,
+                           "kernel_ms": {k: v[0] / v[1] for k, v in profc.items() if v[1]}}
+    log("  %.3f ms/step" % (1e3 * elc / args.steps))
     if not args.no_fp64:
         log("FP64 timed run")
         el64, prof64, d64 = timed_run(pb, 0, args.steps, args.warmup)
@@ -361,8 +367,9 @@ def main():
         log("  %.3f ms/step" % (1e3 * el64 / args.steps))
     if not args.no_error:
         log("FP32 vs FP64 error run, %d steps" % args.err_steps)
-        errs, info = error_run(pb, args.err_steps)
+        errs, info = error_run(pb, args.err_steps, precisions=(1, 2))
         result["error_fp32_vs_fp64"] = errs["fp32"]
+        result["error_fp32_comp_vs_fp64"] = errs["fp32_comp"]
         info["reference"] = ("FP64 GPU path from the same FP32-rounded state with the same "
                              "steps (its parity with the FP64 oracle: <= 1e-11 per field)")
         result["error_run"] = info

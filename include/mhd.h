@@ -16,8 +16,8 @@
  * U^n and B^n by dt.
  *
  * Memory layout of every state array handed across this ABI (device memory,
- * x fastest, interior cells only, element type double for MHD_FP64 and float
- * for MHD_FP32):
+ * x fastest, interior cells only, element type double for MHD_FP64 and
+ * MHD_FP32_COMP, float for MHD_FP32):
  *     cell5 : [5][nz][ny][nx]     rho, Mx, My, Mz, E
  *     bx    : [nz][ny][nx + ox]   face (i,j,k) at x0 + i dx
  *     by    : [nz][ny + oy][nx]
@@ -59,7 +59,21 @@ typedef enum mhd_status {
   MHD_E_WS = -5            /* workspace too small or misaligned */
 } mhd_status;
 
-enum { MHD_FP64 = 0, MHD_FP32 = 1 };
+/* Precision of a context.  MHD_FP32: FP32 bulk; pressure redone in FP64
+   where it cancels (see recovery), FP64 time step and sums.  MHD_FP32_COMP:
+   compensated FP32 -- the 5 cell values rho, M, E kept as pairs of FP32
+   numbers (hi = the value rounded to FP32, lo = the rounding of the rest:
+   about 48 significant bits), each stage's increment (FP32 fluxes and
+   reconstruction, as in MHD_FP32) added to the pairs in FP64, every
+   pressure, primitive, time step and sum computed from the pairs' FP64
+   values; face B in FP32.  Its state arrays across this ABI are double (the
+   pairs' exact values; mhd_init rounds the faces to FP32 and splits the
+   cells into pairs, so a state copied out and back in is the same state);
+   its other arrays (passive scalars, particles, mhd_debug_array) are float.
+   The training entry points (mhd_flux_accumulate, mhd_coarsen,
+   mhd_mlp_samples) return MHD_E_UNSUPPORTED for it; n_fp64_recovery stays
+   0. */
+enum { MHD_FP64 = 0, MHD_FP32 = 1, MHD_FP32_COMP = 2 };
 enum { MHD_RECOVERY_FP64 = 0, MHD_RECOVERY_OFF = 1 };
 enum { MHD_BC_PERIODIC = 0, MHD_BC_OUTFLOW = 1, MHD_BC_INFLOW = 2 };
 enum { MHD_RECON_PAPER = 0, MHD_RECON_KAPPA = 1, MHD_RECON_FIRST = 2 };
@@ -90,7 +104,7 @@ typedef struct mhd_config {
   int32_t nx, ny, nz;     /* interior cells, each >= 1; a padded array,
                              (nx+5)(ny+5)(nz+5) elements, must stay below
                              2^31 elements and 4 GiB */
-  int32_t precision;      /* MHD_FP64 or MHD_FP32 (FP32 bulk, FP64 where cancellation bites) */
+  int32_t precision;      /* MHD_FP64, MHD_FP32 or MHD_FP32_COMP (see above) */
   int32_t bc[6];          /* -x, +x, -y, +y, -z, +z; periodic must be set on both sides */
   double x0, y0, z0;      /* lower corner of the domain */
   double dx, dy, dz;      /* cell sizes, > 0 */
@@ -109,7 +123,8 @@ typedef struct mhd_config {
   int32_t recovery;       /* MHD_FP32: MHD_RECOVERY_FP64 (0, default) redoes the pressure
                              in FP64 in cells where E / (E - rho v^2/2 - B^2/2) > 64;
                              MHD_RECOVERY_OFF (1) keeps every pressure in FP32 (to
-                             measure what the recovery gives).  Must be 0 in MHD_FP64 */
+                             measure what the recovery gives).  Must be 0 in the other
+                             precisions */
   int32_t reserved;       /* must be 0 */
   int64_t npart;          /* N-body particles, >= 0; > 0 needs MHD_SRC_SELF_GRAVITY (see
                              mhd_set_particles) */

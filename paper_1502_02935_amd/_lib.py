@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libmhd.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "mhd.h")
 
 MHD_OK, MHD_E_ARG, MHD_E_HIP, MHD_E_STATE, MHD_E_UNSUPPORTED, MHD_E_WS = 0, -1, -2, -3, -4, -5
-MHD_FP64, MHD_FP32 = 0, 1
+MHD_FP64, MHD_FP32, MHD_FP32_COMP = 0, 1, 2
 RECOVERY_FP64, RECOVERY_OFF = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_PAPER, RECON_KAPPA, RECON_FIRST = 0, 1, 2

@@ -27,6 +27,9 @@ constexpr size_t kAlign = 256;
 // density array), fluxes 21, edges 3, the primitives and cell EMF of the
 // half step (7 + 3).
 constexpr int kNumT = 60;
+// Compensated FP32 adds 15 FP32 arrays after those: the low parts of the 5
+// cell values of each state set (10), the stage increments of the cells (5).
+constexpr int kCompT = 15;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -78,7 +81,8 @@ bool geo_of(const mhd_config* c, Geo* g) {
 
 bool config_ok(const mhd_config* c) {
   if (!c) return false;
-  if (c->precision != MHD_FP64 && c->precision != MHD_FP32) return false;
+  if (c->precision != MHD_FP64 && c->precision != MHD_FP32 && c->precision != MHD_FP32_COMP)
+    return false;
   for (int q = 0; q < 6; ++q)
     if (c->bc[q] < MHD_BC_PERIODIC || c->bc[q] > MHD_BC_INFLOW) return false;
   if (!(c->dx > 0) || !(c->dy > 0) || !(c->dz > 0)) return false;
@@ -104,7 +108,7 @@ bool config_ok(const mhd_config* c) {
   if (c->npart > 0 && c->source != MHD_SRC_SELF_GRAVITY) return false;
   if (c->reserved != 0) return false;
   if (c->recovery != MHD_RECOVERY_FP64 && c->recovery != MHD_RECOVERY_OFF) return false;
-  if (c->precision == MHD_FP64 && c->recovery != MHD_RECOVERY_FP64) return false;
+  if (c->precision != MHD_FP32 && c->recovery != MHD_RECOVERY_FP64) return false;
   Geo g;
   if (!geo_of(c, &g)) return false;
   // the flux kernel addresses every padded array with 32-bit byte offsets
@@ -125,7 +129,7 @@ Layout layout_of(const mhd_config* c) {
   L.arr = align_up((size_t)g.np * es);
   L.arr8 = align_up((size_t)g.np);
   L.off_t = 0;
-  L.off_sg = L.off_t + kNumT * L.arr;
+  L.off_sg = L.off_t + (kNumT + (c->precision == MHD_FP32_COMP ? kCompT : 0)) * L.arr;
   L.off_misc = L.off_sg + 4 * L.arr8;  // 3 sign arrays + shock flags
   L.off_cnt = L.off_misc + align_up(64 * sizeof(double));
   L.off_cfl = L.off_cnt + align_up((size_t)kNumCounters * kCounterSlots * kCounterStride *
@@ -262,6 +266,24 @@ struct mhd_ctx {
     Cons<T> s;
     for (int m = 0; m < 5; ++m) s.u[m] = (T*)arr(8 * set + m);
     for (int a = 0; a < 3; ++a) s.b[a] = (T*)arr(8 * (set ^ fcur) + 5 + a);
+    for (int m = 0; m < 5; ++m) s.lo[m] = comp() ? (float*)arr(kNumT + 5 * set + m) : nullptr;
+    return s;
+  }
+  bool comp() const { return cfg.precision == MHD_FP32_COMP; }
+  // compensated FP32: the sweep's stage increments of the cells
+  Inc inc() const {
+    Inc d;
+    for (int m = 0; m < 5; ++m) d.du[m] = comp() ? (float*)arr(kNumT + 10 + m) : nullptr;
+    return d;
+  }
+  template <class T>
+  Cons<T> inc_cells() const {  // the increments as the cells of a destination set
+    Cons<T> s = cons<T>(0);
+    const Inc d = inc();
+    for (int m = 0; m < 5; ++m) {
+      s.u[m] = (T*)d.du[m];
+      s.lo[m] = nullptr;
+    }
     return s;
   }
   template <class T>
@@ -467,7 +489,13 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   const Cons<T> U = c->cons<T>(0), Us = c->cons<T>(1);
   // the corrector's result: U's cells in place, the new faces in the half
   // step's face arrays (which become U's at the end of the step)
-  const Cons<T> Un = {{U.u[0], U.u[1], U.u[2], U.u[3], U.u[4]}, {Us.b[0], Us.b[1], Us.b[2]}};
+  Cons<T> Un = U;
+  for (int a = 0; a < 3; ++a) Un.b[a] = Us.b[a];
+  // compensated FP32: the sweeps leave the stage increments, which the
+  // stage updates add to the pairs
+  const bool comp = c->comp();
+  const Cons<T> Dn = comp ? c->inc_cells<T>() : Us, Dc = comp ? c->inc_cells<T>() : Un;
+  const Inc inc = c->inc();
   const Prim<T> W = c->prim<T>(0), Ws = c->prim<T>(1);
   const Flux<T> F = c->flux<T>();
   const Edge<T> E = c->edge<T>();
@@ -529,7 +557,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   // primitives
   c->mark(MHD_K_FLUX);
   if (swept) {
-    launch_sweep<T>(g, c->ph, W, U, Us, F, first, c->grav<T>(), half, cnt, store, c->st);
+    launch_sweep<T>(g, c->ph, W, U, Dn, F, first, c->grav<T>(), half, cnt, store, comp, c->st);
     c->mark(MHD_K_FLUX_OUTER);
     launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, store, c->st);
   } else {
@@ -538,7 +566,8 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, W, F, E, c->st);
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, Us, W, Ws, F, E, c->grav<T>(), half, cnt, nullptr, swept, c->st);
+  launch_update<T>(g, c->ph, U, Us, W, Ws, F, E, c->grav<T>(), half, cnt, nullptr, swept, inc,
+                   c->st);
   if (ns) {
     c->mark(MHD_K_SCALARS);
     launch_scalar_update<T>(g, W.w[0], F, Xn, Xn, Xh, ns, first, half, c->st);
@@ -566,7 +595,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     }
   } else if (swept) {
     c->mark(MHD_K_FLUX);
-    launch_sweep<T>(g, c->ph, Ws, Un, Un, F, second, c->grav<T>(), dt, cnt, store, c->st);
+    launch_sweep<T>(g, c->ph, Ws, Un, Dc, F, second, c->grav<T>(), dt, cnt, store, comp, c->st);
     c->mark(MHD_K_FLUX_OUTER);
     launch_flux_outer<T>(g, c->ph, Ws, Us, F, second, cnt, store, c->st);
   } else {
@@ -581,7 +610,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   launch_emf<T>(g, Ws, F, E, c->st);
   c->mark(MHD_K_UPDATE);
   launch_update<T>(g, c->ph, U, Un, Ws, W, F, E, c->grav<T>(), dt, cnt, c->cfl_part(), swept,
-                   c->st);
+                   inc, c->st);
   if (ns) {
     c->mark(MHD_K_SCALARS);
     launch_scalar_update<T>(g, Ws.w[0], F, Xn, Xh, Xn, ns, second, dt, c->st);
@@ -713,6 +742,11 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
                            (const double*)d_by, (const double*)d_bz, c->cons<double>(0), c->st);
     launch_ghosts<double>(c->g, c->ph, c->cons<double>(0), false, c->st);
     enqueue_cfl<double>(c);
+  } else if (c->comp()) {
+    launch_scatter_comp(c->g, (const double*)d_cell5, (const double*)d_bx, (const double*)d_by,
+                        (const double*)d_bz, c->cons<float>(0), c->st);
+    launch_ghosts<float>(c->g, c->ph, c->cons<float>(0), false, c->st);
+    enqueue_cfl<float>(c);
   } else {
     launch_scatter<float>(c->g, (const float*)d_cell5, (const float*)d_bx, (const float*)d_by,
                           (const float*)d_bz, c->cons<float>(0), c->st);
@@ -819,6 +853,9 @@ int mhd_get_state(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz)
   if (c->cfg.precision == MHD_FP64)
     launch_gather<double>(c->g, c->cons<double>(0), (double*)d_cell5, (double*)d_bx,
                           (double*)d_by, (double*)d_bz, c->st);
+  else if (c->comp())
+    launch_gather_comp(c->g, c->cons<float>(0), (double*)d_cell5, (double*)d_bx, (double*)d_by,
+                       (double*)d_bz, c->st);
   else
     launch_gather<float>(c->g, c->cons<float>(0), (float*)d_cell5, (float*)d_bx, (float*)d_by,
                          (float*)d_bz, c->st);
@@ -968,6 +1005,7 @@ int mhd_set_mlp(mhd_ctx* c, const float* d_params, const mhd_gate* gate) {
 
 int mhd_flux_accumulate(mhd_ctx* c, void* d_acc) {
   if (!c) return MHD_E_ARG;
+  if (d_acc && c->comp()) return MHD_E_UNSUPPORTED;
   if (d_acc && !coarsenable(c)) return MHD_E_UNSUPPORTED;
   c->flux_acc = d_acc;
   return MHD_OK;
@@ -975,6 +1013,7 @@ int mhd_flux_accumulate(mhd_ctx* c, void* d_acc) {
 
 int mhd_coarsen(mhd_ctx* c, void* d_cell5, void* d_bx, void* d_by, void* d_bz) {
   if (!c || !d_cell5 || !d_bx || !d_by || !d_bz) return MHD_E_ARG;
+  if (c->comp()) return MHD_E_UNSUPPORTED;
   if (!coarsenable(c)) return MHD_E_UNSUPPORTED;
   if (c->cfg.precision == MHD_FP64)
     launch_coarsen<double>(c->g, c->cons<double>(0), (double*)d_cell5, (double*)d_bx,
@@ -998,6 +1037,7 @@ int mhd_mlp_samples(mhd_ctx* c, const void* d_acc, double dt_coarse, int64_t n,
   if (n > 0 && (!d_acc || !d_faces || !d_x || !d_t || !d_mask)) return MHD_E_ARG;
   // the last step must have left every component of its corrector fluxes
   if (!c->fluxes_kept) return MHD_E_ARG;
+  if (c->comp()) return MHD_E_UNSUPPORTED;
 
   if (n == 0) return MHD_OK;
   if (c->cfg.precision == MHD_FP64) {

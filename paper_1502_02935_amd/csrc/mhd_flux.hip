@@ -363,7 +363,10 @@ struct SweepGrid {
 // MUSCL variant then spills a few registers to scratch, which costs less
 // than the fourth wave gains; the FP64 variants would spill heavily and keep
 // the compiler's choice.
-template <class T, int RS, bool FO>
+//
+// INC (compensated FP32): s0's cells are not read; s1's cells receive the
+// stage increment (the update without s0's value).
+template <class T, int RS, bool FO, bool INC>
 __global__ void __launch_bounds__(kSwX* kSwY)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
     k_sweep(Geo g, Physics ph, SweepGrid sgd, Prim<T> w, Cons<T> s0, Cons<T> s1, Flux<T> f,
@@ -472,8 +475,9 @@ __global__ void __launch_bounds__(kSwX* kSwY)
         }
         store_face<T, 2>(f, Fz, o, p, store, k == k0);
       }
+      // the stage's base value (INC: none, s1 gets the increment)
 #pragma unroll
-      for (int m = 0; m < 5; ++m) un[m] = gld(s0.u[m], o);
+      for (int m = 0; m < 5; ++m) un[m] = INC ? T(0) : gld(s0.u[m], o);
       // source from the stage's primitives at the cell (z-frame order of
       // the z-stencil: rho, vz, vx, vy, ...)
       cell_source<T>(g, ph, gr, i, j, k, p, zs.v[0][2], zs.v[2][2], zs.v[3][2], zs.v[1][2], S);
@@ -528,14 +532,21 @@ __global__ void __launch_bounds__(kSwX* kSwY)
 template <class T, int RS, bool FO>
 static void launch_sweep_rs(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s0, Cons<T> s1,
                             Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c,
-                            int store, hipStream_t st) {
+                            int store, bool inc, hipStream_t st) {
   SweepGrid sg;
   sg.ntx = (g.n[0] + kSwX - 1) / kSwX;
   sg.nty = (g.n[1] + kSwY - 1) / kSwY;
   sg.nch = (g.n[2] + kSwZ - 1) / kSwZ;
   sg.nblk = sg.ntx * sg.nty * sg.nch;
-  hipLaunchKernelGGL((k_sweep<T, RS, FO>), dim3((unsigned)sg.nblk), dim3(kSwX * kSwY), 0, st, g,
-                     ph, sg, w, s0, s1, f, m, gr, dt, c, store);
+  if constexpr (sizeof(T) == 4) {
+    if (inc) {
+      hipLaunchKernelGGL((k_sweep<T, RS, FO, true>), dim3((unsigned)sg.nblk),
+                         dim3(kSwX * kSwY), 0, st, g, ph, sg, w, s0, s1, f, m, gr, dt, c, store);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_sweep<T, RS, FO, false>), dim3((unsigned)sg.nblk), dim3(kSwX * kSwY), 0,
+                     st, g, ph, sg, w, s0, s1, f, m, gr, dt, c, store);
 }
 
 template <class T, int RS>
@@ -570,24 +581,24 @@ void launch_flux_outer(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Fl
 template <class T, int RS>
 static void launch_sweep_fo(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s0, Cons<T> s1,
                             Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c,
-                            int store, hipStream_t st) {
+                            int store, bool inc, hipStream_t st) {
   if (m.first_order)
-    launch_sweep_rs<T, RS, true>(g, ph, w, s0, s1, f, m, gr, dt, c, store, st);
+    launch_sweep_rs<T, RS, true>(g, ph, w, s0, s1, f, m, gr, dt, c, store, inc, st);
   else
-    launch_sweep_rs<T, RS, false>(g, ph, w, s0, s1, f, m, gr, dt, c, store, st);
+    launch_sweep_rs<T, RS, false>(g, ph, w, s0, s1, f, m, gr, dt, c, store, inc, st);
 }
 
 template <class T>
 void launch_sweep(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s0, Cons<T> s1,
-                  Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c, int store,
+                  Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c, int store, bool inc,
                   hipStream_t st) {
   const int sm = store;
   if (ph.riemann == kRiemannHLL)
-    launch_sweep_fo<T, kRiemannHLL>(g, ph, w, s0, s1, f, m, gr, dt, c, sm, st);
+    launch_sweep_fo<T, kRiemannHLL>(g, ph, w, s0, s1, f, m, gr, dt, c, sm, inc, st);
   else if (ph.riemann == kRiemannHLLC)
-    launch_sweep_fo<T, kRiemannHLLC>(g, ph, w, s0, s1, f, m, gr, dt, c, sm, st);
+    launch_sweep_fo<T, kRiemannHLLC>(g, ph, w, s0, s1, f, m, gr, dt, c, sm, inc, st);
   else
-    launch_sweep_fo<T, kRiemannHLLD>(g, ph, w, s0, s1, f, m, gr, dt, c, sm, st);
+    launch_sweep_fo<T, kRiemannHLLD>(g, ph, w, s0, s1, f, m, gr, dt, c, sm, inc, st);
 }
 
 template <class T, int RS>
@@ -624,9 +635,9 @@ template void launch_flux_outer<float>(const Geo&, const Physics&, Prim<float>, 
                                        Flux<float>, Muscl<float>, Counters, int, hipStream_t);
 template void launch_sweep<double>(const Geo&, const Physics&, Prim<double>, Cons<double>,
                                    Cons<double>, Flux<double>, Muscl<double>, Grav<double>,
-                                   DtRef, Counters, int, hipStream_t);
+                                   DtRef, Counters, int, bool, hipStream_t);
 template void launch_sweep<float>(const Geo&, const Physics&, Prim<float>, Cons<float>,
                                   Cons<float>, Flux<float>, Muscl<float>, Grav<float>, DtRef,
-                                  Counters, int, hipStream_t);
+                                  Counters, int, bool, hipStream_t);
 
 }  // namespace mhd

@@ -85,7 +85,9 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
   // every source value is loaded before the first store (a store through
   // one array pointer would otherwise order the next array's load after it)
   T v[8];
+  float vl[5];  // compensated FP32: the low parts of the cell pairs
   bool put[8];
+  const bool comp = s.lo[0] != nullptr;
   // cell arrays
   {
     bool inflow = false;
@@ -99,6 +101,16 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
     for (int q = 0; q < 5; ++q) {
       put[q] = !bx_only && (inflow || moved);
       v[q] = !put[q] ? T(0) : (inflow ? (T)ph.inflow_u[q] : s.u[q][q0]);
+      vl[q] = 0.f;
+      if (comp && put[q]) {
+        if (inflow) {
+          float h;
+          pair_split(ph.inflow_u[q], h, vl[q]);
+          v[q] = (T)h;
+        } else {
+          vl[q] = s.lo[q][q0];
+        }
+      }
     }
   }
   // face arrays: the normal axis has nf interior entries
@@ -117,7 +129,10 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q)
-    if (put[q]) s.u[q][p] = v[q];
+    if (put[q]) {
+      s.u[q][p] = v[q];
+      if (comp) s.lo[q][p] = vl[q];
+    }
 #pragma unroll
   for (int f = 0; f < 3; ++f)
     if (put[5 + f]) s.b[f][p] = v[5 + f];
@@ -263,6 +278,37 @@ __device__ __forceinline__ void store_prim(T gam, const Prim<T>& w, int p, T rho
   w.ec[2][p] = vy * bcx - vx * bcy;
 }
 
+// Compensated FP32: primitives and cell EMF of a cell from the FP64 values
+// of its pairs and its FP32 faces, every quantity in FP64 and rounded once
+// to FP32 (every pass that writes primitives uses this function).
+__device__ __forceinline__ void store_prim_comp(double gam, const Prim<float>& w, int p,
+                                                const double u[5], float b0x, float b1x,
+                                                float b0y, float b1y, float b0z, float b1z) {
+  const double bcx = 0.5 * ((double)b0x + (double)b1x);
+  const double bcy = 0.5 * ((double)b0y + (double)b1y);
+  const double bcz = 0.5 * ((double)b0z + (double)b1z);
+  const double ir = 1.0 / u[0];
+  const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+  const double ke = 0.5 * (u[1] * vx + u[2] * vy + u[3] * vz);
+  const double me = 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz);
+  w.w[1][p] = (float)vx;
+  w.w[2][p] = (float)vy;
+  w.w[3][p] = (float)vz;
+  w.w[4][p] = (float)((gam - 1.0) * (u[4] - ke - me));
+  w.w[5][p] = (float)bcx;
+  w.w[6][p] = (float)bcy;
+  w.w[7][p] = (float)bcz;
+  w.ec[0][p] = (float)(vz * bcy - vy * bcz);
+  w.ec[1][p] = (float)(vx * bcz - vz * bcx);
+  w.ec[2][p] = (float)(vy * bcx - vx * bcy);
+}
+
+// The FP64 values of the five cell pairs of s at p.
+__device__ __forceinline__ void load_pairs(const Cons<float>& s, int p, double u[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) u[m] = pair_value(s.u[m][p], s.lo[m][p]);
+}
+
 // CFL = true: the interior cells also give their time-step candidates,
 // folded per block into part[] (the step's own dt, from the same loads).
 template <class T, bool CFL>
@@ -276,10 +322,24 @@ __global__ void __launch_bounds__(kSpanThreads) k_prim(Geo g, Physics ph, Span s
     const T rho = s.u[0][p], mx = s.u[1][p], my = s.u[2][p], mz = s.u[3][p], E = s.u[4][p];
     const T b0x = s.b[0][p], b1x = s.b[0][p + 1], b0y = s.b[1][p], b1y = s.b[1][p + g.sy];
     const T b0z = s.b[2][p], b1z = s.b[2][p + g.sz];
-    store_prim((T)ph.gamma, w, p, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, rec,
-               ph.recover);
-    if constexpr (CFL) {
-      if (pt.i >= 0 && pt.i < g.n[0] && pt.j >= 0 && pt.j < g.n[1] && pt.k >= 0 && pt.k < g.n[2])
+    const bool inside =
+        pt.i >= 0 && pt.i < g.n[0] && pt.j >= 0 && pt.j < g.n[1] && pt.k >= 0 && pt.k < g.n[2];
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (s.lo[0]) {  // compensated FP32
+        double u[5];
+        load_pairs(s, p, u);
+        store_prim_comp(ph.gamma, w, p, u, b0x, b1x, b0y, b1y, b0z, b1z);
+        if (CFL && inside)
+          r = cfl_cell<double>(g, ph, u[0], u[1], u[2], u[3], u[4], b0x, b1x, b0y, b1y, b0z,
+                               b1z, cnt.status);
+        done = true;
+      }
+    }
+    if (!done) {
+      store_prim((T)ph.gamma, w, p, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, rec,
+                 ph.recover);
+      if (CFL && inside)
         r = cfl_cell<T>(g, ph, rho, mx, my, mz, E, b0x, b1x, b0y, b1y, b0z, b1z, cnt.status);
     }
   }
@@ -343,9 +403,20 @@ __global__ void __launch_bounds__(256) k_prim_shell(Geo g, Physics ph, Cons<T> s
   bool rec = false;
   if (shell_cell(g, (int)(blockIdx.x * 256u + threadIdx.x), c)) {
     const int p = pidx(g, c[0], c[1], c[2]);
-    store_prim((T)ph.gamma, w, p, s.u[0][p], s.u[1][p], s.u[2][p], s.u[3][p], s.u[4][p],
-               s.b[0][p], s.b[0][p + 1], s.b[1][p], s.b[1][p + g.sy], s.b[2][p],
-               s.b[2][p + g.sz], rec, ph.recover);
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (s.lo[0]) {  // compensated FP32
+        double u[5];
+        load_pairs(s, p, u);
+        store_prim_comp(ph.gamma, w, p, u, s.b[0][p], s.b[0][p + 1], s.b[1][p],
+                        s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz]);
+        done = true;
+      }
+    }
+    if (!done)
+      store_prim((T)ph.gamma, w, p, s.u[0][p], s.u[1][p], s.u[2][p], s.u[3][p], s.u[4][p],
+                 s.b[0][p], s.b[0][p + 1], s.b[1][p], s.b[1][p + g.sy], s.b[2][p],
+                 s.b[2][p + g.sz], rec, ph.recover);
   }
   if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);
 }
@@ -631,9 +702,12 @@ template <class T, bool CFL, bool SWEPT>
 __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span sp, Cons<T> s0,
                                                          Cons<T> s1, Prim<T> w, Prim<T> wo,
                                                          Flux<T> f, Edge<T> e, Grav<T> gr,
-                                                         DtRef dtr, Counters cnt, double* part) {
+                                                         DtRef dtr, Counters cnt, double* part,
+                                                         Inc inc) {
   const Pt pt = span_point(g, sp);
   bool hit = false, rec = false;
+  // compensated FP32: u below is the stage increment, added to s0's pairs
+  const bool comp = sizeof(T) == 4 && s0.lo[0] != nullptr;
   double r = INFINITY;
   if (pt.valid) {
     const int i = pt.i, j = pt.j, k = pt.k;
@@ -653,7 +727,7 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
       // the sweep left the update of every cell, without the fluxes of the
       // upper faces on its tile seams (last column, row or plane of a tile)
 #pragma unroll
-      for (int m = 0; m < 5; ++m) u[m] = s1.u[m][p];
+      for (int m = 0; m < 5; ++m) u[m] = comp ? (T)inc.du[m][p] : s1.u[m][p];
       if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
         store_u = i % kSwX == kSwX - 1 || i == g.n[0] - 1 || j % kSwY == kSwY - 1 ||
                   j == g.n[1] - 1 || k % kSwZ == kSwZ - 1 || k == g.n[2] - 1;
@@ -681,7 +755,7 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
         const T* fx = f.f[0][frame_comp(0, m)];
         const T* fy = f.f[1][frame_comp(1, m)];
         const T* fz = f.f[2][frame_comp(2, m)];
-        T v = s0.u[m][p];
+        T v = comp ? T(0) : s0.u[m][p];
         v -= rx * (fx[p + 1] - fx[p]);
         v -= ry * (fy[p + g.sy] - fy[p]);
         v -= rz * (fz[p + g.sz] - fz[p]);
@@ -694,7 +768,46 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
       const int b = (a + 1) % 3, c = (a + 2) % 3;
       if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) s1.b[a][p] = bnew[a];
     }
-    if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (comp && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+        // the new pairs: s0's value plus the increment, floors, pressure,
+        // primitives and time-step candidate in FP64
+        double v[5];
+        load_pairs(s0, p, v);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) v[m] += (double)u[m];
+        if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
+          if (v[0] < ph.rho_floor) {
+            v[0] = ph.rho_floor;
+            hit = true;
+          }
+          const double bcx = 0.5 * ((double)bnew[0] + (double)bup[0]);
+          const double bcy = 0.5 * ((double)bnew[1] + (double)bup[1]);
+          const double bcz = 0.5 * ((double)bnew[2] + (double)bup[2]);
+          const double P = (ph.gamma - 1.0) *
+                           (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0] -
+                            0.5 * (bcx * bcx + bcy * bcy + bcz * bcz));
+          if (P < ph.p_floor) {
+            v[4] += (ph.p_floor - P) / (ph.gamma - 1.0);
+            hit = true;
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          float h, l;
+          pair_split(v[m], h, l);
+          s1.u[m][p] = h;
+          s1.lo[m][p] = l;
+        }
+        store_prim_comp(ph.gamma, wo, p, v, bnew[0], bup[0], bnew[1], bup[1], bnew[2], bup[2]);
+        if constexpr (CFL)
+          r = cfl_cell<double>(g, ph, v[0], v[1], v[2], v[3], v[4], bnew[0], bup[0], bnew[1],
+                               bup[1], bnew[2], bup[2], cnt.status);
+        done = true;
+      }
+    }
+    if (!done && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
       const T gam = (T)ph.gamma;
       T rho = u[0], E = u[4];
       if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
@@ -740,24 +853,24 @@ int update_cfl_blocks(const Geo& g) { return update_span(g).nblk; }
 template <class T, bool SWEPT>
 static void launch_update_sw(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                              Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
-                             double* cfl_part, hipStream_t st) {
+                             double* cfl_part, Inc inc, hipStream_t st) {
   const Span sp = update_span(g);
   if (cfl_part)
     hipLaunchKernelGGL((k_update<T, true, SWEPT>), span_grid(sp), dim3(kSpanThreads), 0, st, g,
-                       ph, sp, s0, s1, w, wo, f, e, gr, dt, c, cfl_part);
+                       ph, sp, s0, s1, w, wo, f, e, gr, dt, c, cfl_part, inc);
   else
     hipLaunchKernelGGL((k_update<T, false, SWEPT>), span_grid(sp), dim3(kSpanThreads), 0, st, g,
-                       ph, sp, s0, s1, w, wo, f, e, gr, dt, c, nullptr);
+                       ph, sp, s0, s1, w, wo, f, e, gr, dt, c, nullptr, inc);
 }
 
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
-                   double* cfl_part, bool swept, hipStream_t st) {
+                   double* cfl_part, bool swept, Inc inc, hipStream_t st) {
   if (swept)
-    launch_update_sw<T, true>(g, ph, s0, s1, w, wo, f, e, gr, dt, c, cfl_part, st);
+    launch_update_sw<T, true>(g, ph, s0, s1, w, wo, f, e, gr, dt, c, cfl_part, inc, st);
   else
-    launch_update_sw<T, false>(g, ph, s0, s1, w, wo, f, e, gr, dt, c, cfl_part, st);
+    launch_update_sw<T, false>(g, ph, s0, s1, w, wo, f, e, gr, dt, c, cfl_part, inc, st);
 }
 
 // ------------------------------------------------------------------------
@@ -772,9 +885,21 @@ __global__ void __launch_bounds__(kSpanThreads) k_cfl(Geo g, Physics ph, Span sp
   double r = INFINITY;
   if (pt.valid) {
     const int p = pt.p;
-    r = cfl_cell<T>(g, ph, s.u[0][p], s.u[1][p], s.u[2][p], s.u[3][p], s.u[4][p], s.b[0][p],
-                    s.b[0][p + 1], s.b[1][p], s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz],
-                    cnt.status);
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (s.lo[0]) {  // compensated FP32: the pairs' values
+        double u[5];
+        load_pairs(s, p, u);
+        r = cfl_cell<double>(g, ph, u[0], u[1], u[2], u[3], u[4], s.b[0][p], s.b[0][p + 1],
+                             s.b[1][p], s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz],
+                             cnt.status);
+        done = true;
+      }
+    }
+    if (!done)
+      r = cfl_cell<T>(g, ph, s.u[0][p], s.u[1][p], s.u[2][p], s.u[3][p], s.u[4][p], s.b[0][p],
+                      s.b[0][p + 1], s.b[1][p], s.b[1][p + g.sy], s.b[2][p], s.b[2][p + g.sz],
+                      cnt.status);
   }
   block_min_to(r, part);
 }
@@ -880,6 +1005,12 @@ __global__ void __launch_bounds__(BX* BY) k_diag(Geo g, Physics ph, Cons<T> s, d
     if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
 #pragma unroll
       for (int m = 0; m < 5; ++m) v[m] = (double)s.u[m][p];
+      if constexpr (sizeof(T) == 4) {
+        if (s.lo[0]) {  // compensated FP32: the pairs' values
+#pragma unroll
+          for (int m = 0; m < 5; ++m) v[m] += (double)s.lo[m][p];
+        }
+      }
       const double b0[3] = {(double)s.b[0][p], (double)s.b[1][p], (double)s.b[2][p]};
       const double b1[3] = {(double)s.b[0][p + 1], (double)s.b[1][p + g.sy],
                             (double)s.b[2][p + g.sz]};
@@ -1002,6 +1133,62 @@ __global__ void __launch_bounds__(BX* BY) k_copy(Geo g, T* cell5, T* bx, T* by, 
         arr[a][q] = s.b[a][p];
     }
   }
+}
+
+// Compensated FP32: FP64 interior arrays <-> the cell pairs and FP32 faces.
+// A pair written out is its exact FP64 value, and splitting that value again
+// gives the same pair (a checkpoint resumes bit for bit).
+template <bool IN>
+__global__ void __launch_bounds__(BX* BY) k_copy_comp(Geo g, double* cell5, double* bx,
+                                                      double* by, double* bz, Cons<float> s) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i > g.n[0] || j > g.n[1]) return;
+  const int p = pidx(g, i, j, k);
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  if (i < nx && j < ny && k < nz) {
+    const size_t ncell = (size_t)nx * ny * nz;
+    const size_t q = ((size_t)k * ny + j) * nx + i;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      if (IN) {
+        float h, l;
+        pair_split(cell5[m * ncell + q], h, l);
+        s.u[m][p] = h;
+        s.lo[m][p] = l;
+      } else {
+        cell5[m * ncell + q] = pair_value(s.u[m][p], s.lo[m][p]);
+      }
+    }
+  }
+  double* arr[3] = {bx, by, bz};
+  const int cc[3] = {i, j, k};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int e[3] = {nx, ny, nz};
+    e[a] = g.nf[a];
+    if (cc[0] < e[0] && cc[1] < e[1] && cc[2] < e[2]) {
+      const size_t q = ((size_t)k * e[1] + j) * e[0] + i;
+      if (IN)
+        s.b[a][p] = (float)arr[a][q];
+      else
+        arr[a][q] = (double)s.b[a][p];
+    }
+  }
+}
+
+void launch_scatter_comp(const Geo& g, const double* cell5, const double* bx, const double* by,
+                         const double* bz, Cons<float> s, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_comp<true>), grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1),
+                     dim3(BX, BY), 0, st, g, const_cast<double*>(cell5), const_cast<double*>(bx),
+                     const_cast<double*>(by), const_cast<double*>(bz), s);
+}
+
+void launch_gather_comp(const Geo& g, Cons<float> s, double* cell5, double* bx, double* by,
+                        double* bz, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_comp<false>), grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1),
+                     dim3(BX, BY), 0, st, g, cell5, bx, by, bz, s);
 }
 
 template <class T>
@@ -1233,7 +1420,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
   template void launch_prim_shell<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,     \
                                      bool, hipStream_t);                                         \
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Prim<T>, \
-                                 Flux<T>, Edge<T>, Grav<T>, DtRef, Counters, double*, bool,      \
+                                 Flux<T>, Edge<T>, Grav<T>, DtRef, Counters, double*, bool, Inc, \
                                  hipStream_t);                                                   \
   template void launch_cfl_reduce<T>(const Geo&, const Physics&, double*, int, double*, Parts<T>, \
                                      hipStream_t);                                               \

@@ -27,11 +27,38 @@ struct Geo {
   double x0[3];
 };
 
+// Conserved state: 5 cell arrays + 3 face arrays.  Compensated FP32
+// (MHD_FP32_COMP): lo[m] holds the rest of cell value m, the value being
+// the pair u[m] + lo[m] evaluated in FP64 (u[m] is its FP32 rounding, lo[m]
+// the rounding of what remains: about 48 significant bits); lo[0] is null
+// in the other modes.
 template <class T>
-struct Cons {  // conserved state: 5 cell arrays + 3 face arrays
+struct Cons {
   T* u[5];
   T* b[3];
+  float* lo[5];
 };
+
+// Compensated FP32: the stage increments of the cells the fused sweep
+// leaves for the stage update to add to the pairs (null otherwise).
+struct Inc {
+  float* du[5];
+};
+
+// Value of a compensated pair.
+__device__ __forceinline__ double pair_value(float hi, float lo) {
+  return (double)hi + (double)lo;
+}
+// Split x into a pair: hi its FP32 rounding, lo the FP32 rounding of the
+// rest; then renormalised so that hi is the FP32 rounding of hi + lo (a pair
+// written out in FP64 and split again is the same pair).
+__device__ __forceinline__ void pair_split(double x, float& hi, float& lo) {
+  float h = (float)x;
+  float l = (float)(x - (double)h);
+  const double s = (double)h + (double)l;
+  hi = (float)s;
+  lo = (float)(s - (double)hi);
+}
 
 // Primitives rho, vx, vy, vz, P, Bcx, Bcy, Bcz and cell EMF.  w[0] is the
 // density array of the conserved state the primitives belong to: the
@@ -194,10 +221,15 @@ void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
 // time-step candidates as update_cfl_blocks(g) per-block minima.  swept:
 // s1's cells already hold the update of launch_sweep (seam fluxes still to
 // add) instead of f holding every face's flux.
+// Compensated FP32 (s0.lo non-null): the cells' new pairs are s0's pairs
+// plus the stage increment in FP64 (swept: the increments the sweep left in
+// inc, plus the seam fluxes; else the flux differences and dt S), always
+// stored; the floors, pressure, primitives and time-step candidates come
+// from the FP64 value.
 template <class T>
 void launch_update(const Geo& g, const Physics& ph, Cons<T> s0, Cons<T> s1, Prim<T> w,
                    Prim<T> wo, Flux<T> f, Edge<T> e, Grav<T> gr, DtRef dt, Counters c,
-                   double* cfl_part, bool swept, hipStream_t st);
+                   double* cfl_part, bool swept, Inc inc, hipStream_t st);
 // Tiles of the fused flux sweep: kSwX x kSwY cells a block (one wave per
 // x-row), walking kSwZ planes in z.
 constexpr int kSwX = 64, kSwY = 8, kSwZ = 16;
@@ -209,9 +241,11 @@ constexpr int kSwX = 64, kSwY = 8, kSwZ = 16;
 // components of the fluxes and the mass-flux signs of every face to f for
 // the EMFs; store 1: also the mass fluxes (passive scalars), 2: every
 // component.  s1's cells may be s0's.  launch_flux_outer completes f.
+// inc (compensated FP32): s0's cells are not read and s1's cells receive
+// the stage increment (the update without s0's value).
 template <class T>
 void launch_sweep(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s0, Cons<T> s1,
-                  Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c, int store,
+                  Flux<T> f, Muscl<T> m, Grav<T> gr, DtRef dt, Counters c, int store, bool inc,
                   hipStream_t st);
 // After launch_sweep: every component of the faces of the points in the
 // outer layer of the flux range, [-1, n]^3 without [0, n-1]^3 (the faces
@@ -296,6 +330,12 @@ void launch_scatter(const Geo& g, const T* cell5, const T* bx, const T* by, cons
                     Cons<T> s, hipStream_t st);
 template <class T>
 void launch_gather(const Geo& g, Cons<T> s, T* cell5, T* bx, T* by, T* bz, hipStream_t st);
+// Compensated FP32: FP64 interior arrays <-> the pairs of s (cells) and
+// its FP32 faces.
+void launch_scatter_comp(const Geo& g, const double* cell5, const double* bx, const double* by,
+                         const double* bz, Cons<float> s, hipStream_t st);
+void launch_gather_comp(const Geo& g, Cons<float> s, double* cell5, double* bx, double* by,
+                        double* bz, hipStream_t st);
 
 // learned correction: training and data pipeline (mhd_mlp.hip)
 void launch_mlp_forward(int64_t n, const float* x, const float* P, float* y, hipStream_t st);

@@ -189,6 +189,11 @@ def attribution(nx, ny, nz, steps, seed=1):
     rows.append(_banded(ref, s32.get_state(), "fp32"))
     s32.close()
     del s32
+    sc = Sim(config_from_problem(pb, precision=L.MHD_FP32_COMP), pb.cell5, pb.bx, pb.by, pb.bz)
+    sc.step(steps, dt=dts)
+    rows.append(_banded(ref, sc.get_state(), "fp32_comp"))
+    sc.close()
+    del sc
     for tag, rf in (("fp64_rounded_all", (0, 1, 2, 3, 4, 5, 6, 7)), ("fp64_rounded_E", (4,)),
                     ("fp64_rounded_M", (1, 2, 3)), ("fp64_rounded_rho", (0,)),
                     ("fp64_rounded_B", (5, 6, 7))):

@@ -62,6 +62,14 @@ class MHDConfig:
 
     @property
     def dtype(self):
+        """Element type of the state arrays handed across the ABI (FP64 for
+        MHD_FP64 and the compensated MHD_FP32_COMP, FP32 for MHD_FP32)."""
+        return torch.float32 if self.precision == L.MHD_FP32 else torch.float64
+
+    @property
+    def work_dtype(self):
+        """Element type of the working arrays (scalars, particles, debug
+        arrays, flux accumulator): FP32 in both FP32 forms."""
         return torch.float64 if self.precision == L.MHD_FP64 else torch.float32
 
     def face_shapes(self):
@@ -192,7 +200,7 @@ class Sim:
             L.check(self.L.mhd_flux_accumulate(self.ctx, None), "mhd_flux_accumulate")
             return getattr(self, "_acc", None)
         cfg = self.cfg
-        self._acc = torch.zeros((3, 7, cfg.nz // 2, cfg.ny // 2, cfg.nx // 2), dtype=cfg.dtype,
+        self._acc = torch.zeros((3, 7, cfg.nz // 2, cfg.ny // 2, cfg.nx // 2), dtype=cfg.work_dtype,
                                 device=self.device)
         L.check(self.L.mhd_flux_accumulate(self.ctx, _ptr(self._acc)), "mhd_flux_accumulate")
         return self._acc
@@ -219,7 +227,7 @@ class Sim:
         this context's last step (taken with set_full_fluxes on)."""
         n = faces.shape[0]
         assert faces.dtype == torch.int32 and faces.is_contiguous() and faces.shape == (n, 4)
-        assert acc.dtype == self.cfg.dtype and acc.is_contiguous()
+        assert acc.dtype == self.cfg.work_dtype and acc.is_contiguous()
         x = torch.empty((n, 32), dtype=torch.float32, device=self.device)
         t = torch.empty((n, 8), dtype=torch.float32, device=self.device)
         m = torch.empty(n, dtype=torch.uint8, device=self.device)
@@ -234,9 +242,9 @@ class Sim:
         [npart] (positions wrap into the box)."""
         cfg = self.cfg
         n = cfg.npart
-        xs = _dev(x, cfg.dtype, self.device)
-        vs = _dev(v, cfg.dtype, self.device)
-        ms = _dev(m, cfg.dtype, self.device)
+        xs = _dev(x, cfg.work_dtype, self.device)
+        vs = _dev(v, cfg.work_dtype, self.device)
+        ms = _dev(m, cfg.work_dtype, self.device)
         assert tuple(xs.shape) == (3, n) and tuple(vs.shape) == (3, n) and tuple(ms.shape) == (n,)
         L.check(self.L.mhd_set_particles(self.ctx, _ptr(xs), _ptr(vs), _ptr(ms)),
                 "mhd_set_particles")
@@ -244,7 +252,7 @@ class Sim:
     def get_particles(self):
         """(positions, velocities), each [3][npart] on the device."""
         cfg = self.cfg
-        x = torch.empty((3, cfg.npart), dtype=cfg.dtype, device=self.device)
+        x = torch.empty((3, cfg.npart), dtype=cfg.work_dtype, device=self.device)
         v = torch.empty_like(x)
         L.check(self.L.mhd_get_particles(self.ctx, _ptr(x), _ptr(v)), "mhd_get_particles")
         return x, v
@@ -254,13 +262,14 @@ class Sim:
     def set_scalars(self, rho_x):
         """Replace the passive scalars rho X_s ([nscalar][nz][ny][nx])."""
         cfg = self.cfg
-        a = _dev(rho_x, cfg.dtype, self.device)
+        a = _dev(rho_x, cfg.work_dtype, self.device)
         assert tuple(a.shape) == (cfg.nscalar, cfg.nz, cfg.ny, cfg.nx), a.shape
         L.check(self.L.mhd_set_scalars(self.ctx, _ptr(a)), "mhd_set_scalars")
 
     def get_scalars(self) -> torch.Tensor:
         cfg = self.cfg
-        a = torch.empty((cfg.nscalar, cfg.nz, cfg.ny, cfg.nx), dtype=cfg.dtype, device=self.device)
+        a = torch.empty((cfg.nscalar, cfg.nz, cfg.ny, cfg.nx), dtype=cfg.work_dtype,
+                        device=self.device)
         L.check(self.L.mhd_get_scalars(self.ctx, _ptr(a)), "mhd_get_scalars")
         return a
 
@@ -285,7 +294,7 @@ class Sim:
 
     def debug_array(self, what: int) -> torch.Tensor:
         cfg = self.cfg
-        out = torch.empty((cfg.nz + 5, cfg.ny + 5, cfg.nx + 5), dtype=cfg.dtype,
+        out = torch.empty((cfg.nz + 5, cfg.ny + 5, cfg.nx + 5), dtype=cfg.work_dtype,
                           device=self.device)
         n = C.c_size_t()
         L.check(self.L.mhd_debug_array(self.ctx, what, _ptr(out), C.byref(n)), "mhd_debug_array")

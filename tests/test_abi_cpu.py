@@ -37,7 +37,7 @@ def test_workspace_bytes_valid():
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-3), dict(dx=0.0), dict(dz=-1.0), dict(gamma=1.0), dict(cfl=0.0),
-    dict(cfl=1.5), dict(precision=2), dict(recon=5), dict(kappa=1.0), dict(source=9),
+    dict(cfl=1.5), dict(precision=3), dict(recon=5), dict(kappa=1.0), dict(source=9),
     dict(rho_floor=-1.0), dict(bc=(0, 1, 0, 0, 0, 0)), dict(bc=(7, 7, 0, 0, 0, 0)),
     dict(nx=1 << 21), dict(nx=2048, ny=2048, nz=1024), dict(nscalar=-1), dict(nscalar=9),
     dict(npart=-1), dict(npart=10),
@@ -131,3 +131,23 @@ def test_grad_noalloc_checks_arguments_on_the_host():
     assert lib.mhd_mlp_grad_noalloc(0, fake, fake, fake, fake, None, None) == L.MHD_E_ARG
     assert lib.mhd_mlp_grad_noalloc(10, None, fake, fake, fake, None, None) == L.MHD_E_ARG
     assert lib.mhd_mlp_grad_noalloc(10, fake, fake, fake, None, None, None) == L.MHD_E_ARG
+
+
+def test_compensated_precision_configuration():
+    """MHD_FP32_COMP: 15 FP32 arrays more than MHD_FP32 (the low parts of the
+    two state sets' cells, the stage increments); the recovery switch is an
+    MHD_FP32 option only."""
+    base = workspace_bytes(_cfg(precision=L.MHD_FP32))
+    comp = workspace_bytes(_cfg(precision=L.MHD_FP32_COMP))
+    arr = (16 + 5) * (8 + 5) * (4 + 5) * 4
+    arr = (arr + 255) // 256 * 256
+    assert comp == base + 15 * arr
+    lib = L.load()
+    n = C.c_size_t()
+    for prec in (L.MHD_FP64, L.MHD_FP32_COMP):
+        c = _cfg(precision=prec, recovery=L.RECOVERY_OFF).to_c()
+        assert lib.mhd_workspace_bytes(C.byref(c), C.byref(n)) == L.MHD_E_ARG
+    c = _cfg(precision=L.MHD_FP32, recovery=L.RECOVERY_OFF).to_c()
+    assert lib.mhd_workspace_bytes(C.byref(c), C.byref(n)) == L.MHD_OK
+    c = _cfg(precision=3).to_c()
+    assert lib.mhd_workspace_bytes(C.byref(c), C.byref(n)) == L.MHD_E_ARG
