@@ -667,15 +667,146 @@ void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st) {
 
 // CT update of the A-face at index q: B_A - dt (dE_C/db - dE_B/dc) with
 // (A, B, C) cyclic, rb = dt/d_B, rc = dt/d_C.
+// From values: the face's old field b, the C-edges at its lower and upper B
+// side, the B-edges at its lower and upper C side (every kernel that forms a
+// face uses this expression, so a face gets bitwise one value).
+template <class T>
+__device__ __forceinline__ T ct_value(T b, T rb, T ec_up, T ec, T rc, T eb_up, T eb) {
+#pragma clang fp contract(on)
+  return b - rb * (ec_up - ec) + rc * (eb_up - eb);
+}
+
 template <class T, int A>
 __device__ __forceinline__ T ct_face(const Geo& g, const Cons<T>& s0, const Edge<T>& e, int q,
                                      T rb, T rc) {
-#pragma clang fp contract(on)
   constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
   const T* Ec = e.e[C];
   const T* Eb = e.e[B];
-  return s0.b[A][q] - rb * (Ec[q + stride_of(g, B)] - Ec[q]) +
-         rc * (Eb[q + stride_of(g, C)] - Eb[q]);
+  return ct_value(s0.b[A][q], rb, Ec[q + stride_of(g, B)], Ec[q], rc, Eb[q + stride_of(g, C)],
+                  Eb[q]);
+}
+
+// The swept stage values of the interior cell (i, j, k) at p: u holds what
+// the sweep left (its update, or the compensated increment); the fluxes of
+// the cell's upper faces on the sweep's tile seams (the last column, row or
+// plane of a tile), which the sweep left to f, are subtracted.  Returns
+// whether the cell lies on a seam.
+template <class T>
+__device__ __forceinline__ bool add_seams(const Geo& g, const Flux<T>& f, int i, int j, int k,
+                                          int p, T rx, T ry, T rz, T u[5]) {
+  const bool sx = i % kSwX == kSwX - 1 || i == g.n[0] - 1;
+  const bool sy = j % kSwY == kSwY - 1 || j == g.n[1] - 1;
+  const bool sz = k % kSwZ == kSwZ - 1 || k == g.n[2] - 1;
+  if (sx) {
+    // face n of a periodic x axis is read at its image, face 0
+    const int q = g.nf[0] == g.n[0] && i == g.n[0] - 1 ? p + 1 - g.n[0] : p + 1;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) u[m] -= rx * f.f[0][frame_comp(0, m)][q];
+  }
+  if (sy) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) u[m] -= ry * f.f[1][frame_comp(1, m)][p + g.sy];
+  }
+  if (sz) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) u[m] -= rz * f.f[2][frame_comp(2, m)][p + g.sz];
+  }
+  return sx || sy || sz;
+}
+
+// Compensated FP32: the rest of an interior cell's stage update from its
+// new FP64 value v (s0's pair plus the increment): floors, the new pairs,
+// then the primitives and cell EMF into wo and, CFL, the time-step
+// candidate folded into the minimum r, both from the value the pairs hold
+// (as every kernel that reads the pairs back computes them).
+template <bool CFL>
+__device__ __forceinline__ void finish_comp(const Geo& g, const Physics& ph, const Cons<float>& s1,
+                                            const Prim<float>& wo, int p, double v[5],
+                                            const float bnew[3], const float bup[3],
+                                            const Counters& cnt, bool& hit, double& r) {
+  if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
+    if (v[0] < ph.rho_floor) {
+      v[0] = ph.rho_floor;
+      hit = true;
+    }
+    const double bcx = 0.5 * ((double)bnew[0] + (double)bup[0]);
+    const double bcy = 0.5 * ((double)bnew[1] + (double)bup[1]);
+    const double bcz = 0.5 * ((double)bnew[2] + (double)bup[2]);
+    const double P = (ph.gamma - 1.0) *
+                     (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0] -
+                      0.5 * (bcx * bcx + bcy * bcy + bcz * bcz));
+    if (P < ph.p_floor) {
+      v[4] += (ph.p_floor - P) / (ph.gamma - 1.0);
+      hit = true;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    float h, l;
+    pair_split(v[m], h, l);
+    s1.u[m][p] = h;
+    s1.lo[m][p] = l;
+    v[m] = pair_value(h, l);
+  }
+  store_prim_comp(ph.gamma, wo, p, v, bnew[0], bup[0], bnew[1], bup[1], bnew[2], bup[2]);
+  if constexpr (CFL)
+    r = fmin(r, cfl_cell<double>(g, ph, v[0], v[1], v[2], v[3], v[4], bnew[0], bup[0], bnew[1],
+                                 bup[1], bnew[2], bup[2], cnt.status));
+}
+
+// The rest of an interior cell's stage update, from its stage values u (or,
+// compensated, its increment) and its new faces (lower bnew, upper bup):
+// floors, the conserved values (stored where store_u, where a floor acts,
+// and always in compensated FP32), the primitives and cell EMF into wo and,
+// CFL, the cell's FP64 time-step candidate folded into the minimum r.  hit
+// and rec are set (never cleared) where a floor acts and where the FP32
+// pressure is recovered in FP64.
+template <class T, bool CFL>
+__device__ __forceinline__ void finish_cell(const Geo& g, const Physics& ph, const Cons<T>& s0,
+                                            const Cons<T>& s1, const Prim<T>& wo, int p, T u[5],
+                                            const T bnew[3], const T bup[3], bool store_u,
+                                            bool comp, const Counters& cnt, bool& hit, bool& rec,
+                                            double& r) {
+  if constexpr (sizeof(T) == 4) {
+    if (comp) {
+      // the new pairs: s0's value plus the increment
+      double v[5];
+      load_pairs(s0, p, v);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) v[m] += (double)u[m];
+      finish_comp<CFL>(g, ph, s1, wo, p, v, bnew, bup, cnt, hit, r);
+      return;
+    }
+  }
+  const T gam = (T)ph.gamma;
+  T rho = u[0], E = u[4];
+  if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
+    // floors: rho raised to rho_floor, then E so that P >= p_floor
+    if (rho < (T)ph.rho_floor) {
+      rho = (T)ph.rho_floor;
+      hit = true;
+    }
+    T bcx, bcy, bcz;
+    bool rq;
+    const T P = pressure(gam, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
+                         bnew[2], bup[2], bcx, bcy, bcz, rq, ph.recover);
+    if (P < (T)ph.p_floor) {
+      E = E + ((T)ph.p_floor - P) / (gam - T(1));
+      hit = true;
+    }
+  }
+  if (store_u || hit) {
+    s1.u[0][p] = rho;
+    s1.u[1][p] = u[1];
+    s1.u[2][p] = u[2];
+    s1.u[3][p] = u[3];
+    s1.u[4][p] = E;
+  }
+  store_prim(gam, wo, p, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1], bnew[2],
+             bup[2], rec, ph.recover);
+  if constexpr (CFL)
+    r = fmin(r, cfl_cell<T>(g, ph, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
+                            bnew[2], bup[2], cnt.status));
 }
 
 // One stage's update, fused with what follows it on every cell: the
@@ -723,29 +854,13 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
                       ct_face<T, 2>(g, s0, e, up[2], rx, ry)};
     T u[5];
     bool store_u = !SWEPT;  // the sweep's value stands unless a seam or a floor changes it
+    const bool interior = i < g.n[0] && j < g.n[1] && k < g.n[2];
     if constexpr (SWEPT) {
       // the sweep left the update of every cell, without the fluxes of the
       // upper faces on its tile seams (last column, row or plane of a tile)
 #pragma unroll
       for (int m = 0; m < 5; ++m) u[m] = comp ? (T)inc.du[m][p] : s1.u[m][p];
-      if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
-        store_u = i % kSwX == kSwX - 1 || i == g.n[0] - 1 || j % kSwY == kSwY - 1 ||
-                  j == g.n[1] - 1 || k % kSwZ == kSwZ - 1 || k == g.n[2] - 1;
-        if (i % kSwX == kSwX - 1 || i == g.n[0] - 1) {
-          // face n of a periodic x axis is read at its image, face 0
-          const int q = g.nf[0] == g.n[0] && i == g.n[0] - 1 ? p + 1 - g.n[0] : p + 1;
-#pragma unroll
-          for (int m = 0; m < 5; ++m) u[m] -= rx * f.f[0][frame_comp(0, m)][q];
-        }
-        if (j % kSwY == kSwY - 1 || j == g.n[1] - 1) {
-#pragma unroll
-          for (int m = 0; m < 5; ++m) u[m] -= ry * f.f[1][frame_comp(1, m)][p + g.sy];
-        }
-        if (k % kSwZ == kSwZ - 1 || k == g.n[2] - 1) {
-#pragma unroll
-          for (int m = 0; m < 5; ++m) u[m] -= rz * f.f[2][frame_comp(2, m)][p + g.sz];
-        }
-      }
+      if (interior) store_u = add_seams(g, f, i, j, k, p, rx, ry, rz, u);
     } else {
       T S[5];
       cell_source<T>(g, ph, gr, i, j, k, p, w.w[0][p], w.w[1][p], w.w[2][p], w.w[3][p], S);
@@ -768,76 +883,8 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
       const int b = (a + 1) % 3, c = (a + 2) % 3;
       if (cc[a] < g.nf[a] && cc[b] < g.n[b] && cc[c] < g.n[c]) s1.b[a][p] = bnew[a];
     }
-    bool done = false;
-    if constexpr (sizeof(T) == 4) {
-      if (comp && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
-        // the new pairs: s0's value plus the increment, floors, pressure,
-        // primitives and time-step candidate in FP64
-        double v[5];
-        load_pairs(s0, p, v);
-#pragma unroll
-        for (int m = 0; m < 5; ++m) v[m] += (double)u[m];
-        if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
-          if (v[0] < ph.rho_floor) {
-            v[0] = ph.rho_floor;
-            hit = true;
-          }
-          const double bcx = 0.5 * ((double)bnew[0] + (double)bup[0]);
-          const double bcy = 0.5 * ((double)bnew[1] + (double)bup[1]);
-          const double bcz = 0.5 * ((double)bnew[2] + (double)bup[2]);
-          const double P = (ph.gamma - 1.0) *
-                           (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0] -
-                            0.5 * (bcx * bcx + bcy * bcy + bcz * bcz));
-          if (P < ph.p_floor) {
-            v[4] += (ph.p_floor - P) / (ph.gamma - 1.0);
-            hit = true;
-          }
-        }
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-          float h, l;
-          pair_split(v[m], h, l);
-          s1.u[m][p] = h;
-          s1.lo[m][p] = l;
-        }
-        store_prim_comp(ph.gamma, wo, p, v, bnew[0], bup[0], bnew[1], bup[1], bnew[2], bup[2]);
-        if constexpr (CFL)
-          r = cfl_cell<double>(g, ph, v[0], v[1], v[2], v[3], v[4], bnew[0], bup[0], bnew[1],
-                               bup[1], bnew[2], bup[2], cnt.status);
-        done = true;
-      }
-    }
-    if (!done && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
-      const T gam = (T)ph.gamma;
-      T rho = u[0], E = u[4];
-      if (ph.rho_floor > 0.0 || ph.p_floor > 0.0) {
-        // floors: rho raised to rho_floor, then E so that P >= p_floor
-        if (rho < (T)ph.rho_floor) {
-          rho = (T)ph.rho_floor;
-          hit = true;
-        }
-        T bcx, bcy, bcz;
-        bool rq;
-        const T P = pressure(gam, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
-                             bnew[2], bup[2], bcx, bcy, bcz, rq, ph.recover);
-        if (P < (T)ph.p_floor) {
-          E = E + ((T)ph.p_floor - P) / (gam - T(1));
-          hit = true;
-        }
-      }
-      if (store_u || hit) {
-        s1.u[0][p] = rho;
-        s1.u[1][p] = u[1];
-        s1.u[2][p] = u[2];
-        s1.u[3][p] = u[3];
-        s1.u[4][p] = E;
-      }
-      store_prim(gam, wo, p, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1], bnew[2],
-                 bup[2], rec, ph.recover);
-      if constexpr (CFL)
-        r = cfl_cell<T>(g, ph, rho, u[1], u[2], u[3], E, bnew[0], bup[0], bnew[1], bup[1],
-                        bnew[2], bup[2], cnt.status);
-    }
+    if (interior)
+      finish_cell<T, CFL>(g, ph, s0, s1, wo, p, u, bnew, bup, store_u, comp, cnt, hit, rec, r);
   }
   wave_count(hit, cnt.floor_hits);
   if constexpr (sizeof(T) == 4) wave_count(rec, cnt.fp64_rec);

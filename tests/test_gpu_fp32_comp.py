@@ -10,7 +10,8 @@ pairs in FP64, pressure, primitives, time step and sums from the pairs.
 * Properties: a uniform state stays uniform to the FP32 rounding of the
   increments (interior cells bitwise: every difference of equal fluxes is
   zero; the cells on the sweep's tile seams sum the same FP32 terms in
-  another order, 1e-8 apart); a periodic box keeps its sums; two runs are
+  another order, 1e-8 apart, which can move their cell EMFs by an FP32
+  rounding and so the faces around them); a periodic box keeps its sums; two runs are
   bitwise equal; a state read out (FP64) and read back in continues bit for
   bit; n_fp64_recovery stays 0 (every pressure is FP64)."""
 import json
@@ -90,7 +91,8 @@ def test_comp_uniform_state_stays_uniform():
         # a cell inside a sweep tile (away from its seams) is exact
         assert c5[m][5, 5, 5] == c5[m][6, 6, 6], m
     for a in range(3):
-        assert np.all(b[a] == b[a].flat[0]), a
+        b0 = pb.bx.flat[0] if a == 0 else (pb.by.flat[0] if a == 1 else pb.bz.flat[0])
+        assert np.abs(b[a] - b0).max() <= 1e-6 * abs(b0), a
 
 
 def test_comp_conservation_periodic():
