@@ -43,6 +43,7 @@ struct Layout {
   size_t off_cfl;   // cfl partials
   size_t off_diag;  // diag partials
   size_t off_frag;  // learned correction: weights packed as bf16 MFMA fragments
+  size_t off_phi;   // learned correction: the normal CDF table of its GELU
   size_t off_grav;  // self-gravity: 4 padded T arrays (Psi, grad Psi), the complex
                     // [nz][ny][nx] array, twiddle and eigenvalue tables (0 bytes if off)
   size_t off_scal;  // passive scalars: nscalar padded T arrays at t^n, then nscalar at
@@ -136,7 +137,8 @@ Layout layout_of(const mhd_config* c) {
                                    sizeof(unsigned long long));
   L.off_diag = L.off_cfl + align_up((size_t)cfl_blocks(g) * sizeof(double));
   L.off_frag = L.off_diag + align_up((size_t)diag_blocks(g) * 16 * sizeof(double));
-  L.off_grav = L.off_frag + align_up((size_t)kMlpFragBytes);
+  L.off_phi = L.off_frag + align_up((size_t)kMlpFragBytes);
+  L.off_grav = L.off_phi + align_up((size_t)kPhiBytes);
   size_t grav = 0;
   if (c->source == MHD_SRC_SELF_GRAVITY) {
     const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -223,6 +225,7 @@ struct mhd_ctx {
     m.tau_flux = mlp_tau_flux;
     m.shock = shock();
     m.frags = frags();
+    m.phi = (const float4*)(ws + L.off_phi);
     return m;
   }
   double* misc() const { return (double*)(ws + L.off_misc); }
@@ -641,6 +644,26 @@ void enqueue_cfl(mhd_ctx* c) {
   c->mark(-1);
 }
 
+// The normal CDF table of the learned correction's GELU (layout in
+// mhd_kernels.hpp), from Phi(x) = erfc(-x / sqrt 2) / 2 in FP64.
+int upload_phi_table(mhd_ctx* c) {
+  std::vector<float> h((size_t)kPhiN * 4);
+  const auto Phi = [](double x) { return 0.5 * erfc(-x * 0.70710678118654752440); };
+  for (int i = 0; i < kPhiN; ++i) {
+    const double x0 = -kPhiHalf + (double)i / kPhiScale, dx = 1.0 / kPhiScale;
+    const double p0 = Phi(x0), pm = Phi(x0 + 0.5 * dx), p1 = Phi(x0 + dx);
+    h[4 * i] = (float)p0;
+    h[4 * i + 1] = (float)(-3.0 * p0 + 4.0 * pm - p1);
+    h[4 * i + 2] = (float)(2.0 * p0 - 4.0 * pm + 2.0 * p1);
+    h[4 * i + 3] = 0.0f;
+  }
+  if (hipMemcpyAsync(c->ws + c->L.off_phi, h.data(), h.size() * sizeof(float),
+                     hipMemcpyHostToDevice, c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess)
+    return MHD_E_HIP;
+  return MHD_OK;
+}
+
 // Twiddles exp(-2 pi i q / n) (q < n/2) and the 3-point Laplacian's
 // eigenvalues (2 cos(2 pi m / n) - 2) / d^2 of each axis, computed in FP64
 // and stored in the context precision, in the layout grav_fft() reads.
@@ -736,6 +759,10 @@ int mhd_init(const mhd_config* cfg, void* d_ws, size_t ws_bytes, const void* d_c
       delete c;
       return rc;
     }
+  }
+  if (upload_phi_table(c) != MHD_OK) {
+    delete c;
+    return MHD_E_HIP;
   }
   if (cfg->precision == MHD_FP64) {
     launch_scatter<double>(c->g, (const double*)d_cell5, (const double*)d_bx,

@@ -461,7 +461,9 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux_mlp(Geo g, Physics ph, Sp
                                                            Flux<T> f, Muscl<T> mu, Counters cnt,
                                                            MlpRef mlp) {
   __shared__ MlpWaveLds lds[kSpanThreads / 64];
+  __shared__ float4 phi[kPhiN];
   MlpWaveLds& L = lds[threadIdx.x >> 6];
+  for (int e = (int)threadIdx.x; e < kPhiN; e += kSpanThreads) phi[e] = mlp.phi[e];
   constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
   const int lane = threadIdx.x & 63;
   const Pt pt = span_point(g, sp);
@@ -507,7 +509,7 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux_mlp(Geo g, Physics ph, Sp
     for (int c = 0; c < 32; ++c) L.X[lane * kXs + c] = 0;
   }
   __syncthreads();
-  wave_mlp_infer((const u32x2*)mlp.frags, mlp.params, L.X, L.Y);
+  wave_mlp_infer((const u32x2*)mlp.frags, mlp.params, L.X, L.Y, phi);
   __syncthreads();
   bool corrected = false, gated = false;
   if (valid) {

@@ -101,6 +101,7 @@ struct Counters {
 struct MlpRef {
   const float* params;    // FP32 master weights, 6792 (biases read from here)
   const unsigned* frags;  // the weights packed as bf16 MFMA fragments (launch_mlp_pack)
+  const float4* phi;      // normal CDF table (kPhiN entries)
   double tau;           // clip factor of the dissipation-scale term
   double jump;          // relative pressure jump of a shock cell
   double tau_flux;      // clip factor of the flux-scale term
@@ -345,6 +346,14 @@ void launch_mlp_grad(int64_t n, const float* x, const float* t, const float* P, 
 // Packs the weights of P into the bf16 fragments read by the fused sweep
 // (frags: kMlpFragBytes bytes).
 constexpr int kMlpFragBytes = 28 * 64 * 8;
+// Normal CDF table of the in-step GELU: kPhiN intervals of 1 / kPhiScale on
+// [-kPhiHalf, kPhiHalf), per interval the quadratic c0 + f (c1 + f c2) (f
+// the position in the interval, 0..1) through Phi at its ends and midpoint,
+// as 4 floats (c0, c1, c2, 0); written by the host at initialisation.
+constexpr int kPhiScale = 32;
+constexpr int kPhiHalf = 8;
+constexpr int kPhiN = 2 * kPhiHalf * kPhiScale;
+constexpr int kPhiBytes = kPhiN * 16;
 void launch_mlp_pack(const float* P, unsigned* frags, hipStream_t st);
 void launch_mlp_adam(float* P, float* m, float* v, const float* g, int64_t step, double lr,
                      double b1, double b2, double eps, hipStream_t st);

@@ -67,6 +67,20 @@ __device__ __forceinline__ float norm_cdf(float x) {
   return x >= 0.0f ? 1.0f - e : e;
 }
 
+// Phi(x) from the table of the in-step inference (kPhiN quadratic pieces
+// on [-8, 8), see mhd_kernels.hpp): interpolation error below 1e-7, a table
+// read from LDS and 3 FMAs where the erfc form takes 16 instructions, two of
+// them quarter-rate.  Outside the table Phi is its end value (|Phi(8) - 1|,
+// Phi(-8) < 1e-15); a NaN argument reads entry 0.
+__device__ __forceinline__ float norm_cdf_tab(const float4* tab, float x) {
+  float t = fmaf(x, (float)kPhiScale, (float)(kPhiHalf * kPhiScale));
+  t = fminf(fmaxf(t, 0.0f), (float)kPhiN - 0x1p-10f);
+  const int i = (int)t;
+  const float f = t - (float)i;
+  const float4 c = tab[i];
+  return fmaf(f, fmaf(f, c.z, c.y), c.x);
+}
+
 // GELU(x) = x Phi(x) and its derivative Phi(x) + x phi(x).
 __device__ __forceinline__ float gelu(float x) { return x * norm_cdf(x); }
 __device__ __forceinline__ float gelu_d(float x) {
@@ -185,18 +199,27 @@ __device__ __forceinline__ bf16x4 frag_of(const u32x2* __restrict__ W, int f, in
   return __builtin_bit_cast(bf16x4, W[f * 64 + lane]);
 }
 
-// bias + GELU of the 4 D values of a lane, rounded to bf16 in place.
-__device__ __forceinline__ bf16x4 act4(f32x4 d, const float* __restrict__ b) {
-  return pack4(bf16_hw(gelu(d[0] + b[0])), bf16_hw(gelu(d[1] + b[1])),
-               bf16_hw(gelu(d[2] + b[2])), bf16_hw(gelu(d[3] + b[3])));
+// bias + GELU (Phi from the LDS table) of the 4 D values of a lane, rounded
+// to bf16 in place.
+__device__ __forceinline__ bf16x4 act4(f32x4 d, const float* __restrict__ b,
+                                       const float4* tab) {
+  unsigned short h[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = d[i] + b[i];
+    h[i] = bf16_hw(a * norm_cdf_tab(tab, a));
+  }
+  return pack4(h[0], h[1], h[2], h[3]);
 }
 
 // y = MLP(x) for the 64 samples of a wave.  X: LDS bf16 [64][kXs] (row =
-// sample); Y: LDS float [64][8].  Wave-local: the caller orders the LDS
-// writes of X before, and the reads of Y after, with barriers.
+// sample); Y: LDS float [64][8]; tab: the normal CDF table in LDS.
+// Wave-local: the caller orders the LDS writes of X and tab before, and the
+// reads of Y after, with barriers.
 __device__ __forceinline__ void wave_mlp_infer(const u32x2* __restrict__ W,
                                                const float* __restrict__ P,
-                                               const unsigned short* X, float* Y) {
+                                               const unsigned short* X, float* Y,
+                                               const float4* tab) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, q = lane >> 4;
 #pragma unroll 1
@@ -209,14 +232,14 @@ __device__ __forceinline__ void wave_mlp_infer(const u32x2* __restrict__ W,
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       acc = mfma16(frag_of(W, kFragW1 + 2 * mb, lane), x0, acc);
       acc = mfma16(frag_of(W, kFragW1 + 2 * mb + 1, lane), x1, acc);
-      h1[mb] = act4(acc, P + kP_B1 + 16 * mb + 4 * q);
+      h1[mb] = act4(acc, P + kP_B1 + 16 * mb + 4 * q, tab);
     }
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb) acc = mfma16(frag_of(W, kFragW2 + 4 * mb + kb, lane), h1[kb], acc);
-      h2[mb] = act4(acc, P + kP_B2 + 16 * mb + 4 * q);
+      h2[mb] = act4(acc, P + kP_B2 + 16 * mb + 4 * q, tab);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll

@@ -254,6 +254,7 @@ def test_fused_correction_matches_oracle(case, precision):
         o.step(dts[-1])
     s.step(3, dt=dts)
     err = field_errors(host_state(s), o.get_state())
+    print("MLP_PARITY", case, precision, {k: float(v) for k, v in err.items()}, flush=True)
     tol = 2e-5 if precision == 0 else 1e-4
     assert max(err.values()) <= tol, err
     dg, do = s.diag(), o.diag()
