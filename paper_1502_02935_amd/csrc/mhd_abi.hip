@@ -74,6 +74,7 @@ bool geo_of(const mhd_config* c, Geo* g) {
   g->d[0] = c->dx;
   g->d[1] = c->dy;
   g->d[2] = c->dz;
+  for (int a = 0; a < 3; ++a) g->id[a] = 1.0 / g->d[a];
   g->x0[0] = c->x0;
   g->x0[1] = c->y0;
   g->x0[2] = c->z0;

@@ -207,8 +207,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Time-step candidate of one interior cell from its conserved state: the
 // smallest dx_a / (|v_a| + c_f,a) over the three axes, in FP64 (the
-// start-of-step state of a step that computes its own dt).  A non-finite
-// value, rho <= 0 or P <= 0 sets the sticky status bit and gives +inf.
+// start-of-step state of a step that computes its own dt), formed as the
+// inverse of the largest (|v_a| + c_f,a) / dx_a with one reciprocal of the
+// density (two divisions a cell, where one per quotient took eight).  A
+// non-finite value, rho <= 0 or P <= 0 sets the sticky status bit and
+// gives +inf.
 template <class T>
 __device__ __forceinline__ double cfl_cell(const Geo& g, const Physics& ph, T rho_, T mx_, T my_,
                                            T mz_, T E_, T b0x, T b1x, T b0y, T b1y, T b0z, T b1z,
@@ -217,25 +220,26 @@ __device__ __forceinline__ double cfl_cell(const Geo& g, const Physics& ph, T rh
   const double rho = rho_, mx = mx_, my = my_, mz = mz_, E = E_;
   const double bc[3] = {0.5 * ((double)b0x + (double)b1x), 0.5 * ((double)b0y + (double)b1y),
                         0.5 * ((double)b0z + (double)b1z)};
-  const double ke = 0.5 * (mx * mx + my * my + mz * mz) / rho;
+  const double ir = 1.0 / rho;
+  const double ke = 0.5 * (mx * mx + my * my + mz * mz) * ir;
   const double me = 0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
   const double P = (ph.gamma - 1.0) * (E - ke - me);
-  const double v[3] = {mx / rho, my / rho, mz / rho};
+  const double v[3] = {mx * ir, my * ir, mz * ir};
   const bool ok = rho > 0.0 && P > 0.0 && isfinite(E) && isfinite(mx) && isfinite(my) &&
                   isfinite(mz) && isfinite(bc[0]) && isfinite(bc[1]) && isfinite(bc[2]);
   if (!ok) {
     atomicOr(status, 1u);
     return INFINITY;
   }
-  double r = INFINITY;
+  double s = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double cf = fast_speed<double>(rho, P, bc[a], bc[(a + 1) % 3], bc[(a + 2) % 3],
-                                         ph.gamma);
-    const double t = g.d[a] / (fabs(v[a]) + cf);
-    r = t < r ? t : r;
+    const double cf = fast_speed_id<double>(ir, P, bc[a], bc[(a + 1) % 3], bc[(a + 2) % 3],
+                                            ph.gamma);
+    const double w = (fabs(v[a]) + cf) * g.id[a];
+    s = w > s ? w : s;
   }
-  return r;
+  return 1.0 / s;
 }
 
 // Block minimum of r (kSpanThreads threads) into part[blockIdx.x].

@@ -24,6 +24,7 @@ struct Geo {
   int nf[3];    // interior faces along each axis' own normal (n or n+1)
   int bc[6];
   double d[3];
+  double id[3];  // 1 / d
   double x0[3];
 };
 

@@ -100,14 +100,18 @@ __device__ __forceinline__ void muscl_lr(const Muscl<T>& m, T w0, T w1, T w2, T 
 // Fast magnetosonic speed along n; the discriminant is written as
 // (a^2 - b^2)^2 + 4 a^2 bt^2 so it never goes negative by cancellation.
 template <class T>
-__device__ __forceinline__ T fast_speed(T d, T p, T bn, T bt1, T bt2, T gam) {
+__device__ __forceinline__ T fast_speed_id(T id, T p, T bn, T bt1, T bt2, T gam) {
 #pragma clang fp contract(on)
-  const T id = rcp(d);
   const T a2 = gam * p * id;
   const T bt2s = (bt1 * bt1 + bt2 * bt2) * id;
   const T b2 = bt2s + bn * bn * id;
   const T q = a2 - b2;
   return root(T(0.5) * ((a2 + b2) + root(q * q + T(4) * a2 * bt2s)));
+}
+// The same from the density d itself (id = 1/d).
+template <class T>
+__device__ __forceinline__ T fast_speed(T d, T p, T bn, T bt1, T bt2, T gam) {
+  return fast_speed_id(rcp(d), p, bn, bt1, bt2, gam);
 }
 
 // Conserved vector and physical flux (Eq. 3) of a face state; igm1 =
