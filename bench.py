@@ -11,7 +11,8 @@ Prints one JSON line: FP32-bulk throughput (the headline value), the FP64
 throughput, the FP32-vs-FP64 L1/Linf error per field after 100 steps from the
 same FP32-rounded state with the same time steps (plain and compensated
 FP32), the disc slab's (512 x 512 x 128, 200 steps) FP32 errors and
-throughput, the compensated FP32 throughput, the roofline position of the
+throughput, the production-size disc's (1024 x 1024 x 256) plain and
+compensated FP32 throughput, the compensated FP32 throughput, the roofline position of the
 dominant kernel (HIP events around each launch inside the timed region) and
 of the whole path, and the FP64 CPU oracle timed on a bounded sample of the
 same workload (all host threads, and one).
@@ -50,6 +51,8 @@ def _args():
     ap.add_argument("--no-comp", action="store_true", help="skip the compensated FP32 run")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-disc", action="store_true")
+    ap.add_argument("--no-disc-large", action="store_true",
+                    help="skip the 1024x1024x256 disc throughput")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verbose", action="store_true")
@@ -296,6 +299,27 @@ def disc_leg(steps):
     return out
 
 
+def disc_large_leg(steps=10, warmup=2):
+    """The production-size disc slab 1024 x 1024 x 256 (48 x 48 x 12 kpc,
+    the same cell size): plain and compensated FP32 throughput with their own
+    CFL steps."""
+    import gc
+    from mhd_inputs import problems as P
+    t0 = time.perf_counter()
+    pb = P.disc(1024, 1024, 256, lx=48.0, ly=48.0, lz=12.0).astype("float32")
+    log("  large disc generated in %.1f s" % (time.perf_counter() - t0))
+    out = {"workload": "disc slab 1024x1024x256, 48x48x12 kpc, rotation 200 km/s (Mach 20), "
+                       "toroidal B beta 10, outflow, log-potential source, floors",
+           "cells": pb.ncell, "steps": steps}
+    for prec, key in ((1, "fp32"), (2, "fp32_comp")):
+        el, _, d = timed_run(pb, prec, steps, warmup)
+        out[key] = {"cell_updates_per_s": pb.ncell * steps / el, "ms_per_step": 1e3 * el / steps,
+                    "status": d["status"]}
+        log("  %s %.3f ms/step" % (key, 1e3 * el / steps))
+        gc.collect()
+    return out
+
+
 def main():
     args = _args()
     if args.gpus != 1:
@@ -379,6 +403,9 @@ def main():
     if not args.no_disc:
         log("disc slab 512x512x128: FP32 throughput and %d-step error" % args.disc_steps)
         result["disc"] = disc_leg(args.disc_steps)
+    if not args.no_disc_large:
+        log("disc slab 1024x1024x256: FP32 and compensated FP32 throughput")
+        result["disc_large"] = disc_large_leg()
     torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
