@@ -24,11 +24,17 @@ HIPCC_FLAGS = [
 ]
 
 
+# roctx: the step's host-side ranges (rocprofv3 --marker-trace)
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+LINK_FLAGS = ["-L" + os.path.join(ROCM, "lib"), "-Wl,-rpath," + os.path.join(ROCM, "lib"),
+              "-lrocprofiler-sdk-roctx"]
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+           *[os.path.join(CSRC, s) for s in SOURCES], *LINK_FLAGS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

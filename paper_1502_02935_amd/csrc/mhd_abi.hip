@@ -14,6 +14,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "mhd.h"
 #include "mhd_kernels.hpp"
 
@@ -488,6 +490,9 @@ int scratch_address(int dev, float** out) {
 
 template <class T>
 void enqueue_step(mhd_ctx* c, DtRef dt) {
+  // host-side ranges of the enqueueing (rocprofv3 --marker-trace): the
+  // step, its predictor and its corrector
+  roctxRangePushA("mhd_step");
   const Geo& g = c->g;
   const Counters cnt = c->counters();
   const Cons<T> U = c->cons<T>(0), Us = c->cons<T>(1);
@@ -559,6 +564,7 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   half.factor = 0.5;
   // predictor: first-order fluxes of U^n, half step into U* and its
   // primitives
+  roctxRangePushA("mhd_predictor");
   c->mark(MHD_K_FLUX);
   if (swept) {
     launch_sweep<T>(g, c->ph, W, U, Dn, F, first, c->grav<T>(), half, cnt, store, comp, c->st);
@@ -581,8 +587,10 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   launch_ghosts<T>(g, c->ph, Us, x_lite, c->st);
   c->mark(MHD_K_PRIM);
   launch_prim_shell<T>(g, c->ph, Us, Ws, cnt, x_lite, c->st);
+  roctxRangePop();
   // corrector: MUSCL fluxes of U*, full step from U^n, the primitives of
   // U^{n+1} and the candidates of the next step's dt
+  roctxRangePushA("mhd_corrector");
   if (c->gravity()) {
     c->mark(MHD_K_GRAVITY);
     launch_self_gravity<T>(g, c->ph, Ws.w[0], c->grav_fft<T>(), c->grav<T>(), Pp, at_half,
@@ -628,12 +636,14 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     c->mark(MHD_K_NBODY);
     launch_kick_drift<T>(g, Pp, c->grav<T>(), dt, c->st);
   }
+  roctxRangePop();
   c->mark(MHD_K_OTHER);
   launch_advance_time(c->misc() + M_T, (long long*)(c->misc() + M_STEP), dt, c->st);
   c->mark(-1);
   c->fcur ^= 1;
   c->w_valid = true;
   c->cfl_valid = true;
+  roctxRangePop();
 }
 
 template <class T>

@@ -4,6 +4,7 @@ counter runs) of this library into a short text table.
     python -m paper_1502_02935_amd.profile_summary stats  <kernel_stats.csv>
     python -m paper_1502_02935_amd.profile_summary trace  <kernel_trace.csv>
     python -m paper_1502_02935_amd.profile_summary counter <counter_collection.csv> [copy_bytes]
+    python -m paper_1502_02935_amd.profile_summary markers <marker_api_trace.csv>
 
 The counter mode reports the per-kernel average of every counter per
 dispatch (FETCH_SIZE and WRITE_SIZE are in KiB), and, for a single-counter
@@ -61,11 +62,26 @@ def counter(path, copy_bytes=None):
                     k, avg, copy_bytes / 1024.0, avg / (copy_bytes / 1024.0)))
 
 
+def markers(path):
+    """Count and mean duration of each roctx range (host-side spans)."""
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.OrderedDict()
+    for r in rows:
+        name = r.get("Function") or r.get("Message") or r.get("Name") or "?"
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        agg.setdefault(name[:40], []).append(d)
+    print("%-40s %8s %12s %12s" % ("range", "count", "avg_us", "total_ms"))
+    for k, v in agg.items():
+        print("%-40s %8d %12.1f %12.3f" % (k, len(v), sum(v) / len(v) / 1e3, sum(v) / 1e6))
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
     if mode == "stats":
         stats(path)
     elif mode == "trace":
         trace(path)
+    elif mode == "markers":
+        markers(path)
     else:
         counter(path, float(sys.argv[3]) if len(sys.argv) > 3 else None)

@@ -151,3 +151,18 @@ def test_compensated_precision_configuration():
     assert lib.mhd_workspace_bytes(C.byref(c), C.byref(n)) == L.MHD_OK
     c = _cfg(precision=3).to_c()
     assert lib.mhd_workspace_bytes(C.byref(c), C.byref(n)) == L.MHD_E_ARG
+
+
+def test_library_links_roctx_for_stage_ranges():
+    """The step marks its enqueueing with roctx ranges (mhd_step,
+    mhd_predictor, mhd_corrector) for rocprofv3 --marker-trace: the library
+    needs the roctx runtime and imports its range calls."""
+    import shutil
+    import subprocess
+    if shutil.which("readelf") is None:
+        pytest.skip("readelf not available")
+    dyn = subprocess.run(["readelf", "-d", L.LIB_PATH], capture_output=True, text=True).stdout
+    assert "librocprofiler-sdk-roctx" in dyn
+    syms = subprocess.run(["readelf", "--dyn-syms", "-W", L.LIB_PATH], capture_output=True,
+                          text=True).stdout
+    assert "roctxRangePushA" in syms and "roctxRangePop" in syms

@@ -70,7 +70,9 @@ def test_abi_host_code_under_sanitizers():
         for rc, out in res:
             assert rc == 0, out
         exe = os.path.join(d, "abi_driver")
-        rc, out = _run([HIPCC, *flags, *objs, "-o", exe])
+        rocm_lib = os.path.join(os.path.dirname(os.path.dirname(HIPCC)), "lib")
+        rc, out = _run([HIPCC, *flags, *objs, "-L" + rocm_lib, "-Wl,-rpath," + rocm_lib,
+                        "-lrocprofiler-sdk-roctx", "-o", exe])
         assert rc == 0, out
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="print_stacktrace=1")
         rc, out = _run([exe], env=env)
