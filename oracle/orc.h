@@ -36,7 +36,9 @@
  * leaves open, through the closed forms they give on uniform states; the
  * CFL step through hand-worked values for oblique states on unequal cells;
  * the fixed potentials through the momentum a short step gives gas at rest,
- * against central differences of the potentials as printed).
+ * against central differences of the potentials as printed; the two-stage
+ * integrator through the closed form it takes on a contact wave with
+ * first-order reconstruction).
  * Parity unpinned: the exact value of the HLLD degenerate-state threshold
  * (pinned only to keep the flux bounded near it).
  *
