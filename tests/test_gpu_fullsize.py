@@ -68,3 +68,21 @@ def test_fullsize_fp32_sampled(turbulent):
         assert max(err.values()) <= 1e-4, (lo, err)
         assert l1_rel(got[0][0], ref[0][0]) <= 1e-6, lo
         assert l1_rel(got[0][4], ref[0][4]) <= 1e-6, lo
+
+
+def test_fullsize_fp32_comp_sampled(turbulent):
+    """Compensated FP32 (cell values as FP32 pairs, FP32 stage increments
+    added in FP64) from the FP32-rounded state against the FP64 oracle: the
+    FP32 path's bars, and density and energy at least as close as the plain
+    FP32 path's on every sample (10 % for the spread of rounding errors)."""
+    pb = turbulent.astype("float32")
+    d, out = _run(pb, 2)
+    assert d["status"] == 0 and d["n_fp64_recovery"] == 0
+    _, out32 = _run(pb, 1)
+    for (lo, got, ref), (_, got32, _) in zip(out, out32):
+        err = field_errors(got, ref)
+        print("FULLSIZE_COMP", lo, {k: float(v) for k, v in err.items()}, flush=True)
+        assert max(err.values()) <= 1e-4, (lo, err)
+        for m in (0, 4):
+            lc, l32 = l1_rel(got[0][m], ref[0][m]), l1_rel(got32[0][m], ref[0][m])
+            assert lc <= 1e-6 and lc <= 1.1 * l32 + 1e-15, (lo, m, lc, l32)
