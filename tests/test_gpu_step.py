@@ -284,6 +284,30 @@ def test_bad_state_rejected():
         gpu_sim(pb, state=(c5, pb.bx, pb.by, pb.bz))
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unstable_run_sets_sticky_state(precision):
+    """Steps far above the CFL limit drive the state to rho <= 0, P <= 0 or
+    non-finite values inside the run: the device status word, set by the
+    stage update's checks, makes mhd_dt and mhd_diag return MHD_E_STATE
+    (with the diagnostics filled), and every later step is refused with it
+    (sticky), on the same context."""
+    from paper_1502_02935_amd import MHDError
+    pb = P.random_smooth((16, 16, 16), seed=38)
+    s = gpu_sim(pb, precision=precision)
+    dt = s.dt()
+    s.step(20, dt=30.0 * dt)
+    d = s.diag(check=False)
+    print("UNSTABLE", precision, d["rc"], d["status"], d["rho_min"], d["p_min"], flush=True)
+    assert d["rc"] == -3 and d["status"] != 0
+    with pytest.raises(MHDError) as e:
+        s.dt()
+    assert e.value.code == -3
+    with pytest.raises(MHDError) as e:
+        s.step(1, dt=dt)
+    assert e.value.code == -3
+    s.close()
+
+
 def test_conservation_and_divb_on_device():
     """Periodic box on the GPU alone (any size): FP64 sums of mass, momentum,
     energy and face B are constant; div B stays at rounding level."""
