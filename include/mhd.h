@@ -259,9 +259,10 @@ int mhd_set_full_fluxes(mhd_ctx *ctx, int enable);
    rho, vx, vy, vz, P, Bcx, Bcy, Bcz, and with self-gravity 35 Psi and
    36..38 its gradient at the cells.  *n_out gets the element count.  On a
    box periodic on all sides, steps without full fluxes, passive scalars,
-   learned correction or flux accumulation leave the x ghost layers of the
-   cell arrays unrefreshed (their readers take the interior images): read
-   the interior entries.  Synchronises. */
+   learned correction or flux accumulation leave the ghost layers of the
+   cell arrays, the primitives' ghost shell and the fluxes outside the
+   interior faces unrefreshed (their readers take the interior images):
+   read the interior entries.  Synchronises. */
 int mhd_debug_array(mhd_ctx *ctx, int what, void *d_out, size_t *n_out);
 
 /* Kernel classes timed by the profiling hook. */

@@ -256,9 +256,10 @@ struct mhd_ctx {
   // shell), as the last step left them; cfl_valid: cfl_part() holds that
   // step's update_cfl_blocks() partials of U's time-step candidates.
   bool w_valid = false, cfl_valid = false;
-  // xg_stale: the last ghost fill of U and of prim<T>(0) ran with x_lite (on
-  // a fully periodic box the fused path reads x ghosts at their interior
-  // images, so its stages skip those layers); any other path refills them
+  // xg_stale: the last step ran lite (on a fully periodic box the fused path
+  // reads every ghost at its interior image, so its stages fill only the
+  // faces at index n, and neither the primitives' ghost shell nor the outer
+  // flux layer); any other path refills the ghosts of U and its primitives
   // first.
   bool xg_stale = false;
   // keep every component of every face's flux in memory (mhd_set_full_fluxes)
@@ -526,21 +527,22 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   const bool swept = !c->mlp_params && !c->flux_acc;
   const int store = c->full_fluxes ? 2 : (ns > 0 ? 1 : 0);
   c->fluxes_kept = !swept || c->full_fluxes;
-  // x ghost layers left out of the stages' ghost fills: only where nothing
-  // of this step reads them (fully periodic box, fused path, no passive
-  // scalar, no full fluxes kept for samples)
+  // ghost layers, the primitives' ghost shell and the outer flux layer left
+  // out of the stages: only where nothing of this step reads them (fully
+  // periodic box, fused path, no passive scalar, no full fluxes kept for
+  // samples): every reader takes the interior images
   bool per = true;
   for (int a = 0; a < 6; ++a) per = per && g.bc[a] == 0;
-  const bool x_lite = per && swept && ns == 0 && !c->full_fluxes;
-  if (c->xg_stale && !x_lite) {
+  const bool lite = per && swept && ns == 0 && !c->full_fluxes;
+  if (c->xg_stale && !lite) {
     c->mark(MHD_K_GHOSTS);
     launch_ghosts<T>(g, c->ph, U, false, c->st);
     if (c->w_valid) {
       c->mark(MHD_K_PRIM);
-      launch_prim_shell<T>(g, c->ph, U, W, cnt, false, c->st);
+      launch_prim_shell<T>(g, c->ph, U, W, cnt, c->st);
     }
   }
-  c->xg_stale = x_lite;
+  c->xg_stale = lite;
   // primitives of U^n (and the step's own dt): left by the previous step's
   // corrector, else one pass over U
   c->mark(MHD_K_PRIM);
@@ -568,8 +570,10 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->mark(MHD_K_FLUX);
   if (swept) {
     launch_sweep<T>(g, c->ph, W, U, Dn, F, first, c->grav<T>(), half, cnt, store, comp, c->st);
-    c->mark(MHD_K_FLUX_OUTER);
-    launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, store, c->st);
+    if (!lite) {
+      c->mark(MHD_K_FLUX_OUTER);
+      launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, store, c->st);
+    }
   } else {
     launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
   }
@@ -584,9 +588,11 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     launch_scalar_ghosts<T>(g, Xh, ns, c->st);
   }
   c->mark(MHD_K_GHOSTS);
-  launch_ghosts<T>(g, c->ph, Us, x_lite, c->st);
-  c->mark(MHD_K_PRIM);
-  launch_prim_shell<T>(g, c->ph, Us, Ws, cnt, x_lite, c->st);
+  launch_ghosts<T>(g, c->ph, Us, lite, c->st);
+  if (!lite) {
+    c->mark(MHD_K_PRIM);
+    launch_prim_shell<T>(g, c->ph, Us, Ws, cnt, c->st);
+  }
   roctxRangePop();
   // corrector: MUSCL fluxes of U*, full step from U^n, the primitives of
   // U^{n+1} and the candidates of the next step's dt
@@ -608,8 +614,10 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   } else if (swept) {
     c->mark(MHD_K_FLUX);
     launch_sweep<T>(g, c->ph, Ws, Un, Dc, F, second, c->grav<T>(), dt, cnt, store, comp, c->st);
-    c->mark(MHD_K_FLUX_OUTER);
-    launch_flux_outer<T>(g, c->ph, Ws, Us, F, second, cnt, store, c->st);
+    if (!lite) {
+      c->mark(MHD_K_FLUX_OUTER);
+      launch_flux_outer<T>(g, c->ph, Ws, Us, F, second, cnt, store, c->st);
+    }
   } else {
     c->mark(MHD_K_FLUX);
     launch_flux<T>(g, c->ph, Ws, Us, F, second, cnt, c->st);
@@ -629,9 +637,11 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
     launch_scalar_ghosts<T>(g, Xn, ns, c->st);
   }
   c->mark(MHD_K_GHOSTS);
-  launch_ghosts<T>(g, c->ph, Un, x_lite, c->st);
-  c->mark(MHD_K_PRIM);
-  launch_prim_shell<T>(g, c->ph, Un, W, cnt, x_lite, c->st);
+  launch_ghosts<T>(g, c->ph, Un, lite, c->st);
+  if (!lite) {
+    c->mark(MHD_K_PRIM);
+    launch_prim_shell<T>(g, c->ph, Un, W, cnt, c->st);
+  }
   if (Pp.n > 0) {
     c->mark(MHD_K_NBODY);
     launch_kick_drift<T>(g, Pp, c->grav<T>(), dt, c->st);

@@ -344,15 +344,16 @@ __device__ __forceinline__ int face_copies(const Geo& g, const int c[3], int A) 
   return m;
 }
 
-// Index step from x-index i to the cell d away along x (|d| <= 2), wrapped
-// into [0, n) on a periodic x axis, as an unsigned (two's complement) count.
-__device__ __forceinline__ unsigned x_step(const Geo& g, int i, int d) {
-  int t = i + d;
-  if (g.nf[0] == g.n[0]) {
-    t %= g.n[0];
-    if (t < 0) t += g.n[0];
+// Index step from index c to the cell d away along axis a (|d| <= 2),
+// wrapped into [0, n) on a periodic axis, as an unsigned (two's complement)
+// count of that axis' points.
+__device__ __forceinline__ unsigned axis_step(const Geo& g, int a, int c, int d) {
+  int t = c + d;
+  if (g.nf[a] == g.n[a]) {
+    t %= g.n[a];
+    if (t < 0) t += g.n[a];
   }
-  return (unsigned)(t - i);
+  return (unsigned)(t - c);
 }
 
 struct SweepGrid {
@@ -388,11 +389,14 @@ __global__ void __launch_bounds__(kSwX* kSwY)
   const bool x_up = lx < kSwX - 1 && i + 1 < g.n[0];
   const bool y_up = ly < kSwY - 1 && j + 1 < g.n[1];
   const unsigned es = (unsigned)sizeof(T);
-  // byte offsets of the x-stencil's points from the cell: on a periodic x
-  // axis they wrap onto the interior images, so the x ghost layer of the
-  // primitives is never read
-  const unsigned xm2 = x_step(g, i, -2) * es, xm1 = x_step(g, i, -1) * es,
-                 xp1 = x_step(g, i, 1) * es;
+  // byte offsets of the x- and y-stencils' points from the cell: on a
+  // periodic axis they wrap onto the interior images, so the ghost layers of
+  // the primitives are never read there (the z-stencil's planes likewise)
+  const unsigned xm2 = axis_step(g, 0, i, -2) * es, xm1 = axis_step(g, 0, i, -1) * es,
+                 xp1 = axis_step(g, 0, i, 1) * es;
+  const unsigned sy = (unsigned)g.sy * es, sz = (unsigned)g.sz * es;
+  const unsigned ym2 = axis_step(g, 1, j, -2) * sy, ym1 = axis_step(g, 1, j, -1) * sy,
+                 yp1 = axis_step(g, 1, j, 1) * sy;
   const double dt = (dtr.ptr ? *dtr.ptr : dtr.value) * dtr.factor;
   const T rx = (T)(dt / g.d[0]), ry = (T)(dt / g.d[1]), rz = (T)(dt / g.d[2]), dtT = (T)dt;
   // z-stencil of the z-face at plane k: planes k-2..k+1 in zs.v[.][0..3]
@@ -401,17 +405,17 @@ __global__ void __launch_bounds__(kSwX* kSwY)
 #pragma unroll
   for (int c = 0; c < 7; ++c) zs.v[c][0] = zs.v[c][1] = zs.v[c][2] = zs.v[c][3] = T(0);
   if (act) {
-    const unsigned o = (unsigned)pidx(g, i, j, k0) * es, sz = (unsigned)g.sz * es;
+    const unsigned o = (unsigned)pidx(g, i, j, k0) * es;
     T v[7];
     if constexpr (!FO) {
-      load_point<T, 2>(w, o - 2 * sz, v);
+      load_point<T, 2>(w, o + axis_step(g, 2, k0, -2) * sz, v);
 #pragma unroll
       for (int c = 0; c < 7; ++c) zs.v[c][0] = v[c];
       load_point<T, 2>(w, o, v);
 #pragma unroll
       for (int c = 0; c < 7; ++c) zs.v[c][2] = v[c];
     }
-    load_point<T, 2>(w, o - sz, v);
+    load_point<T, 2>(w, o + axis_step(g, 2, k0, -1) * sz, v);
 #pragma unroll
     for (int c = 0; c < 7; ++c) zs.v[c][1] = v[c];
   }
@@ -428,7 +432,7 @@ __global__ void __launch_bounds__(kSwX* kSwY)
     } else {
       {  // the plane the z-stencil gains: k+1 (first order: k)
         T v[7];
-        load_point<T, 2>(w, FO ? o : o + (unsigned)g.sz * es, v);
+        load_point<T, 2>(w, FO ? o : o + axis_step(g, 2, k, 1) * sz, v);
 #pragma unroll
         for (int c = 0; c < 7; ++c) zs.v[c][FO ? 2 : 3] = v[c];
       }
@@ -452,9 +456,7 @@ __global__ void __launch_bounds__(kSwX* kSwY)
       }
       __builtin_amdgcn_sched_barrier(0);
       {
-        const unsigned sy = (unsigned)g.sy * es;
-        const Stencil<T> sy_st =
-            sweep_stencil<T, 1, FO>(0u - 2u * sy, 0u - sy, sy, w, s0.b[1], o);
+        const Stencil<T> sy_st = sweep_stencil<T, 1, FO>(ym2, ym1, yp1, w, s0.b[1], o);
         const int cy = face_solve<T, RS, FO>(ph, sy_st, mu, Fy);
         const int cc[3] = {i, j, k};
         if (cy) {

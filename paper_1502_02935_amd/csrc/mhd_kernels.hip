@@ -34,53 +34,58 @@ __device__ __forceinline__ int map_axis(int c, int m, int n, int bclo, int bchi,
 
 // Thread t -> ghost point c (the 5 ghost layers of x, then of y, then of z,
 // over the full extent of the other two axes); false past the last one.
-// xl = 1 keeps of the x layers only the points at x-index n, whose only
-// value filled is the x-face n (*bx_only): on a fully periodic box the
-// fused stage path reads every other x ghost at its interior image.
-__device__ __forceinline__ bool ghost_point(const Geo& g, long long t, int xl, int c[3],
-                                           bool& bx_only) {
+// nl = 1 keeps of each axis' layers only the points at index n, whose only
+// value filled is that axis' face n (*face_only = the axis, else -1): on a
+// fully periodic box the fused stage path reads every other ghost at its
+// interior image, and the faces n give the last cells their cell-centred B
+// in the kernels outside the step (diagnostics, time step).
+__device__ __forceinline__ bool ghost_point(const Geo& g, long long t, int nl, int c[3],
+                                           int& face_only) {
   const long long E0 = g.ext[0], E1 = g.ext[1], E2 = g.ext[2];
-  const long long nxl = xl * E1 * E2, ny5 = 5 * E0 * E2, nz5 = 5 * E0 * E1;
+  const long long nx = nl * E1 * E2, ny = nl * E0 * E2, nz = nl * E0 * E1;
   long long r;
-  bx_only = false;
-  if (t < nxl) {
-    const int l = xl == 5 ? (int)(t % 5) : 2;
-    r = t / xl;
+  face_only = -1;
+  if (t < nx) {
+    const int l = nl == 5 ? (int)(t % 5) : 2;
+    r = t / nl;
     c[0] = l < 2 ? l - 2 : g.n[0] + (l - 2);
     c[1] = (int)(r % E1) - NG;
     c[2] = (int)(r / E1) - NG;
-    bx_only = xl != 5;
-  } else if (t < nxl + ny5) {  // x fastest: a wave covers a run of one row
-    r = t - nxl;
+    if (nl != 5) face_only = 0;
+  } else if (t < nx + ny) {  // x fastest: a wave covers a run of one row
+    r = t - nx;
     c[0] = (int)(r % E0) - NG;
     r /= E0;
-    const int l = (int)(r % 5);
+    const int l = nl == 5 ? (int)(r % 5) : 2;
     c[1] = l < 2 ? l - 2 : g.n[1] + (l - 2);
-    c[2] = (int)(r / 5) - NG;
-  } else if (t < nxl + ny5 + nz5) {
-    r = t - nxl - ny5;
+    c[2] = (int)(r / nl) - NG;
+    if (nl != 5) face_only = 1;
+  } else if (t < nx + ny + nz) {
+    r = t - nx - ny;
     c[0] = (int)(r % E0) - NG;
     r /= E0;
     c[1] = (int)(r % E1) - NG;
-    const int l = (int)(r / E1);
+    const int l = nl == 5 ? (int)(r / E1) : 2;
     c[2] = l < 2 ? l - 2 : g.n[2] + (l - 2);
+    if (nl != 5) face_only = 2;
   } else {
     return false;
   }
   return true;
 }
 
-static unsigned ghost_blocks(const Geo& g, int bs, int xl) {
-  const long long tot = (long long)xl * g.ext[1] * g.ext[2] +
-                        5ll * ((long long)g.ext[0] * g.ext[2] + (long long)g.ext[0] * g.ext[1]);
+static unsigned ghost_blocks(const Geo& g, int bs, int nl) {
+  const long long tot =
+      (long long)nl * ((long long)g.ext[1] * g.ext[2] + (long long)g.ext[0] * g.ext[2] +
+                       (long long)g.ext[0] * g.ext[1]);
   return (unsigned)((tot + bs - 1) / bs);
 }
 
 template <class T>
-__global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
+__global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int nl) {
   int c[3];
-  bool bx_only;
-  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, xl, c, bx_only)) return;
+  int face_only;
+  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, nl, c, face_only)) return;
   const int p = pidx(g, c[0], c[1], c[2]);
   // every source value is loaded before the first store (a store through
   // one array pointer would otherwise order the next array's load after it)
@@ -99,7 +104,7 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
     const int q0 = pidx(g, m[0], m[1], m[2]);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      put[q] = !bx_only && (inflow || moved);
+      put[q] = face_only < 0 && (inflow || moved);
       v[q] = !put[q] ? T(0) : (inflow ? (T)ph.inflow_u[q] : s.u[q][q0]);
       vl[q] = 0.f;
       if (comp && put[q]) {
@@ -123,7 +128,7 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
       m[a] = map_axis(c[a], a == f ? g.nf[a] : g.n[a], g.n[a], g.bc[2 * a], g.bc[2 * a + 1],
                       inflow);
     const bool moved = m[0] != c[0] || m[1] != c[1] || m[2] != c[2];
-    put[5 + f] = (!bx_only || f == 0) && (inflow || moved);
+    put[5 + f] = (face_only < 0 || f == face_only) && (inflow || moved);
     v[5 + f] = !put[5 + f] ? T(0)
                            : (inflow ? (T)ph.inflow_b[f] : s.b[f][pidx(g, m[0], m[1], m[2])]);
   }
@@ -139,10 +144,10 @@ __global__ void k_ghosts(Geo g, Physics ph, Cons<T> s, int xl) {
 }
 
 template <class T>
-void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, bool x_lite, hipStream_t st) {
-  const int xl = x_lite ? 1 : 5;
-  hipLaunchKernelGGL(k_ghosts<T>, dim3(ghost_blocks(g, 256, xl)), dim3(256), 0, st, g, ph, s,
-                     xl);
+void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, bool lite, hipStream_t st) {
+  const int nl = lite ? 1 : 5;
+  hipLaunchKernelGGL(k_ghosts<T>, dim3(ghost_blocks(g, 256, nl)), dim3(256), 0, st, g, ph, s,
+                     nl);
 }
 
 // ------------------------------------------------------------------------
@@ -387,19 +392,13 @@ __device__ __forceinline__ bool shell_cell(const Geo& g, int t, int c[3]) {
   return true;
 }
 
-// x_lite: without the x-cells at the ends of the interior rows (the last
-// part of the enumeration).
-static int shell_cells(const Geo& g, bool x_lite) {
+static int shell_cells(const Geo& g) {
   const int w0 = g.n[0] + 2 * NG, w1 = g.n[1] + 2 * NG;
-  return 2 * NG * (w0 * w1 + w0 * g.n[2] + (x_lite ? 0 : g.n[1] * g.n[2]));
+  return 2 * NG * (w0 * w1 + w0 * g.n[2] + g.n[1] * g.n[2]);
 }
 
-// Primitives of the ghost shell (after the ghost fill; the interior cells'
-// come from the stage update).  After a ghost fill with x_lite the x-end
-// cells are left out; so are, in effect, the ghost planes' and rows' cells
-// at x-indices outside [0, n) (computed from x-ghost faces of the interior
-// rows that such a fill does not refresh, and read by nothing that runs
-// after it).
+// Primitives of the ghost shell (after a full ghost fill; the interior
+// cells' come from the stage update).
 template <class T>
 __global__ void __launch_bounds__(256) k_prim_shell(Geo g, Physics ph, Cons<T> s, Prim<T> w,
                                                     Counters cnt) {
@@ -427,8 +426,8 @@ __global__ void __launch_bounds__(256) k_prim_shell(Geo g, Physics ph, Cons<T> s
 
 template <class T>
 void launch_prim_shell(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
-                       bool x_lite, hipStream_t st) {
-  const int n = shell_cells(g, x_lite);
+                       hipStream_t st) {
+  const int n = shell_cells(g);
   hipLaunchKernelGGL(k_prim_shell<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, ph,
                      s, w, c);
 }
@@ -612,19 +611,26 @@ __device__ __forceinline__ T upwind(int8_t sgn, T from_low, T from_high) {
   return sgn > 0 ? from_low : (sgn < 0 ? from_high : T(0.5) * (from_low + from_high));
 }
 
-// Faces and cells at x-index -1 and n of a periodic x axis are read at
-// their images n-1 and 0 (the fused flux sweep does not store that face
-// layer and the stage's ghost fill may leave that cell layer out; where
-// both are filled they hold the same values): i is the point's x-index.
+// Faces and cells at index -1 and n of a periodic axis are read at their
+// images n-1 and 0 (the fused flux sweep and the outer flux layer do not
+// store those faces on a fully periodic box, and the stage's ghost fill
+// leaves those cells out there; where both are filled they hold the same
+// values): c is the point's (i, j, k).
 template <class T, int C>
 __device__ __forceinline__ T corner(const Geo& g, const Prim<T>& w, const Flux<T>& f, int p,
-                                    int i) {
+                                    const int c[3]) {
   constexpr int A = (C + 1) % 3, B = (C + 2) % 3;
   const int sa = stride_of(g, A), sb = stride_of(g, B);
-  const bool xper = g.nf[0] == g.n[0];
-  const int pw = xper && i == g.n[0] ? p - g.n[0] : p;        // the point itself
-  const int xm = xper && i == 0 ? p + g.n[0] - 1 : p - 1;     // one step down x
-  const int pa = A == 0 ? xm : pw - sa, pb = B == 0 ? xm : pw - sb;
+  // the point itself (index n of a periodic axis at its image 0), then one
+  // step down a and one down b from it (index 0 of a periodic axis wraps to
+  // n-1); only the edge's two transverse axes a and b are stepped
+  int pw = p;
+  if (g.nf[A] == g.n[A] && c[A] == g.n[A]) pw -= g.n[A] * sa;
+  if (g.nf[B] == g.n[B] && c[B] == g.n[B]) pw -= g.n[B] * sb;
+  const int ca = c[A] == g.n[A] ? 0 : c[A], cb = c[B] == g.n[B] ? 0 : c[B];
+  const int da = g.nf[A] == g.n[A] && ca == 0 ? (g.n[A] - 1) * sa : -sa;
+  const int db = g.nf[B] == g.n[B] && cb == 0 ? (g.n[B] - 1) * sb : -sb;
+  const int pa = pw + da, pb = pw + db;
   const T* __restrict__ fa = f.f[A][5];  // B_b flux at a-faces (t1 of the a-frame)
   const T* __restrict__ fb = f.f[B][6];  // B_a flux at b-faces (t2 of the b-frame)
   const int8_t* __restrict__ ga = f.sg[A];
@@ -633,8 +639,8 @@ __device__ __forceinline__ T corner(const Geo& g, const Prim<T>& w, const Flux<T
   const T X0 = -fa[pw], X1 = -fa[pb];
   const T Y0 = fb[pw], Y1 = fb[pa];
   // the four cells around the edge: pw, pw - e_a (pa), pw - e_b (pb), and
-  // one step down both (a step down x is xm)
-  const int pab = A == 0 ? xm - sb : (B == 0 ? xm - sa : pw - sa - sb);
+  // one step down both
+  const int pab = pw + da + db;
   const T c00 = cc[pab], c10 = cc[pb], c01 = cc[pa], c11 = cc[pw];
   const T db1 = upwind(ga[pw], c01 - Y1, c11 - Y0);
   const T db3 = upwind(ga[pb], Y1 - c00, Y0 - c10);
@@ -652,9 +658,10 @@ __global__ void __launch_bounds__(kSpanThreads) k_emf(Geo g, Span sp, Prim<T> w,
   const Pt pt = span_point(g, sp);
   if (!pt.valid) return;
   const int p = pt.p;
-  const T ex = corner<T, 0>(g, w, f, p, pt.i);
-  const T ey = corner<T, 1>(g, w, f, p, pt.i);
-  const T ez = corner<T, 2>(g, w, f, p, pt.i);
+  const int c[3] = {pt.i, pt.j, pt.k};
+  const T ex = corner<T, 0>(g, w, f, p, c);
+  const T ey = corner<T, 1>(g, w, f, p, c);
+  const T ez = corner<T, 2>(g, w, f, p, c);
   if (pt.i < g.n[0]) e.e[0][p] = ex;
   if (pt.j < g.n[1]) e.e[1][p] = ey;
   if (pt.k < g.n[2]) e.e[2][p] = ez;
@@ -704,18 +711,20 @@ __device__ __forceinline__ bool add_seams(const Geo& g, const Flux<T>& f, int i,
   const bool sy = j % kSwY == kSwY - 1 || j == g.n[1] - 1;
   const bool sz = k % kSwZ == kSwZ - 1 || k == g.n[2] - 1;
   if (sx) {
-    // face n of a periodic x axis is read at its image, face 0
+    // face n of a periodic axis is read at its image, face 0
     const int q = g.nf[0] == g.n[0] && i == g.n[0] - 1 ? p + 1 - g.n[0] : p + 1;
 #pragma unroll
     for (int m = 0; m < 5; ++m) u[m] -= rx * f.f[0][frame_comp(0, m)][q];
   }
   if (sy) {
+    const int q = g.nf[1] == g.n[1] && j == g.n[1] - 1 ? p + g.sy - g.n[1] * g.sy : p + g.sy;
 #pragma unroll
-    for (int m = 0; m < 5; ++m) u[m] -= ry * f.f[1][frame_comp(1, m)][p + g.sy];
+    for (int m = 0; m < 5; ++m) u[m] -= ry * f.f[1][frame_comp(1, m)][q];
   }
   if (sz) {
+    const int q = g.nf[2] == g.n[2] && k == g.n[2] - 1 ? p + g.sz - g.n[2] * g.sz : p + g.sz;
 #pragma unroll
-    for (int m = 0; m < 5; ++m) u[m] -= rz * f.f[2][frame_comp(2, m)][p + g.sz];
+    for (int m = 0; m < 5; ++m) u[m] -= rz * f.f[2][frame_comp(2, m)][q];
   }
   return sx || sy || sz;
 }
@@ -1362,8 +1371,8 @@ void launch_scalar_update(const Geo& g, const T* rho, Flux<T> f, Scal<T> x0, Sca
 template <class T>
 __global__ void k_scalar_ghosts(Geo g, Scal<T> x, int ns) {
   int c[3];
-  bool bx_only;
-  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, 5, c, bx_only)) return;
+  int face_only;
+  if (!ghost_point(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, 5, c, face_only)) return;
   const int p = pidx(g, c[0], c[1], c[2]);
   bool inflow = false;
   int m[3];
@@ -1471,7 +1480,7 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
                                    Muscl<T>, Counters, MlpRef, hipStream_t);                     \
   template void launch_shock<T>(const Geo&, Prim<T>, uint8_t*, double, hipStream_t);           \
   template void launch_prim_shell<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,     \
-                                     bool, hipStream_t);                                         \
+                                     hipStream_t);                                               \
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Prim<T>, \
                                  Flux<T>, Edge<T>, Grav<T>, DtRef, Counters, double*, bool, Inc, \
                                  hipStream_t);                                                   \

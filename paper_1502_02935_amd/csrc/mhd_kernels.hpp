@@ -193,10 +193,12 @@ struct DtRef {
   double factor;  // 0.5 for the predictor, 1 for the corrector
 };
 
-// x_lite: of the x ghost layers only the x-face at index n (for a fully
-// periodic box whose stage path reads the other x ghosts at their images).
+// lite: of each axis' ghost layers only that axis' face at index n (for a
+// fully periodic box whose stage path reads every other ghost at its
+// interior image; the faces n give the last cells their cell-centred B in
+// the kernels outside the step).
 template <class T>
-void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, bool x_lite, hipStream_t st);
+void launch_ghosts(const Geo& g, const Physics& ph, Cons<T> s, bool lite, hipStream_t st);
 template <class T>
 void launch_prim(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
                  hipStream_t st);
@@ -261,11 +263,10 @@ void launch_flux_outer(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Fl
                        Muscl<T> m, Counters c, int store, hipStream_t st);
 int update_cfl_blocks(const Geo& g);
 // Primitives of the ghost shell [-NG, n+NG-1]^3 minus the interior (after
-// the ghost fill; x_lite: without the x-end cells of the interior rows,
-// after a fill with x_lite).
+// a full ghost fill).
 template <class T>
 void launch_prim_shell(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, Counters c,
-                       bool x_lite, hipStream_t st);
+                       hipStream_t st);
 // Passive scalars of one stage: x1 = x0 - dt div F_X, with F_X the mass flux
 // of f times X = xs / rho (rho: the stage's primitive density) reconstructed
 // by m on the upwind side; interior cells.  x1 may be x0.
