@@ -1080,7 +1080,7 @@ __global__ void __launch_bounds__(BX* BY) k_diag(Geo g, Physics ph, Cons<T> s, d
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         bc[a] = 0.5 * (b0[a] + b1[a]);
-        div += (b1[a] - b0[a]) / g.d[a];
+        div += (b1[a] - b0[a]) * g.id[a];
       }
       const double rho = v[0];
       const double ke = 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / rho;
@@ -1128,6 +1128,28 @@ __global__ void __launch_bounds__(BX* BY) k_diag(Geo g, Physics ph, Cons<T> s, d
   }
 }
 
+// The per-block partials folded in two passes (one block walking every
+// partial is latency bound: ~670 us for the 84k blocks of a 256^3 box):
+// kDiagReduce blocks each fold a contiguous share of the rows, column by
+// column (one wave a column), in a fixed order; then one block folds those.
+constexpr int kDiagReduce = 64;
+
+__global__ void k_diag_reduce(const double* part, int nb, double* out) {
+  const int q = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const bool is_min = q == 9 || q == 10;
+  const bool is_max = q == 8 || q == 11;
+  const int share = (nb + kDiagReduce - 1) / kDiagReduce;
+  const int lo = (int)blockIdx.x * share, hi = min(nb, lo + share);
+  double x = is_min ? INFINITY : 0.0;
+  for (int b = lo + lane; b < hi; b += 64) {
+    const double y = part[(size_t)b * kDiagCols + q];
+    x = is_min ? fmin(x, y) : (is_max ? fmax(x, y) : x + y);
+  }
+  x = is_min ? wave_min(x) : (is_max ? wave_max(x) : wave_sum(x));
+  if (lane == 0) out[(size_t)blockIdx.x * kDiagCols + q] = x;
+}
+
 __global__ void k_diag_final(const double* part, int nb, double dv, double* out) {
   // one wave per column, 16 waves
   const int q = threadIdx.x >> 6;
@@ -1143,17 +1165,23 @@ __global__ void k_diag_final(const double* part, int nb, double dv, double* out)
   if (lane == 0) out[q] = (q < 8) ? x * dv : x;
 }
 
-int diag_blocks(const Geo& g) {
+static int diag_partials(const Geo& g) {
   const dim3 gr = grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1);
   return (int)(gr.x * gr.y * gr.z);
 }
 
+int diag_blocks(const Geo& g) { return diag_partials(g) + kDiagReduce; }
+
 template <class T>
 void launch_diag(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* out,
                  hipStream_t st) {
+  const int nb = diag_partials(g);
+  double* folded = part + (size_t)nb * kDiagCols;
   hipLaunchKernelGGL(k_diag<T>, grid_for(g.n[0] + 1, g.n[1] + 1, g.n[2] + 1), dim3(BX, BY), 0, st,
                      g, ph, s, part);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64 * kDiagCols), 0, st, part, diag_blocks(g),
+  hipLaunchKernelGGL(k_diag_reduce, dim3(kDiagReduce), dim3(64 * kDiagCols), 0, st, part, nb,
+                     folded);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64 * kDiagCols), 0, st, folded, kDiagReduce,
                      g.d[0] * g.d[1] * g.d[2], out);
 }
 

@@ -321,7 +321,8 @@ void launch_particles_out(Parts<T> pp, T* x_out, T* v_out, hipStream_t st);
 void launch_advance_time(double* t, long long* step, DtRef dt, hipStream_t st);
 
 // Diagnostics: writes 14 doubles to out: mass, M(3), E, bsum(3), divb_max,
-// rho_min, p_min, bmax, (2 spare).
+// rho_min, p_min, bmax, (2 spare).  part holds diag_blocks(g) rows of 16
+// doubles (the per-block partials and the first folding pass).
 int diag_blocks(const Geo& g);
 template <class T>
 void launch_diag(const Geo& g, const Physics& ph, Cons<T> s, double* part, double* out,
