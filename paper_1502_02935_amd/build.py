@@ -21,6 +21,10 @@ HIPCC_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall",
+    # matrix-core results in ordinary VGPRs rather than accumulation
+    # registers: the in-step MLP would otherwise copy every result out
+    # before its activation (36 extra instructions per 16 samples)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 

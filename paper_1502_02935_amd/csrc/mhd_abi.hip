@@ -522,8 +522,9 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   DtRef at_n = dt, at_half = dt;  // particle positions of the two potentials
   at_n.factor = 0.0;
   at_half.factor = 0.5;
-  // the fused flux sweep unless the learned correction or the flux
-  // accumulation needs every face's full flux in memory
+  // the fused flux sweep: always in the predictor; in the corrector unless
+  // the learned correction or the flux accumulation needs every face's full
+  // flux in memory
   const bool swept = !c->mlp_params && !c->flux_acc;
   const int store = c->full_fluxes ? 2 : (ns > 0 ? 1 : 0);
   c->fluxes_kept = !swept || c->full_fluxes;
@@ -568,19 +569,15 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   // primitives
   roctxRangePushA("mhd_predictor");
   c->mark(MHD_K_FLUX);
-  if (swept) {
-    launch_sweep<T>(g, c->ph, W, U, Dn, F, first, c->grav<T>(), half, cnt, store, comp, c->st);
-    if (!lite) {
-      c->mark(MHD_K_FLUX_OUTER);
-      launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, store, c->st);
-    }
-  } else {
-    launch_flux<T>(g, c->ph, W, U, F, first, cnt, c->st);
+  launch_sweep<T>(g, c->ph, W, U, Dn, F, first, c->grav<T>(), half, cnt, store, comp, c->st);
+  if (!lite) {
+    c->mark(MHD_K_FLUX_OUTER);
+    launch_flux_outer<T>(g, c->ph, W, U, F, first, cnt, store, c->st);
   }
   c->mark(MHD_K_EMF);
   launch_emf<T>(g, W, F, E, c->st);
   c->mark(MHD_K_UPDATE);
-  launch_update<T>(g, c->ph, U, Us, W, Ws, F, E, c->grav<T>(), half, cnt, nullptr, swept, inc,
+  launch_update<T>(g, c->ph, U, Us, W, Ws, F, E, c->grav<T>(), half, cnt, nullptr, true, inc,
                    c->st);
   if (ns) {
     c->mark(MHD_K_SCALARS);

@@ -458,11 +458,17 @@ struct MlpWaveLds {
   float Y[64 * 8];
 };
 
+// Three phases, so that only the face scales stay live across the network
+// (the reconstruction, the Riemann solve and their states would otherwise
+// hold some 40 registers through it): the features from the four cells,
+// the wave's inference, then the stencil read again (from the caches), the
+// reconstruction, HLLD and the clipped correction.  FP32: at least 4 waves
+// per SIMD (at most 128 VGPRs).
 template <class T, int A>
-__global__ void __launch_bounds__(kSpanThreads) k_flux_mlp(Geo g, Physics ph, Span sp,
-                                                           Prim<T> w, const T* __restrict__ bn,
-                                                           Flux<T> f, Muscl<T> mu, Counters cnt,
-                                                           MlpRef mlp) {
+__global__ void __launch_bounds__(kSpanThreads)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
+    k_flux_mlp(Geo g, Physics ph, Span sp, Prim<T> w, const T* __restrict__ bn, Flux<T> f,
+               Muscl<T> mu, Counters cnt, MlpRef mlp) {
   __shared__ MlpWaveLds lds[kSpanThreads / 64];
   __shared__ float4 phi[kPhiN];
   MlpWaveLds& L = lds[threadIdx.x >> 6];
@@ -473,37 +479,20 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux_mlp(Geo g, Physics ph, Sp
   const bool valid = pt.valid;
   const int s = stride_of(g, A);
   const int p = valid ? pt.p : 0;
-  int code = 0;
-  T F[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-  Face<T> Lf{}, Rf{};
+  // the face-normal frame's 8 variables of cells p - 2s .. p + s
+  const T* __restrict__ src[8] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2],
+                                  w.w[4], w.w[5 + A], w.w[5 + A1], w.w[5 + A2]};
   FaceScale sc{};
   bool means_ok = false;
-  const float gam = (float)ph.gamma;
   if (valid) {
     float w8[32];
-    const T* __restrict__ src[8] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2],
-                                    w.w[4], w.w[5 + A], w.w[5 + A1], w.w[5 + A2]};
-    T st4[8][4];
 #pragma unroll
     for (int v = 0; v < 8; ++v)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        st4[v][c] = src[v][p + (c - 2) * s];
-        w8[8 * c + v] = (float)st4[v][c];
-      }
-    T l[7], r[7];
-    const int map[7] = {0, 1, 2, 3, 4, 6, 7};  // skip the cell-centred normal B
-#pragma unroll
-    for (int v = 0; v < 7; ++v) {
-      const int q = map[v];
-      muscl_lr(mu, st4[q][0], st4[q][1], st4[q][2], st4[q][3], l[v], r[v]);
-    }
-    Lf = Face<T>{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
-    Rf = Face<T>{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
-    code = hlld(Lf, Rf, bn[p], (T)ph.gamma, (T)ph.igm1, F);
+      for (int c = 0; c < 4; ++c) w8[8 * c + v] = (float)src[v][p + (c - 2) * s];
     float x[32];
     means_ok = (w8[8] + w8[16] > 0.f) && (w8[12] + w8[20] > 0.f);
-    sc = face_scale(w8, gam);
+    sc = face_scale(w8, (float)ph.gamma);
     face_features(w8, sc, x);
 #pragma unroll
     for (int c = 0; c < 32; ++c) L.X[lane * kXs + c] = bf16_bits(x[c]);
@@ -514,8 +503,21 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux_mlp(Geo g, Physics ph, Sp
   __syncthreads();
   wave_mlp_infer((const u32x2*)mlp.frags, mlp.params, L.X, L.Y, phi);
   __syncthreads();
+  int code = 0;
   bool corrected = false, gated = false;
   if (valid) {
+    const int map[7] = {0, 1, 2, 3, 4, 6, 7};  // skip the cell-centred normal B
+    T l[7], r[7];
+#pragma unroll
+    for (int v = 0; v < 7; ++v) {
+      const T* __restrict__ a = src[map[v]];
+      muscl_lr(mu, a[p - 2 * s], a[p - s], a[p], a[p + s], l[v], r[v]);
+    }
+    const Face<T> Lf{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
+    const Face<T> Rf{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+    const T b = bn[p];
+    T F[7];
+    code = hlld(Lf, Rf, b, (T)ph.gamma, (T)ph.igm1, F);
     if (mlp.shock[p - s] || mlp.shock[p] || !means_ok) {
       gated = true;
     } else {
@@ -523,7 +525,6 @@ __global__ void __launch_bounds__(kSpanThreads) k_flux_mlp(Geo g, Physics ph, Sp
 #pragma unroll
       for (int o = 0; o < 8; ++o) y[o] = L.Y[lane * 8 + o];
       out_to_flux(sc, y, df);
-      const T b = bn[p];
       const T igm1 = (T)ph.igm1;
       T ul[7], fl[7], ur[7], fr[7];
       cons_flux(Lf, b, igm1, ul, fl);

@@ -76,7 +76,7 @@ __device__ __forceinline__ float norm_cdf_tab(const float4* tab, float x) {
   float t = fmaf(x, (float)kPhiScale, (float)(kPhiHalf * kPhiScale));
   t = fminf(fmaxf(t, 0.0f), (float)kPhiN - 0x1p-10f);
   const int i = (int)t;
-  const float f = t - (float)i;
+  const float f = __builtin_amdgcn_fractf(t);  // t - i exactly (t >= 0)
   const float4 c = tab[i];
   return fmaf(f, fmaf(f, c.z, c.y), c.x);
 }
@@ -199,16 +199,18 @@ __device__ __forceinline__ bf16x4 frag_of(const u32x2* __restrict__ W, int f, in
   return __builtin_bit_cast(bf16x4, W[f * 64 + lane]);
 }
 
-// bias + GELU (Phi from the LDS table) of the 4 D values of a lane, rounded
-// to bf16 in place.
-__device__ __forceinline__ bf16x4 act4(f32x4 d, const float* __restrict__ b,
-                                       const float4* tab) {
+// The biases of a lane's 4 D values (features 4q .. 4q+3 of the block),
+// the accumulator's start: the matrix core adds them with the products.
+__device__ __forceinline__ f32x4 bias4(const float* __restrict__ b) {
+  return f32x4{b[0], b[1], b[2], b[3]};
+}
+
+// GELU (Phi from the LDS table) of the 4 D values of a lane (bias already
+// in), rounded to bf16 in place.
+__device__ __forceinline__ bf16x4 act4(f32x4 d, const float4* tab) {
   unsigned short h[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float a = d[i] + b[i];
-    h[i] = bf16_hw(a * norm_cdf_tab(tab, a));
-  }
+  for (int i = 0; i < 4; ++i) h[i] = bf16_hw(d[i] * norm_cdf_tab(tab, d[i]));
   return pack4(h[0], h[1], h[2], h[3]);
 }
 
@@ -229,17 +231,17 @@ __device__ __forceinline__ void wave_mlp_infer(const u32x2* __restrict__ W,
     bf16x4 h1[4], h2[4];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      f32x4 acc = bias4(P + kP_B1 + 16 * mb + 4 * q);
       acc = mfma16(frag_of(W, kFragW1 + 2 * mb, lane), x0, acc);
       acc = mfma16(frag_of(W, kFragW1 + 2 * mb + 1, lane), x1, acc);
-      h1[mb] = act4(acc, P + kP_B1 + 16 * mb + 4 * q, tab);
+      h1[mb] = act4(acc, tab);
     }
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      f32x4 acc = bias4(P + kP_B2 + 16 * mb + 4 * q);
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb) acc = mfma16(frag_of(W, kFragW2 + 4 * mb + kb, lane), h1[kb], acc);
-      h2[mb] = act4(acc, P + kP_B2 + 16 * mb + 4 * q, tab);
+      h2[mb] = act4(acc, tab);
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
