@@ -530,11 +530,11 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   c->fluxes_kept = !swept || c->full_fluxes;
   // ghost layers, the primitives' ghost shell and the outer flux layer left
   // out of the stages: only where nothing of this step reads them (fully
-  // periodic box, fused path, no passive scalar, no full fluxes kept for
-  // samples): every reader takes the interior images
+  // periodic box, no flux accumulation, no passive scalar, no full fluxes
+  // kept for samples): every reader takes the interior images
   bool per = true;
   for (int a = 0; a < 6; ++a) per = per && g.bc[a] == 0;
-  const bool lite = per && swept && ns == 0 && !c->full_fluxes;
+  const bool lite = per && !c->flux_acc && ns == 0 && !c->full_fluxes;
   if (c->xg_stale && !lite) {
     c->mark(MHD_K_GHOSTS);
     launch_ghosts<T>(g, c->ph, U, false, c->st);
@@ -601,12 +601,12 @@ void enqueue_step(mhd_ctx* c, DtRef dt) {
   }
   if (c->mlp_params) {
     c->mark(MHD_K_SHOCK);
-    launch_shock<T>(g, Ws, c->shock(), c->mlp_jump, c->st);
+    launch_shock<T>(g, Ws, c->shock(), c->mlp_jump, lite, c->st);
     // the caller may change the weights between steps: repack every step
     launch_mlp_pack(c->mlp_params, c->frags(), c->st);
     for (int a = 0; a < 3; ++a) {
       c->mark(MHD_K_FLUX_MLP);
-      launch_flux_mlp<T>(g, c->ph, a, Ws, Us.b[a], F, second, cnt, c->mlp_ref(), c->st);
+      launch_flux_mlp<T>(g, c->ph, a, Ws, Us.b[a], F, second, cnt, c->mlp_ref(), lite, c->st);
     }
   } else if (swept) {
     c->mark(MHD_K_FLUX);
@@ -1086,12 +1086,12 @@ int mhd_mlp_samples(mhd_ctx* c, const void* d_acc, double dt_coarse, int64_t n,
 
   if (n == 0) return MHD_OK;
   if (c->cfg.precision == MHD_FP64) {
-    launch_shock<double>(c->g, c->prim<double>(1), c->shock(), c->mlp_jump, c->st);
+    launch_shock<double>(c->g, c->prim<double>(1), c->shock(), c->mlp_jump, c->xg_stale, c->st);
     launch_mlp_samples<double>(c->g, c->prim<double>(1), c->flux<double>(), c->shock(),
                                (const double*)d_acc, dt_coarse, c->ph.gamma, n, d_faces, d_x, d_t,
                                d_mask, c->st);
   } else {
-    launch_shock<float>(c->g, c->prim<float>(1), c->shock(), c->mlp_jump, c->st);
+    launch_shock<float>(c->g, c->prim<float>(1), c->shock(), c->mlp_jump, c->xg_stale, c->st);
     launch_mlp_samples<float>(c->g, c->prim<float>(1), c->flux<float>(), c->shock(),
                               (const float*)d_acc, dt_coarse, c->ph.gamma, n, d_faces, d_x, d_t,
                               d_mask, c->st);

@@ -326,36 +326,6 @@ __device__ __forceinline__ void store_face(const Flux<T>& f, const T F[7], unsig
   for (int c = 0; c < cn; ++c) gst(f.f[A][c], o, F[c]);
 }
 
-// How many times the outer layer copies the A-face of interior cell c (its
-// periodic images: along a periodic axis a cell at index 0 reappears at n,
-// one at n-1 at -1, where an A-face exists only if that index is not -1 on
-// A itself), plus one for the face itself: the sweep counts a solver event
-// on that face this many times, as solving the outer layer would.
-__device__ __forceinline__ int face_copies(const Geo& g, const int c[3], int A) {
-  int m = 1;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (g.nf[a] != g.n[a]) continue;  // not periodic
-    int k = 1;
-    if (c[a] == 0) ++k;
-    if (c[a] == g.n[a] - 1 && a != A) ++k;
-    m *= k;
-  }
-  return m;
-}
-
-// Index step from index c to the cell d away along axis a (|d| <= 2),
-// wrapped into [0, n) on a periodic axis, as an unsigned (two's complement)
-// count of that axis' points.
-__device__ __forceinline__ unsigned axis_step(const Geo& g, int a, int c, int d) {
-  int t = c + d;
-  if (g.nf[a] == g.n[a]) {
-    t %= g.n[a];
-    if (t < 0) t += g.n[a];
-  }
-  return (unsigned)(t - c);
-}
-
 struct SweepGrid {
   int ntx, nty, nch, nblk;
 };

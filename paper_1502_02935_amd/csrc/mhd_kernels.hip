@@ -458,13 +458,25 @@ struct MlpWaveLds {
   float Y[64 * 8];
 };
 
+// Offset, in points, from the face's upper cell (index c along A) to the
+// cell d away along A: wrapped onto the interior images along a periodic A
+// where the ghost layers are not filled (LITE).
+template <bool LITE, int A>
+__device__ __forceinline__ int face_step(const Geo& g, int c, int d) {
+  return (LITE ? (int)axis_step(g, A, c, d) : d) * stride_of(g, A);
+}
+
 // Three phases, so that only the face scales stay live across the network
 // (the reconstruction, the Riemann solve and their states would otherwise
 // hold some 40 registers through it): the features from the four cells,
 // the wave's inference, then the stencil read again (from the caches), the
 // reconstruction, HLLD and the clipped correction.  FP32: at least 4 waves
-// per SIMD (at most 128 VGPRs).
-template <class T, int A>
+// per SIMD (at most 128 VGPRs).  LITE (a fully periodic step): only the
+// interior faces are solved, their stencils and the shock flag below the
+// face wrapped onto the interior images (the ghost layers are not filled),
+// each event counted as many times as the full range holds copies of the
+// face.
+template <class T, int A, bool LITE>
 __global__ void __launch_bounds__(kSpanThreads)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
     k_flux_mlp(Geo g, Physics ph, Span sp, Prim<T> w, const T* __restrict__ bn, Flux<T> f,
@@ -477,19 +489,22 @@ __global__ void __launch_bounds__(kSpanThreads)
   const int lane = threadIdx.x & 63;
   const Pt pt = span_point(g, sp);
   const bool valid = pt.valid;
-  const int s = stride_of(g, A);
   const int p = valid ? pt.p : 0;
-  // the face-normal frame's 8 variables of cells p - 2s .. p + s
+  const int ci[3] = {pt.i, pt.j, pt.k};
+  // the face-normal frame's 8 variables of cells 2 below .. 1 above the
+  // face's upper cell along A
   const T* __restrict__ src[8] = {w.w[0], w.w[1 + A], w.w[1 + A1], w.w[1 + A2],
                                   w.w[4], w.w[5 + A], w.w[5 + A1], w.w[5 + A2]};
   FaceScale sc{};
   bool means_ok = false;
   if (valid) {
+    const int so[4] = {face_step<LITE, A>(g, ci[A], -2), face_step<LITE, A>(g, ci[A], -1), 0,
+                       face_step<LITE, A>(g, ci[A], 1)};
     float w8[32];
 #pragma unroll
     for (int v = 0; v < 8; ++v)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) w8[8 * c + v] = (float)src[v][p + (c - 2) * s];
+      for (int c = 0; c < 4; ++c) w8[8 * c + v] = (float)src[v][p + so[c]];
     float x[32];
     means_ok = (w8[8] + w8[16] > 0.f) && (w8[12] + w8[20] > 0.f);
     sc = face_scale(w8, (float)ph.gamma);
@@ -506,19 +521,22 @@ __global__ void __launch_bounds__(kSpanThreads)
   int code = 0;
   bool corrected = false, gated = false;
   if (valid) {
+    // formed again: nothing but the face scales lives across the network
+    const int so[4] = {face_step<LITE, A>(g, ci[A], -2), face_step<LITE, A>(g, ci[A], -1), 0,
+                       face_step<LITE, A>(g, ci[A], 1)};
     const int map[7] = {0, 1, 2, 3, 4, 6, 7};  // skip the cell-centred normal B
     T l[7], r[7];
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
       const T* __restrict__ a = src[map[v]];
-      muscl_lr(mu, a[p - 2 * s], a[p - s], a[p], a[p + s], l[v], r[v]);
+      muscl_lr(mu, a[p + so[0]], a[p + so[1]], a[p], a[p + so[3]], l[v], r[v]);
     }
     const Face<T> Lf{l[0], l[1], l[2], l[3], l[4], l[5], l[6]};
     const Face<T> Rf{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
     const T b = bn[p];
     T F[7];
     code = hlld(Lf, Rf, b, (T)ph.gamma, (T)ph.igm1, F);
-    if (mlp.shock[p - s] || mlp.shock[p] || !means_ok) {
+    if (mlp.shock[p + so[1]] || mlp.shock[p] || !means_ok) {
       gated = true;
     } else {
       float y[8], df[7];
@@ -553,48 +571,75 @@ __global__ void __launch_bounds__(kSpanThreads)
   wave_count((code & 2) != 0, cnt.deg);
   wave_count(corrected, cnt.mlp_faces);
   wave_count(gated, cnt.mlp_gated);
+  if constexpr (LITE) {
+    // the copies of the faces on the box's sides (a wave-uniform branch)
+    const int extra = valid ? face_copies(g, ci, A) - 1 : 0;
+    if (__ballot(extra != 0) != 0ull) {
+      wave_add((code & 1) ? extra : 0, cnt.hll);
+      wave_add((code & 2) ? extra : 0, cnt.deg);
+      wave_add(corrected ? extra : 0, cnt.mlp_faces);
+      wave_add(gated ? extra : 0, cnt.mlp_gated);
+    }
+  }
 }
 
 template <class T>
 void launch_flux_mlp(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
-                     Muscl<T> m, Counters c, MlpRef mlp, hipStream_t st) {
-  // faces 0..n along the axis, rows -1..n across it
-  const Span sp = make_span(g, axis == 0 ? 0 : -1, g.n[0], axis == 1 ? 0 : -1, g.n[1],
-                            axis == 2 ? 0 : -1, g.n[2]);
+                     Muscl<T> m, Counters c, MlpRef mlp, bool lite, hipStream_t st) {
+  // faces 0..n along the axis, rows -1..n across it (lite: the interior
+  // faces 0..n-1, rows 0..n-1)
+  const int lo = lite ? 0 : -1, e = lite ? -1 : 0;
+  const Span sp = make_span(g, axis == 0 ? 0 : lo, g.n[0] + e, axis == 1 ? 0 : lo, g.n[1] + e,
+                            axis == 2 ? 0 : lo, g.n[2] + e);
   const dim3 gr = span_grid(sp), bl(kSpanThreads);
-  if (axis == 0)
-    hipLaunchKernelGGL((k_flux_mlp<T, 0>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
-  else if (axis == 1)
-    hipLaunchKernelGGL((k_flux_mlp<T, 1>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
-  else
-    hipLaunchKernelGGL((k_flux_mlp<T, 2>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
+  if (lite) {
+    if (axis == 0)
+      hipLaunchKernelGGL((k_flux_mlp<T, 0, true>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
+    else if (axis == 1)
+      hipLaunchKernelGGL((k_flux_mlp<T, 1, true>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
+    else
+      hipLaunchKernelGGL((k_flux_mlp<T, 2, true>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
+  } else {
+    if (axis == 0)
+      hipLaunchKernelGGL((k_flux_mlp<T, 0, false>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
+    else if (axis == 1)
+      hipLaunchKernelGGL((k_flux_mlp<T, 1, false>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
+    else
+      hipLaunchKernelGGL((k_flux_mlp<T, 2, false>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
+  }
 }
 
-// Shock cells of the stage state on cells [-1, n]^3: some neighbour's
-// pressure differs by more than `jump` times the cell's and the central
-// divergence of v is negative.
+// Shock cells of the stage state on cells [-1, n]^3 (lite: the interior
+// cells, the others read at their images): some neighbour's pressure
+// differs by more than `jump` times the cell's and the central divergence
+// of v is negative.  Neighbours along a periodic axis wrap onto the
+// interior images.
 template <class T>
 __global__ void __launch_bounds__(kSpanThreads) k_shock(Geo g, Span sp, Prim<T> w, uint8_t* shock,
                                                         double jump) {
   const Pt pt = span_point(g, sp);
   if (!pt.valid) return;
   const int p = pt.p;
-  const int st[3] = {1, g.sy, g.sz};
+  const int ci[3] = {pt.i, pt.j, pt.k};
   const T P = w.w[4][p];
   T jmax = T(0), div = T(0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const T jl = fabs(w.w[4][p - st[a]] - P) / P, jh = fabs(w.w[4][p + st[a]] - P) / P;
+    const int s = stride_of(g, a);
+    const int dn = (int)axis_step(g, a, ci[a], -1) * s, up = (int)axis_step(g, a, ci[a], 1) * s;
+    const T jl = fabs(w.w[4][p + dn] - P) / P, jh = fabs(w.w[4][p + up] - P) / P;
     jmax = jl > jmax ? jl : jmax;
     jmax = jh > jmax ? jh : jmax;
-    div += (w.w[1 + a][p + st[a]] - w.w[1 + a][p - st[a]]) / (T(2) * (T)g.d[a]);
+    div += (w.w[1 + a][p + up] - w.w[1 + a][p + dn]) / (T(2) * (T)g.d[a]);
   }
   shock[p] = (jmax > (T)jump && div < T(0)) ? 1 : 0;
 }
 
 template <class T>
-void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, hipStream_t st) {
-  const Span sp = make_span(g, -1, g.n[0], -1, g.n[1], -1, g.n[2]);
+void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, bool lite,
+                  hipStream_t st) {
+  const int lo = lite ? 0 : -1, e = lite ? -1 : 0;
+  const Span sp = make_span(g, lo, g.n[0] + e, lo, g.n[1] + e, lo, g.n[2] + e);
   hipLaunchKernelGGL(k_shock<T>, span_grid(sp), dim3(kSpanThreads), 0, st, g, sp, w, shock, jump);
 }
 
@@ -700,6 +745,14 @@ __device__ __forceinline__ T ct_face(const Geo& g, const Cons<T>& s0, const Edge
                   Eb[q]);
 }
 
+// Index of the upper a-face of the cell at index c (point p) along a: face
+// n of a periodic axis is read at its image, face 0 (a fully periodic step
+// does not store face n; where it does, the two hold the same values).
+__device__ __forceinline__ int upper_face(const Geo& g, int a, int c, int p) {
+  const int s = stride_of(g, a);
+  return g.nf[a] == g.n[a] && c == g.n[a] - 1 ? p + s - g.n[a] * s : p + s;
+}
+
 // The swept stage values of the interior cell (i, j, k) at p: u holds what
 // the sweep left (its update, or the compensated increment); the fluxes of
 // the cell's upper faces on the sweep's tile seams (the last column, row or
@@ -712,18 +765,17 @@ __device__ __forceinline__ bool add_seams(const Geo& g, const Flux<T>& f, int i,
   const bool sy = j % kSwY == kSwY - 1 || j == g.n[1] - 1;
   const bool sz = k % kSwZ == kSwZ - 1 || k == g.n[2] - 1;
   if (sx) {
-    // face n of a periodic axis is read at its image, face 0
-    const int q = g.nf[0] == g.n[0] && i == g.n[0] - 1 ? p + 1 - g.n[0] : p + 1;
+    const int q = upper_face(g, 0, i, p);
 #pragma unroll
     for (int m = 0; m < 5; ++m) u[m] -= rx * f.f[0][frame_comp(0, m)][q];
   }
   if (sy) {
-    const int q = g.nf[1] == g.n[1] && j == g.n[1] - 1 ? p + g.sy - g.n[1] * g.sy : p + g.sy;
+    const int q = upper_face(g, 1, j, p);
 #pragma unroll
     for (int m = 0; m < 5; ++m) u[m] -= ry * f.f[1][frame_comp(1, m)][q];
   }
   if (sz) {
-    const int q = g.nf[2] == g.n[2] && k == g.n[2] - 1 ? p + g.sz - g.n[2] * g.sz : p + g.sz;
+    const int q = upper_face(g, 2, k, p);
 #pragma unroll
     for (int m = 0; m < 5; ++m) u[m] -= rz * f.f[2][frame_comp(2, m)][q];
   }
@@ -881,15 +933,17 @@ __global__ void __launch_bounds__(kSpanThreads) k_update(Geo g, Physics ph, Span
       T S[5];
       cell_source<T>(g, ph, gr, i, j, k, p, w.w[0][p], w.w[1][p], w.w[2][p], w.w[3][p], S);
       const T dtT = (T)dt;
+      const int qx = upper_face(g, 0, i, p), qy = upper_face(g, 1, j, p),
+                qz = upper_face(g, 2, k, p);
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const T* fx = f.f[0][frame_comp(0, m)];
         const T* fy = f.f[1][frame_comp(1, m)];
         const T* fz = f.f[2][frame_comp(2, m)];
         T v = comp ? T(0) : s0.u[m][p];
-        v -= rx * (fx[p + 1] - fx[p]);
-        v -= ry * (fy[p + g.sy] - fy[p]);
-        v -= rz * (fz[p + g.sz] - fz[p]);
+        v -= rx * (fx[qx] - fx[p]);
+        v -= ry * (fy[qy] - fy[p]);
+        v -= rz * (fz[qz] - fz[p]);
         v += dtT * S[m];
         u[m] = v;
       }
@@ -1506,8 +1560,8 @@ void launch_recon_batch(int64_t n, const T* w4, Muscl<T> m, T* wl, T* wr, hipStr
                                    double*, Counters, Parts<T>, hipStream_t);                    \
   template void launch_emf<T>(const Geo&, Prim<T>, Flux<T>, Edge<T>, hipStream_t);              \
   template void launch_flux_mlp<T>(const Geo&, const Physics&, int, Prim<T>, T*, Flux<T>,        \
-                                   Muscl<T>, Counters, MlpRef, hipStream_t);                     \
-  template void launch_shock<T>(const Geo&, Prim<T>, uint8_t*, double, hipStream_t);           \
+                                   Muscl<T>, Counters, MlpRef, bool, hipStream_t);               \
+  template void launch_shock<T>(const Geo&, Prim<T>, uint8_t*, double, bool, hipStream_t);     \
   template void launch_prim_shell<T>(const Geo&, const Physics&, Cons<T>, Prim<T>, Counters,     \
                                      hipStream_t);                                               \
   template void launch_update<T>(const Geo&, const Physics&, Cons<T>, Cons<T>, Prim<T>, Prim<T>, \

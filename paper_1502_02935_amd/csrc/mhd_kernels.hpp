@@ -211,11 +211,16 @@ void launch_prim_cfl(const Geo& g, const Physics& ph, Cons<T> s, Prim<T> w, doub
 template <class T>
 void launch_flux(const Geo& g, const Physics& ph, Prim<T> w, Cons<T> s, Flux<T> f, Muscl<T> m,
                  Counters c, hipStream_t st);
+// Fluxes of the A-faces with the learned correction (shock flags from
+// launch_shock); lite: only the interior faces (a fully periodic step whose
+// readers take the periodic images at the interior faces).
 template <class T>
 void launch_flux_mlp(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn, Flux<T> f,
-                     Muscl<T> m, Counters c, MlpRef mlp, hipStream_t st);
+                     Muscl<T> m, Counters c, MlpRef mlp, bool lite, hipStream_t st);
+// Shock flags of cells [-1, n]^3 (lite: the interior cells).
 template <class T>
-void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, hipStream_t st);
+void launch_shock(const Geo& g, Prim<T> w, uint8_t* shock, double jump, bool lite,
+                  hipStream_t st);
 template <class T>
 void launch_emf(const Geo& g, Prim<T> w, Flux<T> f, Edge<T> e, hipStream_t st);
 // One stage's update of s0 into s1 (s1's faces must be other arrays than

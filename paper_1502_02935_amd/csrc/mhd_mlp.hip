@@ -7,6 +7,7 @@
 
 #include "mhd_kernels.hpp"
 #include "mhd_mlp.hpp"
+#include "mhd_span.hpp"
 
 namespace mhd {
 
@@ -410,13 +411,20 @@ __global__ void k_mlp_samples(Geo g, Prim<T> w, Flux<T> f, const uint8_t* shock,
   const int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
   const int s = a == 0 ? 1 : (a == 1 ? g.sy : g.sz);
   const int p = pidx2(g, i, j, k);
+  // cells 2 below .. 1 above the face's upper cell, wrapped onto the
+  // interior images along a periodic axis (a fully periodic step leaves
+  // the ghost layers unfilled)
+  const int ci = a == 0 ? i : (a == 1 ? j : k);
+  int so[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) so[c] = (int)axis_step(g, a, ci, c - 2) * s;
   float w8[32];
   const T* src[8] = {w.w[0], w.w[1 + a], w.w[1 + t1], w.w[1 + t2],
                      w.w[4], w.w[5 + a], w.w[5 + t1], w.w[5 + t2]};
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int v = 0; v < 8; ++v) w8[8 * c + v] = (float)src[v][p + (c - 2) * s];
+    for (int v = 0; v < 8; ++v) w8[8 * c + v] = (float)src[v][p + so[c]];
   const FaceScale sc = face_scale(w8, gam);
   float xf[32];
   face_features(w8, sc, xf);
@@ -432,7 +440,7 @@ __global__ void k_mlp_samples(Geo g, Prim<T> w, Flux<T> f, const uint8_t* shock,
   flux_to_out(sc, df, y);
 #pragma unroll
   for (int o = 0; o < 8; ++o) t[b * 8 + o] = y[o];
-  mask[b] = (shock[p - s] || shock[p]) ? 1 : 0;
+  mask[b] = (shock[p + so[1]] || shock[p]) ? 1 : 0;
 }
 
 template <class T>

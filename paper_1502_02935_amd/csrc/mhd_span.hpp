@@ -26,6 +26,41 @@ __device__ __forceinline__ int frame_comp(int a, int m) {
   return d == a ? 1 : (d == (a + 1) % 3 ? 2 : 3);
 }
 
+// How many times the outer face layer copies the A-face of interior cell c
+// (its periodic images: along a periodic axis a cell at index 0 reappears at
+// n, one at n-1 at -1, where an A-face exists only if that index is not -1
+// on A itself), plus one for the face itself: a kernel that solves only the
+// interior faces counts an event on that face this many times, as solving
+// the outer layer too would (faces 0..n along A, rows -1..n across).
+__device__ __forceinline__ int face_copies(const Geo& g, const int c[3], int A) {
+  int m = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (g.nf[a] != g.n[a]) continue;  // not periodic
+    int k = 1;
+    if (c[a] == 0) ++k;
+    if (c[a] == g.n[a] - 1 && a != A) ++k;
+    m *= k;
+  }
+  return m;
+}
+
+// Index step from index c (-2 <= c <= n + 1) to the cell d away along axis
+// a (|d| <= 2), wrapped into [0, n) on a periodic axis, as an unsigned (two's
+// complement) count of that axis' points.  From 4 cells up, c + d lies
+// within one period of [0, n): one add or subtract, no division.
+__device__ __forceinline__ unsigned axis_step(const Geo& g, int a, int c, int d) {
+  int t = c + d;
+  const int n = g.n[a];
+  if (g.nf[a] == n) {
+    if (n >= 4)
+      t = t < 0 ? t + n : (t >= n ? t - n : t);
+    else
+      t = (t % n + n) % n;
+  }
+  return (unsigned)(t - c);
+}
+
 static inline dim3 grid_for(int nx, int ny, int nz) {
   return dim3((unsigned)((nx + BX - 1) / BX), (unsigned)((ny + BY - 1) / BY), (unsigned)nz);
 }

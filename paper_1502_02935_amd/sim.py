@@ -224,7 +224,8 @@ class Sim:
 
     def mlp_samples(self, acc: torch.Tensor, dt_coarse: float, faces: torch.Tensor):
         """Features, targets and masks of faces [n][4] (axis, i, j, k) from
-        this context's last step (taken with set_full_fluxes on)."""
+        this context's last step (taken with set_full_fluxes on, or with the
+        learned correction)."""
         n = faces.shape[0]
         assert faces.dtype == torch.int32 and faces.is_contiguous() and faces.shape == (n, 4)
         assert acc.dtype == self.cfg.work_dtype and acc.is_contiguous()

@@ -265,23 +265,82 @@ def test_fused_correction_matches_oracle(case, precision):
         assert do["n_mlp_gated"] > 0
 
 
-def test_mlp_after_plain_steps_refills_ghosts():
-    """Plain fused steps on a fully periodic box leave the x ghost layers
-    unrefreshed; the first step with the learned correction refills them,
-    so it equals the same step after plain steps that kept every ghost
-    layer (all fluxes kept)."""
-    pb = P.random_smooth((9, 7, 70), seed=15)
+def _corner_blast(shape, seed):
+    """A periodic smooth box with an over-pressured ball centred on the box
+    corner, so that its shocks cross every periodic side (gated faces and
+    shock flags on the sides, read at their images)."""
+    pb = P.random_smooth(shape, seed=seed)
+    X, Y, Z = P.cell_centres(pb)
+    r2 = 0.0
+    for c, x0, n, d in ((X, pb.x0, pb.nx, pb.dx), (Y, pb.y0, pb.ny, pb.dy),
+                        (Z, pb.z0, pb.nz, pb.dz)):
+        u = c - x0
+        r2 = r2 + np.minimum(u, n * d - u) ** 2
+    hot = r2 < (0.3 * min(pb.nx * pb.dx, pb.ny * pb.dy, pb.nz * pb.dz)) ** 2
+    pb.cell5[4][hot] += 10.0
+    return pb
+
+
+COUNTERS = ("n_hll_fallback", "n_degenerate", "n_mlp_faces", "n_mlp_gated", "n_floor")
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 70), (10, 3, 2)])
+def test_learned_step_reads_periodic_images(shape):
+    """On a fully periodic box the learned step solves only the interior
+    faces and reads every ghost at its interior image (no ghost layer, shell
+    primitives or outer flux layer), counting each event as often as the
+    full range holds copies of its face.  Bitwise the same state and event
+    counts as the step that fills the ghost layers and solves the full range
+    (full fluxes kept), whether the plain steps before it kept the ghosts or
+    left them stale (then it refills them).  Also with periodic axes of 3
+    and 2 cells, where the stencils wrap more than once."""
+    pb = _corner_blast(shape, seed=15)
     params = _t(_params(14, 0.05).astype(np.float32))
-    out = []
+    out, cnt = [], []
+    # (full fluxes in the plain steps, in the learned step)
+    for full_plain, full_mlp in ((False, False), (True, True), (False, True)):
+        s = gpu_sim(pb, precision=1)
+        s.set_full_fluxes(full_plain)
+        s.step(2)
+        s.set_full_fluxes(full_mlp)
+        s.set_mlp(params, tau=0.5, jump=0.5, tau_flux=0.1)
+        s.step(1)
+        d = s.diag()
+        assert d["n_mlp_faces"] > 0
+        out.append(host_state(s))
+        cnt.append({k: d[k] for k in COUNTERS})
+    if min(shape) > 3:
+        assert cnt[0]["n_mlp_gated"] > 0
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            np.testing.assert_array_equal(a, b)
+    assert cnt[0] == cnt[1] == cnt[2], cnt
+
+
+def test_samples_after_periodic_learned_step():
+    """Training samples after a learned step on a fully periodic box that
+    left the ghost layers stale (features, targets and shock masks read at
+    the interior images) equal those after the same step with every ghost
+    layer filled, on every face of the box's sides and a random set inside."""
+    import torch
+    pb = _corner_blast((16, 12, 10), seed=11)
+    params = _t(_params(14, 0.05).astype(np.float32))
+    rng = np.random.default_rng(12)
+    side = [(a, i, j, k) for a in range(3) for i in (0, 1, 15) for j in (0, 11) for k in (0, 9)]
+    inner = np.stack([rng.integers(0, 3, 200), rng.integers(0, 16, 200),
+                      rng.integers(0, 12, 200), rng.integers(0, 10, 200)], axis=1)
+    faces = _t(np.concatenate([np.array(side), inner]).astype(np.int32), torch.int32)
+    acc = torch.as_tensor(rng.normal(0, 1e-3, (3, 7, 10, 12, 16)), dtype=torch.float32,
+                          device="cuda")
+    res = []
     for full in (False, True):
         s = gpu_sim(pb, precision=1)
         s.set_full_fluxes(full)
-        s.step(2)
         s.set_mlp(params, tau=0.5, jump=0.5, tau_flux=0.1)
-        s.step(1)
-        assert s.diag()["n_mlp_faces"] > 0
-        out.append(host_state(s))
-    for a, b in zip(*out):
+        s.step(1, dt=1e-3)
+        res.append([v.cpu().numpy() for v in s.mlp_samples(acc, 1e-3, faces)])
+    assert (res[0][2] == 1).any()
+    for a, b in zip(*res):
         np.testing.assert_array_equal(a, b)
 
 
