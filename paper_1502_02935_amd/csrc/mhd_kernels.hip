@@ -482,9 +482,14 @@ __global__ void __launch_bounds__(kSpanThreads)
     k_flux_mlp(Geo g, Physics ph, Span sp, Prim<T> w, const T* __restrict__ bn, Flux<T> f,
                Muscl<T> mu, Counters cnt, MlpRef mlp) {
   __shared__ MlpWaveLds lds[kSpanThreads / 64];
-  __shared__ float4 phi[kPhiN];
+  __shared__ PhiLds phi;
   MlpWaveLds& L = lds[threadIdx.x >> 6];
-  for (int e = (int)threadIdx.x; e < kPhiN; e += kSpanThreads) phi[e] = mlp.phi[e];
+  for (int e = (int)threadIdx.x; e < kPhiN; e += kSpanThreads) {
+    const float4 c = mlp.phi[e];
+    phi.c0[e] = c.x;
+    phi.c1[e] = c.y;
+    phi.c2[e] = c.z;
+  }
   constexpr int A1 = (A + 1) % 3, A2 = (A + 2) % 3;
   const int lane = threadIdx.x & 63;
   const Pt pt = span_point(g, sp);

@@ -30,6 +30,8 @@ constexpr int kP_W3 = kP_B2 + 64;
 constexpr int kP_B3 = kP_W3 + 8 * 64;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16v2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float -> bfloat16 bits, round to nearest, ties to even (finite inputs).
@@ -67,18 +69,25 @@ __device__ __forceinline__ float norm_cdf(float x) {
   return x >= 0.0f ? 1.0f - e : e;
 }
 
-// Phi(x) from the table of the in-step inference (kPhiN quadratic pieces
-// on [-8, 8), see mhd_kernels.hpp): interpolation error below 1e-7, a table
-// read from LDS and 3 FMAs where the erfc form takes 16 instructions, two of
-// them quarter-rate.  Outside the table Phi is its end value (|Phi(8) - 1|,
-// Phi(-8) < 1e-15); a NaN argument reads entry 0.
-__device__ __forceinline__ float norm_cdf_tab(const float4* tab, float x) {
+// The normal CDF table of the in-step inference in LDS (kPhiN quadratic
+// pieces on [-8, 8), see mhd_kernels.hpp), one array per coefficient: the
+// 64 lanes of a read fetch scattered pieces, and one 4-byte word a piece
+// per read spreads them over all the banks, where 16-byte pieces fall into
+// eight bank groups and conflict four times as often.
+struct PhiLds {
+  float c0[kPhiN], c1[kPhiN], c2[kPhiN];
+};
+
+// Phi(x) from the table: interpolation error below 1e-7, three LDS reads
+// and 3 FMAs where the erfc form takes 16 instructions, two of them
+// quarter-rate.  Outside the table Phi is its end value (|Phi(8) - 1|,
+// Phi(-8) < 1e-15); a NaN argument reads piece 0.
+__device__ __forceinline__ float norm_cdf_tab(const PhiLds& tab, float x) {
   float t = fmaf(x, (float)kPhiScale, (float)(kPhiHalf * kPhiScale));
   t = fminf(fmaxf(t, 0.0f), (float)kPhiN - 0x1p-10f);
   const int i = (int)t;
   const float f = __builtin_amdgcn_fractf(t);  // t - i exactly (t >= 0)
-  const float4 c = tab[i];
-  return fmaf(f, fmaf(f, c.z, c.y), c.x);
+  return fmaf(f, fmaf(f, tab.c2[i], tab.c1[i]), tab.c0[i]);
 }
 
 // GELU(x) = x Phi(x) and its derivative Phi(x) + x phi(x).
@@ -207,11 +216,14 @@ __device__ __forceinline__ f32x4 bias4(const float* __restrict__ b) {
 
 // GELU (Phi from the LDS table) of the 4 D values of a lane (bias already
 // in), rounded to bf16 in place.
-__device__ __forceinline__ bf16x4 act4(f32x4 d, const float4* tab) {
-  unsigned short h[4];
+__device__ __forceinline__ bf16x4 act4(f32x4 d, const PhiLds& tab) {
+  float g[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) h[i] = bf16_hw(d[i] * norm_cdf_tab(tab, d[i]));
-  return pack4(h[0], h[1], h[2], h[3]);
+  for (int i = 0; i < 4; ++i) g[i] = d[i] * norm_cdf_tab(tab, d[i]);
+  // two values per conversion (v_cvt_pk_bf16_f32, round to nearest even)
+  const u32x2 w = {__builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{g[0], g[1]}, bf16v2)),
+                   __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{g[2], g[3]}, bf16v2))};
+  return __builtin_bit_cast(bf16x4, w);
 }
 
 // y = MLP(x) for the 64 samples of a wave.  X: LDS bf16 [64][kXs] (row =
@@ -221,7 +233,7 @@ __device__ __forceinline__ bf16x4 act4(f32x4 d, const float4* tab) {
 __device__ __forceinline__ void wave_mlp_infer(const u32x2* __restrict__ W,
                                                const float* __restrict__ P,
                                                const unsigned short* X, float* Y,
-                                               const float4* tab) {
+                                               const PhiLds& tab) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, q = lane >> 4;
 #pragma unroll 1
