@@ -96,9 +96,11 @@ __device__ __forceinline__ float gelu_d(float x) {
   return norm_cdf(x) + x * __expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
-// Hardware round-to-nearest-even conversion (v_cvt_pk_bf16_f32).
-__device__ __forceinline__ unsigned short bf16_hw(float x) {
-  return __builtin_bit_cast(unsigned short, (__bf16)x);
+// Two values in one hardware conversion (v_cvt_pk_bf16_f32, round to
+// nearest even: the same as bf16_bits for finite values), a in the low
+// half, b in the high half.
+__device__ __forceinline__ unsigned bf16_pair(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{a, b}, bf16v2));
 }
 
 __device__ __forceinline__ bf16x4 pack4(unsigned short a, unsigned short b, unsigned short c,
@@ -220,9 +222,7 @@ __device__ __forceinline__ bf16x4 act4(f32x4 d, const PhiLds& tab) {
   float g[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) g[i] = d[i] * norm_cdf_tab(tab, d[i]);
-  // two values per conversion (v_cvt_pk_bf16_f32, round to nearest even)
-  const u32x2 w = {__builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{g[0], g[1]}, bf16v2)),
-                   __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{g[2], g[3]}, bf16v2))};
+  const u32x2 w = {bf16_pair(g[0], g[1]), bf16_pair(g[2], g[3])};
   return __builtin_bit_cast(bf16x4, w);
 }
 
