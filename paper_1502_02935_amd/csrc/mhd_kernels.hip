@@ -516,7 +516,8 @@ __global__ void __launch_bounds__(kSpanThreads)
     face_features(w8, sc, x);
 #pragma unroll
     for (int c = 0; c < 32; c += 4)  // 8-byte stores (the row stride is 72 bytes)
-      *(u32x2*)(L.X + lane * kXs + c) = u32x2{bf16_pair(x[c], x[c + 1]), bf16_pair(x[c + 2], x[c + 3])};
+      *(u32x2*)(L.X + lane * kXs + c) =
+          u32x2{bf16_pair(x[c], x[c + 1]), bf16_pair(x[c + 2], x[c + 3])};
   } else {
 #pragma unroll
     for (int c = 0; c < 32; ++c) L.X[lane * kXs + c] = 0;
