@@ -127,3 +127,105 @@ def test_linear_profile_advects_exactly_with_muscl(recon, axis, v):
     np.testing.assert_allclose(got[6:-6], want[6:-6], rtol=1e-13, atol=0)
     m = np.moveaxis(c5[1 + axis], 2 - axis, 2).reshape(-1)
     np.testing.assert_allclose(m[6:-6], v * want[6:-6], rtol=1e-13, atol=1e-15)
+
+
+# ------------------------------------------------------------------------
+# The limited MUSCL corrector inside the step: on a contact the whole step
+# reduces to scalar upwind advection of the density, with the corrector's
+# face value the upwind cell's limited extrapolation of U*.  The expected
+# value is written with the limiter as its closed-form function phi(r) of
+# the slope ratio (tests/test_oracle_units.py pins the oracle's minmod form
+# against the same phi), so this checks how the step composes the pieces:
+# which cells feed a face's left and right states, that the corrector
+# reconstructs U* (not U^n), and that the upwind state carries the flux.
+
+def _phi_paper(r):
+    """Eq. 13 as printed at kappa = 1/3: 2r, then 2r/3 + 1/3, then 1."""
+    return 0.0 if r <= 0 else (2.0 * r if r < 0.25 else (2.0 * r / 3.0 + 1.0 / 3.0
+                                                         if r <= 1.0 else 1.0))
+
+
+def _phi_kappa(r):
+    """Textbook kappa = 1/3 limited with b = 4: 3r, then r/3 + 2/3, then 2."""
+    return 0.0 if r <= 0 else (3.0 * r if r < 0.25 else (r / 3.0 + 2.0 / 3.0
+                                                         if r <= 4.0 else 2.0))
+
+
+def _face_values(w, phi, left):
+    """Face value at face i-1/2 (between cells i-1 and i) of the periodic
+    profile w: the left state w_{i-1} + phi(r) d / 2, or the right state
+    w_i - phi(r) d / 2, d = w_i - w_{i-1}, r the ratio of the state's cell's
+    other difference to d."""
+    n = len(w)
+    f = np.empty(n)
+    for i in range(n):
+        wm2, wm1, w0, wp1 = w[(i - 2) % n], w[(i - 1) % n], w[i], w[(i + 1) % n]
+        d = w0 - wm1
+        if left:
+            f[i] = wm1 + (0.5 * phi((wm1 - wm2) / d) * d if d != 0 else 0.0)
+        else:
+            f[i] = w0 - (0.5 * phi((wp1 - w0) / d) * d if d != 0 else 0.0)
+    return f
+
+
+def _muscl_scheme(rho, nu, phi, from_star=True, upwind=True):
+    up = 1 if nu > 0 else -1
+    a = abs(nu)
+    rs = rho - 0.5 * a * (rho - np.roll(rho, up))
+    # the upwind state carries the flux: the left one for nu > 0
+    f = _face_values(rs if from_star else rho, phi, (nu > 0) == upwind)  # f[i]: face i-1/2
+    return rho - nu * (np.roll(f, -1) - f)
+
+
+def _pulse(n):
+    """A sine with a square pulse on it: smooth stretches, extrema and two
+    jumps, so every branch of the limiter acts somewhere."""
+    x = (np.arange(n) + 0.5) / n
+    return 1.0 + 0.3 * np.sin(2 * np.pi * x) + 0.5 * ((x > 0.3) & (x < 0.55))
+
+
+@pytest.mark.parametrize("recon", ["paper", "kappa"])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("v", [0.7, -0.45])
+def test_contact_step_with_limited_muscl(recon, axis, v):
+    """One full step of a contact carrying a pulse with the limited MUSCL
+    corrector (Eq. 12-14 as printed, and the textbook kappa form) against
+    the scalar scheme above, along each axis and for both signs of v."""
+    from oracle.pyorc import RECON_KAPPA, RECON_PAPER
+    shape = [1, 1, 1]
+    shape[axis] = N
+    pb = P.uniform(tuple(shape), rho=1.0, v=(0.0, 0.0, 0.0), p=P0, b=(0.0, 0.0, 0.0),
+                   d=(0.1, 0.1, 0.1))
+    rho1 = _pulse(N)
+    rho = np.moveaxis(np.broadcast_to(rho1, (1, 1, N)), 2, 2 - axis).reshape(pb.cell5[0].shape)
+    pb.cell5[0] = rho
+    for a in range(3):
+        pb.cell5[1 + a] = rho * (v if a == axis else 0.0)
+    pb.cell5[4] = P0 / (GAMMA - 1.0) + 0.5 * rho * v * v
+    o = oracle_of(pb, recon=RECON_PAPER if recon == "paper" else RECON_KAPPA)
+    nu = 0.3 * np.sign(v)
+    o.step(abs(nu) * 0.1 / abs(v))
+    want = _muscl_scheme(rho1, nu, _phi_paper if recon == "paper" else _phi_kappa)
+    c5 = o.get_state()[0]
+    got = np.moveaxis(c5[0], 2 - axis, 2).reshape(-1)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)
+    m = np.moveaxis(c5[1 + axis], 2 - axis, 2).reshape(-1)
+    np.testing.assert_allclose(m, v * want, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("phi", [_phi_paper, _phi_kappa])
+def test_limited_muscl_closed_form_separates(phi):
+    """The 1e-12 bar is far below what a wrong composition gives: the
+    corrector reconstructing U^n instead of U*, the downwind state, or the
+    other form's limiter each move the result by more than 1e-4; and the
+    pulse makes the limiter act (the result differs from the unlimited
+    kappa = 1/3 scheme)."""
+    rho = _pulse(N)
+    nu = 0.3
+    good = _muscl_scheme(rho, nu, phi)
+    assert np.abs(good - _muscl_scheme(rho, nu, phi, from_star=False)).max() > 1e-4
+    assert np.abs(good - _muscl_scheme(rho, nu, phi, upwind=False)).max() > 1e-4
+    other = _phi_kappa if phi is _phi_paper else _phi_paper
+    assert np.abs(good - _muscl_scheme(rho, nu, other)).max() > 1e-4
+    unlimited = _muscl_scheme(rho, nu, lambda r: 2.0 / 3.0 + r / 3.0)
+    assert np.abs(good - unlimited).max() > 1e-4
