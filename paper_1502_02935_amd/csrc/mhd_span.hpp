@@ -85,6 +85,7 @@ constexpr int kSpanThreads = 256;
 
 struct Span {
   int lo[3], hi[3];
+  int nt;         // threads (points) per block
   int rows;       // rows per slab (the last slab may be shorter)
   int per_plane;  // points of one slab plane: sy * rows
   int bpp;        // blocks per slab plane
@@ -102,14 +103,16 @@ static inline int slab_rows(int nrows) {
   return (nrows + nslab - 1) / nslab;
 }
 
-static inline Span make_span(const Geo& g, int ilo, int ihi, int jlo, int jhi, int klo, int khi) {
+static inline Span make_span(const Geo& g, int ilo, int ihi, int jlo, int jhi, int klo, int khi,
+                             int nt = kSpanThreads) {
   Span s;
   s.lo[0] = ilo, s.hi[0] = ihi, s.lo[1] = jlo, s.hi[1] = jhi, s.lo[2] = klo, s.hi[2] = khi;
+  s.nt = nt;
   const int nrows = jhi - jlo + 1;
   s.rows = slab_rows(nrows);
   const int nslab = (nrows + s.rows - 1) / s.rows;
   s.per_plane = g.sy * s.rows;
-  s.bpp = (s.per_plane + kSpanThreads - 1) / kSpanThreads;
+  s.bpp = (s.per_plane + nt - 1) / nt;
   s.bps = s.bpp * (khi - klo + 1);
   s.nblk = s.bps * nslab;
   s.inv_sy = 1.0f / (float)g.sy;
@@ -141,7 +144,7 @@ __device__ __forceinline__ Pt span_point(const Geo& g, const Span& s) {
   const int slab = div_small(b, s.bps, s.inv_bps);
   const int bs = b - slab * s.bps;
   const int plane = div_small(bs, s.bpp, s.inv_bpp);
-  const int t = (bs - plane * s.bpp) * kSpanThreads + (int)threadIdx.x;
+  const int t = (bs - plane * s.bpp) * s.nt + (int)threadIdx.x;
   const int row = div_small(t, g.sy, s.inv_sy);
   Pt o;
   o.i = t - row * g.sy - NG;
