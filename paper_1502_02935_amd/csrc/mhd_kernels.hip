@@ -476,15 +476,20 @@ __device__ __forceinline__ int face_step(const Geo& g, int c, int d) {
 // face wrapped onto the interior images (the ghost layers are not filled),
 // each event counted as many times as the full range holds copies of the
 // face.
+// Blocks of 256 faces (the learned coarse step's three launches: 166 us
+// each, against 167 with 128, 175 with 512 and 211 with 1024: the barriers
+// around the network wait on every wave of the block).
+constexpr int kMlpThreads = 256;
+
 template <class T, int A, bool LITE>
-__global__ void __launch_bounds__(kSpanThreads)
+__global__ void __launch_bounds__(kMlpThreads)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1, 8)))
     k_flux_mlp(Geo g, Physics ph, Span sp, Prim<T> w, const T* __restrict__ bn, Flux<T> f,
                Muscl<T> mu, Counters cnt, MlpRef mlp) {
-  __shared__ MlpWaveLds lds[kSpanThreads / 64];
+  __shared__ MlpWaveLds lds[kMlpThreads / 64];
   __shared__ PhiLds phi;
   MlpWaveLds& L = lds[threadIdx.x >> 6];
-  for (int e = (int)threadIdx.x; e < kPhiN; e += kSpanThreads) {
+  for (int e = (int)threadIdx.x; e < kPhiN; e += kMlpThreads) {
     const float4 c = mlp.phi[e];
     phi.c0[e] = c.x;
     phi.c1[e] = c.y;
@@ -597,8 +602,8 @@ void launch_flux_mlp(const Geo& g, const Physics& ph, int axis, Prim<T> w, T* bn
   // faces 0..n-1, rows 0..n-1)
   const int lo = lite ? 0 : -1, e = lite ? -1 : 0;
   const Span sp = make_span(g, axis == 0 ? 0 : lo, g.n[0] + e, axis == 1 ? 0 : lo, g.n[1] + e,
-                            axis == 2 ? 0 : lo, g.n[2] + e);
-  const dim3 gr = span_grid(sp), bl(kSpanThreads);
+                            axis == 2 ? 0 : lo, g.n[2] + e, kMlpThreads);
+  const dim3 gr = span_grid(sp), bl(kMlpThreads);
   if (lite) {
     if (axis == 0)
       hipLaunchKernelGGL((k_flux_mlp<T, 0, true>), gr, bl, 0, st, g, ph, sp, w, bn, f, m, c, mlp);
